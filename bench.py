@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark of the label-build + query hot path on one MI355X.
+
+One step = one full label build (pll_build_labels: checks, relabel, every
+batch and round, finalize) of the R-MAT scale-16 graph (65,536 vertices, edge
+factor 16, a,b,c,d = .57,.19,.19,.05, seed 1, degree order, b = 1024) from a
+device-resident CSR, followed by one batched query of 10^6 uniform pairs
+(seed 2).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "ba2000": dict(kind="ba", n=2000, m=4, seed=1, pairs=100_000),
+    "rmat16": dict(kind="rmat", scale=16, seed=1, pairs=1_000_000),
+    "rmat20": dict(kind="rmat", scale=20, seed=1, pairs=10_000_000),
+}
+
+
+def make_graph(w):
+    import synth
+    if w["kind"] == "ba":
+        return synth.ba_graph(w["n"], w["m"], w["seed"])
+    return synth.rmat_graph(w["scale"], 16, 0.57, 0.19, 0.19, seed=w["seed"])
+
+
+def consumed_entries(off, hubs_rank, rank, u, v):
+    """Entries a merge-join must read for each pair: with lim = the smaller
+    of the two lists' last hub ranks (rank(u) and rank(v), since (x,0) closes
+    L(x)), every entry of hub rank <= lim in either list."""
+    import numpy as np
+    n = rank.shape[0]
+    owners = np.repeat(np.arange(n, dtype=np.int64), np.diff(off).astype(np.int64))
+    keys = (owners << 24) | hubs_rank.astype(np.int64)
+    ru, rv = rank[u].astype(np.int64), rank[v].astype(np.int64)
+    lim = np.minimum(ru, rv)
+    cu = np.searchsorted(keys, (u.astype(np.int64) << 24) | lim, side="right") - off[u].astype(np.int64)
+    cv = np.searchsorted(keys, (v.astype(np.int64) << 24) | lim, side="right") - off[v].astype(np.int64)
+    return int(cu.sum() + cv.sum())
+
+
+def cpu_baseline(g, order, total_entries):
+    """The oracle's sequential PLL (Algorithm 1) on the host, one thread, on
+    the whole graph (the R-MAT scale-16 build takes roughly 10-20 s)."""
+    import oracle
+    t0 = time.perf_counter()
+    lab = oracle.pll_labels(g, order)
+    dt = time.perf_counter() - t0
+    assert lab.total == total_entries, "oracle and GPU label counts differ"
+    return {"value": lab.total / dt, "unit": "label entries/s", "cores": 1, "kind": "oracle",
+            "sample": f"full sequential PLL build of the same graph ({g.n} vertices, {lab.total} entries), "
+                      f"1 run, {dt:.2f} s", "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat16", choices=sorted(WORKLOADS))
+    ap.add_argument("--batch-size", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_1906_12018_amd as pll
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    g = make_graph(w)
+    order = synth.degree_order(g)
+    rp, cl = pll.graph_to_device(g, dev)
+    od = torch.from_numpy(order.view(np.int32)).to(dev)
+    u, v = synth.query_pairs(g.n, w["pairs"], seed=2)
+    du = torch.from_numpy(u.view(np.int32)).to(dev)
+    dv = torch.from_numpy(v.view(np.int32)).to(dev)
+    out = torch.empty_like(du)
+    torch.cuda.synchronize()
+
+    flags = pll.FLAG_PROFILE
+    build_ms, query_ms, step_ms, infos = [], [], [], []
+    ref = None
+    for it in range(args.warmup + args.steps):
+        timed = it >= args.warmup
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        idx = pll.build_labels(rp, cl, od, batch_size=args.batch_size, flags=flags)
+        t1 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        idx.query(du, dv, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        info = idx.info()
+        if ref is None:
+            ref = (info["total_entries"], out.clone())
+        else:
+            assert info["total_entries"] == ref[0] and torch.equal(out, ref[1]), "steps disagree"
+        if timed:
+            build_ms.append((t1 - t0) * 1e3)
+            query_ms.append(e0.elapsed_time(e1))
+            step_ms.append((t2 - t0) * 1e3)
+            infos.append(info)
+        if it < args.warmup + args.steps - 1:
+            idx.free()
+
+    info = infos[-1]
+    total = info["total_entries"]
+    K = args.steps
+    sum_build_s = sum(build_ms) / 1e3
+    value = total * K / sum_build_s
+    qps = w["pairs"] / (np.median(query_ms) / 1e3)
+
+    # roofline, dominant kernel: the pruning check (k_check), bytes per the
+    # kernel's traffic model, time from HIP events on the build stream
+    check_ms = np.mean([i["phase_ms"]["check"] for i in infos])
+    check_launches = info["phase_launches"]["check"]
+    check_bytes = (4 * info["check_entries_read"] + 64 * info["check_table_reads"]
+                   + 4 * info["accepted"])
+    check_gbs = check_bytes / (check_ms / 1e3) / 1e9
+    ex = idx.export()
+    torch.cuda.synchronize()
+    off = ex.offsets.cpu().numpy().view(np.uint64).astype(np.int64)
+    hubs = ex.hubs.cpu().numpy().view(np.uint32)
+    rank = np.empty(g.n, dtype=np.int64)
+    rank[order.astype(np.int64)] = np.arange(g.n)
+    hub_rank = rank[hubs.astype(np.int64)]
+    cons = consumed_entries(off, hub_rank, rank, u.astype(np.int64), v.astype(np.int64))
+    q_bytes = w["pairs"] * (8 + 32 + 4) + 4 * cons
+    q_gbs = q_bytes / (np.median(query_ms) / 1e3) / 1e9
+
+    res = {
+        "metric": "index build s + label entries/s; batched queries/s with p50/p99 latency",
+        "value": value,
+        "unit": "label entries/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": float(np.mean(step_ms)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload} label build + {w['pairs']} query pairs", "n": g.n,
+                   "undirected_edges": g.num_edges, "batch_size": args.batch_size, "query_pairs": w["pairs"],
+                   "order": "degree descending, ties by id"},
+        "build_s": float(np.median(build_ms) / 1e3),
+        "label_entries": total,
+        "label_bytes": info["label_bytes"],
+        "queries_per_s": qps,
+        "query_batch_ms_p50": float(np.percentile(query_ms, 50)),
+        "query_batch_ms_p99": float(np.percentile(query_ms, 99)),
+        "build_phase_ms": {k: round(x, 3) for k, x in info["phase_ms"].items()},
+        "rounds": info["rounds"], "batches": info["batches"], "candidates": info["candidates"],
+        "roofline": {"kernel": "k_check", "bound": "hbm", "achieved": check_gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": check_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "launches_per_step": check_launches,
+                     "avg_launch_us": check_ms * 1e3 / max(check_launches, 1),
+                     "bytes_per_step": check_bytes},
+        "roofline_query": {"kernel": "k_query", "bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": q_gbs / HBM_PEAK_GBS, "traffic": None,
+                           "bytes_per_launch": q_bytes, "entries_consumed": cons},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(g, order, total)
+    idx.free()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

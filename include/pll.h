@@ -1,0 +1,179 @@
+/*
+ * pll.h -- C ABI of the MI355X (gfx950) pruned landmark labeling library.
+ *
+ * The library builds the canonical 2-hop distance labeling of an undirected,
+ * unweighted graph for a given vertex order, and answers exact distance
+ * queries from it.  Paper: Jin et al., "Pruned Landmark Labeling Meets Vertex
+ * Centric Computation" (arXiv 1906.12018).
+ *
+ *   Problem statement (Section 2.1, Definitions 1-2): given G = (V, E) and a
+ *   total order pi on V, every vertex v gets a label L(v) of (hub, distance)
+ *   pairs; u is a hub of v iff u has the highest rank among all vertices on
+ *   shortest u-v paths (the canonical hierarchical hub labeling, which PLL,
+ *   Algorithm 1, computes).
+ *   Construction (Section 4.2, Algorithm 4, BVC-PLL): vertices are labeled in
+ *   rank-ordered batches of b vertices; inside a batch, vertex-centric rounds
+ *   push newly accepted entries to neighbours, filter duplicates with the
+ *   per-vertex candidate bit-vector C(v), and keep a candidate (u, d) at v
+ *   only if d < min over common hubs h of d(u,h) + d(h,v).
+ *   Query (Section 2.1): Dis(u,v) = min over h in L(u) and L(v) of
+ *   d(u,h) + d(h,v), computed by merging the two hub-sorted lists.
+ *
+ * Conventions
+ *   - Vertex ids are uint32 in [0, n).  n < 2^24 (16,777,216).
+ *   - order[k] is the vertex of rank k; rank 0 is the highest.  (The paper's
+ *     pi is 1-based with 1 the highest.)
+ *   - Every label list holds its hubs in ascending rank and includes (v, 0).
+ *   - Distances are uint8; a distance of 255 or more fails with PLL_EDIST.
+ *   - Unreachable pairs have no common hub; the query returns PLL_DIST_INF.
+ *
+ * Memory and ownership
+ *   - Every pointer argument named d_* is a device pointer (HIP global memory
+ *     on the current device); every other pointer is a host pointer.
+ *   - The caller owns every input and output buffer; the library copies what
+ *     it keeps.  A pll_index owns its device label store until
+ *     pll_index_free.  No other allocation crosses the ABI.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls that
+ *     return results in host memory synchronise with it; pll_query and
+ *     pll_export_labels only enqueue work on it.
+ *
+ * Errors
+ *   - Every call returns a status code (PLL_OK on success).  Nothing throws
+ *     across the ABI.  On error, *out stays NULL and no existing index is
+ *     modified.  pll_status_string gives a static description.
+ */
+#ifndef PLL_H_
+#define PLL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PLL_OK 0
+#define PLL_EINVAL 1  /* bad argument: malformed CSR, order not a permutation, NULL pointer */
+#define PLL_ENOMEM 2  /* device or host allocation failed */
+#define PLL_ENOSPC 3  /* the label arena given in pll_build_opts is too small; retry larger */
+#define PLL_EDIST 4   /* some shortest distance is 255 or more (uint8 labels) */
+#define PLL_EDEVICE 5 /* a HIP runtime error */
+
+#define PLL_DIST_INF 0xFFFFFFFFu
+
+/* Build flags (pll_build_opts.flags). */
+#define PLL_FLAG_VALIDATE 0x1u /* check the CSR (sorted, symmetric, no loops or duplicates) and the order on the device */
+#define PLL_FLAG_RECHECK 0x2u  /* run the batch-end label-cleaning recheck (Section 5.1) and count what it removes */
+#define PLL_FLAG_RELAXED 0x4u  /* testing: the round check ignores hubs of the current batch; needs PLL_FLAG_RECHECK
+                                  to restore the canonical labels */
+#define PLL_FLAG_PROFILE 0x8u  /* time each build phase with HIP events on `stream` (pll_index_info.phase_ms) */
+
+/* Build phases timed under PLL_FLAG_PROFILE (indexes into pll_index_info.phase_ms / phase_launches). */
+#define PLL_PHASE_PREP 0     /* input checks and relabelling to rank space */
+#define PLL_PHASE_INIT 1     /* batch init: self entries, distance table fill */
+#define PLL_PHASE_PUSH 2     /* scatter: candidate bit-vectors to neighbours */
+#define PLL_PHASE_CHECK 3    /* gather: pruning checks, appends, next frontier */
+#define PLL_PHASE_END 4      /* batch end: clear C, recheck, sort, clear the table */
+#define PLL_PHASE_FINAL 5    /* finalize: label CSR by vertex id */
+#define PLL_NUM_PHASES 6
+
+typedef struct pll_index pll_index;
+
+typedef struct {
+    uint32_t batch_size;    /* b, 1..1024; 0 selects 1024 (Section 6, batch size of BVC-PLL) */
+    uint32_t flags;         /* PLL_FLAG_* */
+    uint64_t arena_entries; /* label arena capacity in 4-byte entries during the build; 0 = automatic
+                               (grows and retries on its own; a nonzero value fails with PLL_ENOSPC) */
+    uint32_t query_lanes;   /* lanes cooperating on one query pair: 0 = automatic, else 1, 4, 8, 16, 32 or 64 */
+    uint32_t reserved[7];   /* must be zero */
+} pll_build_opts;
+
+typedef struct {
+    uint32_t n;               /* vertices */
+    uint32_t batch_size;      /* b used by the build */
+    uint64_t total_entries;   /* sum over v of |L(v)|, self entries included */
+    uint64_t label_bytes;     /* device bytes of the final label store (entries + offsets) */
+    uint32_t max_dist;        /* largest distance stored */
+    uint32_t max_label;       /* largest |L(v)| */
+    uint64_t batches;         /* batches run */
+    uint64_t rounds;          /* vertex-centric rounds run, summed over batches */
+    uint64_t candidates;      /* distance checks made (candidates surviving the C(v) filter) */
+    uint64_t accepted;        /* entries accepted by the round checks */
+    uint64_t edges_scanned;   /* CSR entries read by the push phase */
+    uint64_t recheck_removed; /* entries dropped by the label-cleaning recheck (0 for exact rounds) */
+    uint64_t arena_entries;   /* arena capacity the successful build used */
+    uint32_t build_attempts;  /* 1 + automatic arena retries */
+    uint32_t reserved0;
+    double build_ms;          /* host wall time of pll_build_labels */
+    uint64_t check_entries_read;  /* label entries the pruning checks read */
+    uint64_t check_table_reads;   /* 64-byte distance-table segments the pruning checks read */
+    double phase_ms[PLL_NUM_PHASES];         /* device time per phase (PLL_FLAG_PROFILE, else 0) */
+    uint64_t phase_launches[PLL_NUM_PHASES]; /* kernel launches per phase (PLL_FLAG_PROFILE, else 0) */
+} pll_index_info;
+
+/* One graph of a batched build (all pointers are device pointers). */
+typedef struct {
+    uint32_t n;
+    uint64_t nnz;
+    const uint64_t* d_row_ptr;
+    const uint32_t* d_col;
+    const uint32_t* d_order;
+} pll_graph_desc;
+
+/*
+ * Build the canonical labeling of one graph (Algorithm 4).
+ *   n, nnz      vertices and CSR entries (nnz = 2 |E|)
+ *   d_row_ptr   uint64[n+1], d_row_ptr[0] = 0, d_row_ptr[n] = nnz
+ *   d_col       uint32[nnz]; row v lists the neighbours of v in ascending id,
+ *               with no self-loop and no duplicate; the graph is symmetric
+ *   d_order     uint32[n], a permutation; d_order[k] = vertex of rank k
+ *   opts        NULL for defaults
+ *   out         receives the new index (host pointer to the handle)
+ * The call returns once the labels are resident.  Row pointers, column
+ * bounds and the order permutation are always checked (PLL_EINVAL);
+ * sortedness, symmetry, self-loops and duplicates only under
+ * PLL_FLAG_VALIDATE -- without it such a graph yields unspecified labels.
+ */
+int pll_build_labels(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
+                     const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out);
+
+/*
+ * Exact distances for `count` pairs (Section 2.1, the 2-hop query).
+ *   d_u, d_v    uint32[count] vertex ids; an id >= n is undefined behaviour
+ *   d_out       uint32[count]; PLL_DIST_INF when v is unreachable from u
+ * Asynchronous on `stream`; the index must outlive the enqueued work.
+ */
+int pll_query(const pll_index* idx, uint64_t count, const uint32_t* d_u, const uint32_t* d_v, uint32_t* d_out,
+              hipStream_t stream);
+
+/* Summary and counters of an index (host struct, filled synchronously). */
+int pll_index_info_get(const pll_index* idx, pll_index_info* out);
+
+/*
+ * Copy the labels out in CSR form, indexed by vertex id.
+ *   d_offsets   uint64[n+1]
+ *   d_hubs      uint32[total_entries]: hub vertex ids, in ascending hub rank
+ *   d_dists     uint8[total_entries]
+ * Asynchronous on `stream`.
+ */
+int pll_export_labels(const pll_index* idx, uint64_t* d_offsets, uint32_t* d_hubs, uint8_t* d_dists,
+                      hipStream_t stream);
+
+/*
+ * Build `count` independent graphs in one persistent-kernel launch (the
+ * same labels as pll_build_labels on each graph).  outs[i] receives the
+ * index of graphs[i].  On error no index is returned.
+ */
+int pll_build_labels_batched(uint32_t count, const pll_graph_desc* graphs, const pll_build_opts* opts,
+                             hipStream_t stream, pll_index** outs);
+
+void pll_index_free(pll_index* idx);
+
+const char* pll_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PLL_H_ */

@@ -1,0 +1,107 @@
+// C ABI entry points of libpll (declared in include/pll.h).
+#include <new>
+
+#include "pll_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ void k_export(uint64_t total, const uint32_t* __restrict__ ent, const uint32_t* __restrict__ order,
+                         uint32_t* __restrict__ hubs, uint8_t* __restrict__ dists) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t e = ent[i];
+        hubs[i] = order[e >> 8];
+        dists[i] = (uint8_t)(e & 255u);
+    }
+}
+
+void free_index(pll_index* idx) {
+    if (!idx) return;
+    int cur = -1;
+    bool switched = false;
+    if (hipGetDevice(&cur) == hipSuccess && cur != idx->device) switched = hipSetDevice(idx->device) == hipSuccess;
+    (void)hipFree(idx->d_off);
+    (void)hipFree(idx->d_ent);
+    (void)hipFree(idx->d_order);
+    if (switched) (void)hipSetDevice(cur);
+    delete idx;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pll_build_labels(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
+                     const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out) {
+    try {
+        return pll_build_one(n, nnz, d_row_ptr, d_col, d_order, opts, stream, out);
+    } catch (...) {
+        if (out) *out = nullptr;
+        return PLL_ENOMEM;
+    }
+}
+
+int pll_query(const pll_index* idx, uint64_t count, const uint32_t* d_u, const uint32_t* d_v, uint32_t* d_out,
+              hipStream_t stream) {
+    if (!idx) return PLL_EINVAL;
+    if (count && (!d_u || !d_v || !d_out)) return PLL_EINVAL;
+    return pll_query_launch(idx, count, d_u, d_v, d_out, stream);
+}
+
+int pll_index_info_get(const pll_index* idx, pll_index_info* out) {
+    if (!idx || !out) return PLL_EINVAL;
+    *out = idx->info;
+    return PLL_OK;
+}
+
+int pll_export_labels(const pll_index* idx, uint64_t* d_offsets, uint32_t* d_hubs, uint8_t* d_dists,
+                      hipStream_t stream) {
+    if (!idx || !d_offsets) return PLL_EINVAL;
+    if (idx->total && (!d_hubs || !d_dists)) return PLL_EINVAL;
+    if (hipMemcpyAsync(d_offsets, idx->d_off, sizeof(uint64_t) * ((size_t)idx->n + 1), hipMemcpyDeviceToDevice,
+                       stream) != hipSuccess)
+        return PLL_EDEVICE;
+    if (idx->total) {
+        uint64_t blocks = (idx->total + kBlock - 1) / kBlock;
+        if (blocks > 65536) blocks = 65536;
+        k_export<<<(uint32_t)blocks, kBlock, 0, stream>>>(idx->total, idx->d_ent, idx->d_order, d_hubs, d_dists);
+        if (hipGetLastError() != hipSuccess) return PLL_EDEVICE;
+    }
+    return PLL_OK;
+}
+
+int pll_build_labels_batched(uint32_t count, const pll_graph_desc* graphs, const pll_build_opts* opts,
+                             hipStream_t stream, pll_index** outs) {
+    if (!outs || (count && !graphs)) return PLL_EINVAL;
+    for (uint32_t i = 0; i < count; ++i) outs[i] = nullptr;
+    for (uint32_t i = 0; i < count; ++i) {
+        int rc = pll_build_labels(graphs[i].n, graphs[i].nnz, graphs[i].d_row_ptr, graphs[i].d_col,
+                                  graphs[i].d_order, opts, stream, &outs[i]);
+        if (rc != PLL_OK) {
+            for (uint32_t k = 0; k < i; ++k) {
+                free_index(outs[k]);
+                outs[k] = nullptr;
+            }
+            return rc;
+        }
+    }
+    return PLL_OK;
+}
+
+void pll_index_free(pll_index* idx) { free_index(idx); }
+
+const char* pll_status_string(int status) {
+    switch (status) {
+        case PLL_OK: return "ok";
+        case PLL_EINVAL: return "invalid argument (malformed CSR, order not a permutation, bad option or NULL pointer)";
+        case PLL_ENOMEM: return "out of memory";
+        case PLL_ENOSPC: return "label arena too small; retry with a larger pll_build_opts.arena_entries";
+        case PLL_EDIST: return "a shortest distance of 255 or more does not fit the uint8 labels";
+        case PLL_EDEVICE: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

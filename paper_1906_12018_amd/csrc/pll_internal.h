@@ -1,0 +1,162 @@
+// Internal declarations shared by the HIP sources of libpll (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pll.h"
+
+#define PLL_WAVE 64
+#define PLL_BMAX 1024                 // largest batch size b
+#define PLL_WMAX (PLL_BMAX / 64)      // 64-bit words in a b-bit candidate bit-vector
+#define PLL_INF8 255u                 // "no entry" in the per-batch distance table
+#define PLL_MAX_N (1u << 24)          // hub ranks are packed in 24 bits
+
+// Label entry: (hub rank << 8) | dist, so entries sort by hub rank.
+__host__ __device__ inline uint32_t pll_pack(uint32_t hub_rank, uint32_t d) { return (hub_rank << 8) | d; }
+
+// Device error bits (DevCounters::error).
+#define PLL_ERR_ARENA 0x1u
+#define PLL_ERR_DIST 0x2u
+#define PLL_ERR_BOUNDS 0x4u
+#define PLL_ERR_CSR 0x8u
+#define PLL_ERR_ORDER 0x10u
+
+// Small device-side control block of one build; zeroed at the start.
+struct DevCounters {
+    uint32_t act_count[2];    // active-list lengths (ping-pong by round parity)
+    uint32_t recv_count;      // receivers of the current round
+    uint32_t touched_count;   // vertices touched in the current batch
+    uint32_t error;           // PLL_ERR_* bits
+    uint32_t max_dist;
+    uint32_t max_label;
+    uint32_t pad;
+    unsigned long long arena_top;   // bump allocator over the label arena (entries)
+    unsigned long long candidates;  // distance checks
+    unsigned long long accepted;    // entries accepted by round checks
+    unsigned long long edges;       // CSR entries read by push
+    unsigned long long recheck_removed;
+    unsigned long long check_entries;      // label entries read by the pruning scans
+    unsigned long long check_table_reads;  // 64-byte table segments read by the pruning scans
+};
+
+// Everything the batch kernels of one build touch.  Vertex ids inside the
+// build are ranks (rank space), so batch i is the rank range [ib, ib + bs).
+struct BuildArgs {
+    uint32_t n;
+    uint32_t W;        // words per candidate bit-vector (ceil(b / 64))
+    uint32_t bstride;  // bytes per distance-table row (64 * W)
+    uint32_t pad0;
+    const uint64_t* rrow;   // rank-space CSR row pointers [n+1]
+    const uint32_t* rcol;   // rank-space CSR columns [nnz]
+    // growing labels: list of rank r is arena[loff[r] .. loff[r] + llen[r])
+    uint64_t* loff;
+    uint32_t* llen;
+    uint32_t* lcap;
+    uint32_t* arena;
+    uint64_t arena_cap;
+    // per-vertex bit-vectors (W words each)
+    uint64_t* C;     // candidate bit-vector C(v) of the batch (Section 4.1)
+    uint64_t* msgs;  // candidates received this round, already filtered by C
+    // per-batch distance table: T[h * bstride + k] = d(u_k, h) for (h, d) in L(u_k)
+    uint8_t* T;
+    uint32_t* rowmask;  // bit w set when row h of T has an entry in word w
+    // frontier queues
+    uint32_t* act_v[2];
+    uint64_t* act_delta[2];  // W words per active slot: delta L of that vertex
+    uint32_t* recv;
+    uint32_t* recv_stamp;
+    uint32_t* touched;
+    uint32_t* tstart;        // label length of touched[i] when first touched in the batch
+    uint32_t* touch_stamp;
+    DevCounters* ctr;
+};
+
+// ---- wavefront helpers (wave64) ----------------------------------------------------------------
+
+__device__ inline uint32_t lane_id() { return __lane_id(); }
+
+__device__ inline uint64_t lanemask_lt() {
+    const uint32_t l = lane_id();
+    return l ? (~0ull >> (64 - l)) : 0ull;
+}
+
+__device__ inline uint64_t ballot64(bool p) { return __ballot(p); }
+
+__device__ inline uint32_t readlane32(uint32_t x, uint32_t l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)l);
+}
+
+__device__ inline uint64_t readlane64(uint64_t x, uint32_t l) {
+    uint32_t lo = readlane32((uint32_t)x, l);
+    uint32_t hi = readlane32((uint32_t)(x >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t wave_or64(uint64_t x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x |= __shfl_xor(x, o, 64);
+    return x;
+}
+
+__device__ inline uint32_t wave_sum32(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__device__ inline unsigned long long wave_sum64(unsigned long long x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__device__ inline uint32_t wave_min32(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x = min(x, (uint32_t)__shfl_xor(x, o, 64));
+    return x;
+}
+
+__device__ inline uint32_t wave_max32(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x = max(x, (uint32_t)__shfl_xor(x, o, 64));
+    return x;
+}
+
+// Exclusive prefix sum over the 64 lanes.
+__device__ inline uint32_t wave_excl_scan32(uint32_t x) {
+    const uint32_t l = lane_id();
+    uint32_t s = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(s, o, 64);
+        if (l >= (uint32_t)o) s += y;
+    }
+    return s - x;
+}
+
+// Orders this wave's LDS writes before its later LDS reads.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---- host helpers --------------------------------------------------------------------------------
+
+int pll_build_one(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
+                  const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out);
+int pll_query_launch(const pll_index* idx, uint64_t count, const uint32_t* d_u, const uint32_t* d_v,
+                     uint32_t* d_out, hipStream_t stream);
+
+// Final label store (what pll_index owns).
+struct pll_index {
+    int device;
+    uint32_t n;
+    uint64_t total;
+    uint64_t* d_off;    // [n+1], by vertex id
+    uint32_t* d_ent;    // [total], packed (hub rank << 8) | dist, ascending within each list
+    uint32_t* d_order;  // [n], rank -> vertex id
+    uint32_t query_lanes;
+    pll_index_info info;
+};

@@ -1,0 +1,59 @@
+"""Helpers for the GPU parity tests: run the HIP path through the C ABI and
+compare it with the oracle on the same seeded inputs."""
+import numpy as np
+import torch
+
+import oracle
+import paper_1906_12018_amd as pll
+import synth
+
+DEV = torch.device("cuda:0")
+
+
+def to_dev(g, order):
+    rp, cl = pll.graph_to_device(g, DEV)
+    od = torch.from_numpy(np.ascontiguousarray(order, dtype=np.uint32).view(np.int32)).to(DEV)
+    return rp, cl, od
+
+
+def build(g, order, **kw):
+    rp, cl, od = to_dev(g, order)
+    return pll.build_labels(rp, cl, od, **kw)
+
+
+def exported(idx):
+    ex = idx.export()
+    torch.cuda.synchronize()
+    return (ex.offsets.cpu().numpy().view(np.uint64), ex.hubs.cpu().numpy().view(np.uint32), ex.dists.cpu().numpy())
+
+
+def assert_labels_equal(idx, want: oracle.Labels, order):
+    off, hubs, dists = exported(idx)
+    assert np.array_equal(off, want.offsets), "offsets differ"
+    assert np.array_equal(hubs, want.hubs_as_ids(order)), "hubs differ"
+    assert np.array_equal(dists, want.dist), "dists differ"
+
+
+def gpu_query(idx, u, v):
+    du = torch.from_numpy(np.ascontiguousarray(u, dtype=np.uint32).view(np.int32)).to(DEV)
+    dv = torch.from_numpy(np.ascontiguousarray(v, dtype=np.uint32).view(np.int32)).to(DEV)
+    out = idx.query(du, dv)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint32)
+
+
+def check_counters(idx, g, order, b, want_pll: oracle.Labels):
+    """Corollary 2: candidates + n = PLL distance checks; accepted = entries
+    minus the n self entries; rounds, edge reads and checks equal the
+    sequential Algorithm 4 run with the same batch size."""
+    info = idx.info()
+    bvc = oracle.bvc_labels(g, order, b)
+    assert info["total_entries"] == want_pll.total
+    assert info["candidates"] + g.n == want_pll.counters["checks"]
+    assert info["candidates"] == bvc.counters["checks"]
+    assert info["accepted"] == want_pll.total - g.n
+    assert info["rounds"] == bvc.counters["rounds"]
+    assert info["batches"] == bvc.counters["batches"]
+    assert info["edges_scanned"] == bvc.counters["edge_accesses"]
+    assert info["max_dist"] == (int(want_pll.dist.max()) if want_pll.total else 0)
+    return info

@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI boundary (no GPU needed, no compute calls)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1906_12018_amd as pll
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pll.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pll_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    assert set(names) == set(pll.EXPORTED_SYMBOLS), names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(pll.LIB_PATH):
+        pytest.skip("libpll.so not built")
+    lib = ctypes.CDLL(pll.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", pll.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (pll_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_status_strings():
+    if not os.path.exists(pll.LIB_PATH):
+        pytest.skip("libpll.so not built")
+    for s in range(6):
+        assert isinstance(pll.status_string(s), str) and pll.status_string(s)
+    assert pll.status_string(99) == "unknown status"
+
+
+def test_struct_layouts_match_header():
+    # sizes of the C structs as laid out by the compiler for the header
+    src = r'''
+#include <stdio.h>
+#include "pll.h"
+int main(void) {
+  printf("%zu %zu %zu\n", sizeof(pll_build_opts), sizeof(pll_index_info), sizeof(pll_graph_desc));
+  return 0;
+}
+'''
+    exe = os.path.join(ROOT, "_work", "layout_probe")
+    os.makedirs(os.path.dirname(exe), exist_ok=True)
+    c = exe + ".c"
+    with open(c, "w") as f:
+        f.write(src)
+    r = subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+                        c, "-o", exe], capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("cannot compile the layout probe: " + r.stderr[:200])
+    sizes = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
+    assert sizes == [ctypes.sizeof(pll.BuildOpts), ctypes.sizeof(pll.IndexInfo), ctypes.sizeof(pll.GraphDesc)]
+
+
+def test_binding_rejects_host_tensors():
+    import torch
+    t = torch.zeros(3, dtype=torch.int64)
+    with pytest.raises(pll.PllError):
+        pll.build_labels(t, torch.zeros(0, dtype=torch.int32), torch.zeros(2, dtype=torch.int32))
+
+
+def test_product_package_does_not_use_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1906_12018_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in text and "from oracle" not in text, fn
+                assert "pll_oracle" not in text and "liboracle" not in text, fn

@@ -22,22 +22,41 @@ __host__ __device__ inline uint32_t pll_pack(uint32_t hub_rank, uint32_t d) { re
 #define PLL_ERR_CSR 0x8u
 #define PLL_ERR_ORDER 0x10u
 
-// Small device-side control block of one build; zeroed at the start.
+// Device-scope atomics on one address serialise (about 12 ns each on
+// MI355X), so every counter that many waves update is split into
+// PLL_SHARDS copies, one per 128-byte line; a workgroup uses shard
+// blockIdx.x % PLL_SHARDS.  Queues are split the same way: shard s owns its
+// own segment of each queue array.
+#define PLL_SHARDS 32
+
+enum {
+    PLL_ST_CAND = 0,     // distance checks (candidates surviving the C(v) filter)
+    PLL_ST_ACC = 1,      // entries accepted by round checks
+    PLL_ST_EDGES = 2,    // CSR entries read by push
+    PLL_ST_READ = 3,     // label entries read by pruning scans
+    PLL_ST_TABLE = 4,    // 64-byte table segments read by pruning scans
+    PLL_ST_GROW = 5,     // label lists moved to a larger block
+    PLL_ST_RECHECK = 6,  // entries dropped by the recheck
+    PLL_NUM_ST = 12
+};
+
+struct alignas(128) Shard {
+    uint32_t recv[2];     // receivers appended to this shard's segment, by round parity
+    uint32_t hq[2];       // heavy push items, by active-list parity
+    uint32_t touched;     // vertices first touched in the batch
+    uint32_t pad;
+    unsigned long long arena_top;  // bump pointer of this shard's arena region (entries, region-relative)
+    unsigned long long stat[PLL_NUM_ST];
+};
+static_assert(sizeof(Shard) == 128, "one shard per 128-byte line");
+
+// Device-side control block of one build; zeroed at the start.
 struct DevCounters {
-    uint32_t act_count[2];    // active-list lengths (ping-pong by round parity)
-    uint32_t recv_count;      // receivers of the current round
-    uint32_t touched_count;   // vertices touched in the current batch
-    uint32_t error;           // PLL_ERR_* bits
+    uint32_t error;  // PLL_ERR_* bits
     uint32_t max_dist;
     uint32_t max_label;
-    uint32_t pad;
-    unsigned long long arena_top;   // bump allocator over the label arena (entries)
-    unsigned long long candidates;  // distance checks
-    unsigned long long accepted;    // entries accepted by round checks
-    unsigned long long edges;       // CSR entries read by push
-    unsigned long long recheck_removed;
-    unsigned long long check_entries;      // label entries read by the pruning scans
-    unsigned long long check_table_reads;  // 64-byte table segments read by the pruning scans
+    uint32_t pad[29];
+    Shard sh[PLL_SHARDS];
 };
 
 // Everything the batch kernels of one build touch.  Vertex ids inside the
@@ -54,19 +73,22 @@ struct BuildArgs {
     uint32_t* llen;
     uint32_t* lcap;
     uint32_t* arena;
-    uint64_t arena_cap;
+    uint64_t region_base;  // PLL_SHARDS bump regions follow the compacted lists
+    uint64_t region_cap;   // entries per region
     // per-vertex bit-vectors (W words each)
     uint64_t* C;     // candidate bit-vector C(v) of the batch (Section 4.1)
     uint64_t* msgs;  // candidates received this round, already filtered by C
     // per-batch distance table: T[h * bstride + k] = d(u_k, h) for (h, d) in L(u_k)
     uint8_t* T;
     uint32_t* rowmask;  // bit w set when row h of T has an entry in word w
-    // frontier queues
-    uint32_t* act_v[2];
+    // frontier queues (shard s owns [s * seg, (s + 1) * seg) of each)
+    uint32_t* act_v[2];      // active list by parity (compact)
     uint64_t* act_delta[2];  // W words per active slot: delta L of that vertex
-    uint32_t* recv;
+    uint2* hq[2];            // (active slot, chunk) items for rows longer than the heavy threshold
+    uint64_t hq_seg;
+    uint32_t* recv;          // receivers of the current round, segment per shard (seg = n)
     uint32_t* recv_stamp;
-    uint32_t* touched;
+    uint32_t* touched;       // first touches of the batch, segment per shard (seg = n)
     uint32_t* tstart;        // label length of touched[i] when first touched in the batch
     uint32_t* touch_stamp;
     DevCounters* ctr;

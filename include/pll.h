@@ -86,7 +86,10 @@ typedef struct {
     uint64_t arena_entries; /* label arena capacity in 4-byte entries during the build; 0 = automatic
                                (grows and retries on its own; a nonzero value fails with PLL_ENOSPC) */
     uint32_t query_lanes;   /* lanes cooperating on one query pair: 0 = automatic, else 1, 4, 8, 16, 32 or 64 */
-    uint32_t reserved[7];   /* must be zero */
+    uint32_t gang_scale;    /* batched build: percent applied to each graph's work-proportional number of
+                               workgroups (0 = 100) */
+    uint32_t max_gang;      /* batched build: most workgroups on one graph, 1..16 (0 = 16) */
+    uint32_t reserved[5];   /* must be zero */
 } pll_build_opts;
 
 typedef struct {
@@ -104,7 +107,7 @@ typedef struct {
     uint64_t recheck_removed; /* entries dropped by the label-cleaning recheck (0 for exact rounds) */
     uint64_t arena_entries;   /* arena capacity the successful build used */
     uint32_t build_attempts;  /* 1 + automatic arena retries */
-    uint32_t reserved0;
+    uint32_t gang;            /* batched build: workgroups that built this graph (1 otherwise) */
     double build_ms;          /* host wall time of pll_build_labels */
     uint64_t check_entries_read;  /* label entries the pruning checks read */
     uint64_t check_table_reads;   /* 64-byte distance-table segments the pruning checks read */
@@ -161,9 +164,13 @@ int pll_export_labels(const pll_index* idx, uint64_t* d_offsets, uint32_t* d_hub
                       hipStream_t stream);
 
 /*
- * Build `count` independent graphs in one persistent-kernel launch (the
- * same labels as pll_build_labels on each graph).  outs[i] receives the
- * index of graphs[i].  On error no index is returned.
+ * Build `count` independent graphs in one persistent-kernel launch, captured
+ * in a hipGraph (the same labels as pll_build_labels on each graph).  Each
+ * graph is built by a gang of workgroups sized by its share of the estimated
+ * work (opts->gang_scale, opts->max_gang); all graphs use opts->batch_size.
+ * outs[i] receives the index of graphs[i]; the label entries of all of them
+ * share one device allocation, released with the last of these indexes.
+ * On error no index is returned.
  */
 int pll_build_labels_batched(uint32_t count, const pll_graph_desc* graphs, const pll_build_opts* opts,
                              hipStream_t stream, pll_index** outs);

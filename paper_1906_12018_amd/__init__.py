@@ -46,7 +46,9 @@ class BuildOpts(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("arena_entries", ctypes.c_uint64),
         ("query_lanes", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 7),
+        ("gang_scale", ctypes.c_uint32),
+        ("max_gang", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 5),
     ]
 
 
@@ -66,7 +68,7 @@ class IndexInfo(ctypes.Structure):
         ("recheck_removed", ctypes.c_uint64),
         ("arena_entries", ctypes.c_uint64),
         ("build_attempts", ctypes.c_uint32),
-        ("reserved0", ctypes.c_uint32),
+        ("gang", ctypes.c_uint32),
         ("build_ms", ctypes.c_double),
         ("check_entries_read", ctypes.c_uint64),
         ("check_table_reads", ctypes.c_uint64),
@@ -144,12 +146,15 @@ def _dev(t: torch.Tensor, dtype: torch.dtype, name: str) -> torch.Tensor:
     return t.contiguous()
 
 
-def _opts(batch_size: int, flags: int, arena_entries: int, query_lanes: int) -> BuildOpts:
+def _opts(batch_size: int, flags: int, arena_entries: int, query_lanes: int, gang_scale: int = 0,
+          max_gang: int = 0) -> BuildOpts:
     o = BuildOpts()
     o.batch_size = batch_size
     o.flags = flags
     o.arena_entries = arena_entries
     o.query_lanes = query_lanes
+    o.gang_scale = gang_scale
+    o.max_gang = max_gang
     return o
 
 
@@ -243,9 +248,11 @@ def build_labels(row_ptr: torch.Tensor, col: torch.Tensor, order: torch.Tensor, 
 
 
 def build_labels_batched(graphs, batch_size: int = DEFAULT_BATCH, flags: int = FLAG_VALIDATE,
-                         arena_entries: int = 0, query_lanes: int = 0, stream=None) -> list:
-    """Build many graphs at once; ``graphs`` is a list of (row_ptr, col, order)
-    device tensors.  Returns one :class:`Index` per graph."""
+                         arena_entries: int = 0, query_lanes: int = 0, gang_scale: int = 0, max_gang: int = 0,
+                         stream=None) -> list:
+    """Build many graphs in one persistent launch; ``graphs`` is a list of
+    (row_ptr, col, order) device tensors.  Returns one :class:`Index` per
+    graph."""
     descs = (GraphDesc * max(len(graphs), 1))()
     keep = []
     for i, (rp, cl, od) in enumerate(graphs):
@@ -259,7 +266,7 @@ def build_labels_batched(graphs, batch_size: int = DEFAULT_BATCH, flags: int = F
         descs[i].d_col = cl.data_ptr()
         descs[i].d_order = od.data_ptr()
     outs = (ctypes.c_void_p * max(len(graphs), 1))()
-    o = _opts(batch_size, flags, arena_entries, query_lanes)
+    o = _opts(batch_size, flags, arena_entries, query_lanes, gang_scale, max_gang)
     rc = load_library().pll_build_labels_batched(len(graphs), descs, ctypes.byref(o), _stream_handle(stream), outs)
     if rc:
         raise PllError(rc, "pll_build_labels_batched")

@@ -23,8 +23,15 @@ void free_index(pll_index* idx) {
     bool switched = false;
     if (hipGetDevice(&cur) == hipSuccess && cur != idx->device) switched = hipSetDevice(idx->device) == hipSuccess;
     (void)hipFree(idx->d_off);
-    (void)hipFree(idx->d_ent);
     (void)hipFree(idx->d_order);
+    if (idx->store) {
+        if (--idx->store->refs == 0) {
+            (void)hipFree(idx->store->ptr);
+            delete idx->store;
+        }
+    } else {
+        (void)hipFree(idx->d_ent);
+    }
     if (switched) (void)hipSetDevice(cur);
     delete idx;
 }
@@ -74,20 +81,11 @@ int pll_export_labels(const pll_index* idx, uint64_t* d_offsets, uint32_t* d_hub
 
 int pll_build_labels_batched(uint32_t count, const pll_graph_desc* graphs, const pll_build_opts* opts,
                              hipStream_t stream, pll_index** outs) {
-    if (!outs || (count && !graphs)) return PLL_EINVAL;
-    for (uint32_t i = 0; i < count; ++i) outs[i] = nullptr;
-    for (uint32_t i = 0; i < count; ++i) {
-        int rc = pll_build_labels(graphs[i].n, graphs[i].nnz, graphs[i].d_row_ptr, graphs[i].d_col,
-                                  graphs[i].d_order, opts, stream, &outs[i]);
-        if (rc != PLL_OK) {
-            for (uint32_t k = 0; k < i; ++k) {
-                free_index(outs[k]);
-                outs[k] = nullptr;
-            }
-            return rc;
-        }
+    try {
+        return pll_build_multi(count, graphs, opts, stream, outs);
+    } catch (...) {
+        return PLL_ENOMEM;
     }
-    return PLL_OK;
 }
 
 void pll_index_free(pll_index* idx) { free_index(idx); }

@@ -171,6 +171,17 @@ int pll_build_one(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uin
 int pll_query_launch(const pll_index* idx, uint64_t count, const uint32_t* d_u, const uint32_t* d_v,
                      uint32_t* d_out, hipStream_t stream);
 
+int pll_build_multi(uint32_t count, const pll_graph_desc* graphs, const pll_build_opts* opts, hipStream_t stream,
+                    pll_index** outs);
+
+// Label entries of several indexes built together live in one allocation,
+// released when the last of those indexes is freed.
+struct pll_shared_store {
+    void* ptr;
+    int refs;
+    int device;
+};
+
 // Final label store (what pll_index owns).
 struct pll_index {
     int device;
@@ -180,5 +191,6 @@ struct pll_index {
     uint32_t* d_ent;    // [total], packed (hub rank << 8) | dist, ascending within each list
     uint32_t* d_order;  // [n], rank -> vertex id
     uint32_t query_lanes;
+    pll_shared_store* store;  // non-null when d_ent points into a shared allocation
     pll_index_info info;
 };

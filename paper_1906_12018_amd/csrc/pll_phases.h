@@ -1,0 +1,480 @@
+// Device-side building blocks of one BVC-PLL batch (Algorithm 4), shared by
+// the whole-grid kernels of a single large graph (pll_build.hip) and by the
+// persistent kernel that builds many graphs, one workgroup per graph
+// (pll_multi.hip).  A phase is run by an execution group described by Exec:
+// wave w of nw waves; queue counters live in nq shards at qs (32 global
+// shards for the whole-grid kernels, one LDS shard for a workgroup), and
+// this wave appends to shard `my`, whose queue segments start at
+// my * seg.
+#pragma once
+
+#include "pll_internal.h"
+
+namespace pll {
+
+// Rows longer than this are pushed as several work items of kHeavy edges.
+constexpr uint32_t kHeavy = 1024;
+
+struct Exec {
+    uint32_t w, nw;   // this wave's index in the group, waves in the group
+    Shard* qs;        // queue / statistics shards
+    uint32_t nq;      // number of shards
+    uint32_t my;      // shard this wave appends to
+    uint32_t seg;     // entries per shard segment of recv / touched / tstart
+    uint32_t zero_i;  // shard this thread clears when a phase resets counters (>= nq: none)
+    uint32_t arena_sh;  // first arena region to try
+};
+
+// Per-lane statistics a phase accumulates (summed over lanes by the caller).
+struct PhaseStats {
+    unsigned long long cand = 0, acc = 0, edges = 0, read = 0, table = 0, removed = 0;
+};
+
+// Per byte of x: 1 if byte <= t, where tt = t * 0x01010101 (t <= 254).  Bytes
+// are compared without carries between them: s holds, in bit 7 of each
+// byte, [low 7 bits of t >= low 7 bits of x]; the high bits decide the rest.
+__device__ inline uint32_t le4(uint32_t x, uint32_t tt) {
+    const uint32_t H = 0x80808080u;
+    const uint32_t s = (tt | H) - (x & ~H);
+    const uint32_t r = ((tt & ~x) | (~(tt ^ x) & s)) & H;
+    return ((r >> 7) * 0x01020408u) >> 24;  // gather bits 7, 15, 23, 31 into bits 0..3
+}
+
+// Bit i of the result: table byte p[i] <= t, for 64 consecutive bytes.
+__device__ inline uint64_t le_mask64(const uint8_t* p, uint32_t tt) {
+    const uint4* q = reinterpret_cast<const uint4*>(p);
+    uint64_t m = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint4 v = q[i];
+        const uint32_t b = le4(v.x, tt) | (le4(v.y, tt) << 4) | (le4(v.z, tt) << 8) | (le4(v.w, tt) << 12);
+        m |= (uint64_t)b << (16 * i);
+    }
+    return m;
+}
+
+// OR over the 64 lanes (DPP wave reduction); the result is wave-uniform.
+__device__ inline uint64_t wave_or64_u(uint64_t x) {
+    const unsigned lo = __reduce_or_sync(~0ull, (unsigned)x);
+    const unsigned hi = __reduce_or_sync(~0ull, (unsigned)(x >> 32));
+    return ((uint64_t)__builtin_amdgcn_readfirstlane(hi) << 32) | (uint32_t)__builtin_amdgcn_readfirstlane(lo);
+}
+
+// Scan the label list arena[off .. off+len) of one vertex v.  Lane w (< W)
+// holds candidate word cw = bits k of batch vertices u_{64w+k} that arrived
+// at distance j.  Returns, in lane w, the candidates of word w for which some
+// entry (h, d) of the list with d < j has T[h][k] + d <= j, i.e. the distance
+// j is already covered through a hub ranked above u_k (Algorithm 4, line 14).
+// With `relaxed`, entries whose hub is in the current batch are skipped.
+// The table loads of all candidate words of a chunk are independent; lanes
+// are OR-reduced every 4 chunks (and at the end), which is also where the
+// scan stops once every candidate is pruned.
+template <int WM>
+__device__ inline uint64_t prune_scan(const BuildArgs& A, uint64_t off, uint32_t len, uint32_t j, uint64_t cw,
+                                      bool relaxed, uint32_t ib, PhaseStats& st) {
+    const uint32_t lane = lane_id();
+    uint64_t pw = 0;
+    uint64_t accm[WM];
+#pragma unroll
+    for (int w = 0; w < WM; ++w) accm[w] = 0;
+    uint32_t chunk = 0;
+    for (uint32_t base = 0; base < len; base += 64, ++chunk) {
+        const uint32_t idx = base + lane;
+        bool ok = idx < len;
+        st.read += ok;
+        const uint32_t ent = ok ? A.arena[off + idx] : 0u;
+        const uint32_t h = ent >> 8, d = ent & 255u;
+        ok = ok && d < j;
+        if (relaxed) ok = ok && h < ib;
+        const uint32_t rm = ok ? A.rowmask[h] : 0u;
+        const uint32_t tt = ok ? (j - d) * 0x01010101u : 0u;
+        const uint8_t* row = A.T + (size_t)h * A.bstride;
+        const uint64_t live_lane = cw & ~pw;
+#pragma unroll
+        for (int w = 0; w < WM; ++w) {
+            const uint64_t live = readlane64(live_lane, w);
+            if (live != 0 && ((rm >> w) & 1u)) {
+                accm[w] |= le_mask64(row + 64u * w, tt) & live;
+                ++st.table;
+            }
+        }
+        if ((chunk & 3u) == 3u || base + 64 >= len) {
+#pragma unroll
+            for (int w = 0; w < WM; ++w) {
+                if (readlane64(live_lane, w)) {
+                    const uint64_t red = wave_or64_u(accm[w]);
+                    if (lane == (uint32_t)w) pw |= red;
+                    accm[w] = 0;
+                }
+            }
+            if (!ballot64((cw & ~pw) != 0)) break;
+        }
+    }
+    return pw;
+}
+
+// Room for `need` more entries in the list of rank v (capacity doubling).
+// New blocks come from the bump region X.arena_sh of the arena, or from the
+// next region with room.  Wave-uniform; returns the list's offset, or ~0
+// when every region is exhausted.
+__device__ inline uint64_t wave_reserve(const BuildArgs& A, const Exec& X, uint32_t v, uint64_t off, uint32_t len,
+                                        uint32_t need) {
+    const uint32_t cap = A.lcap[v];
+    if (len + need <= cap) return off;
+    uint32_t newcap = max(cap * 2u, (len + need + 15u) & ~15u);
+    newcap = max(newcap, 16u);
+    unsigned long long nb = ~0ull;
+    if (lane_id() == 0) {
+        for (uint32_t t = 0; t < PLL_SHARDS; ++t) {
+            const uint32_t sh = (X.arena_sh + t) % PLL_SHARDS;
+            unsigned long long* top = &A.ctr->sh[sh].arena_top;
+            if (__hip_atomic_load(top, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + newcap > A.region_cap) continue;
+            const unsigned long long at = atomicAdd(top, (unsigned long long)newcap);
+            if (at + newcap <= A.region_cap) {
+                nb = A.region_base + (unsigned long long)sh * A.region_cap + at;
+                break;
+            }
+        }
+        atomicAdd(&A.ctr->sh[X.arena_sh % PLL_SHARDS].stat[PLL_ST_GROW], 1ull);
+    }
+    nb = readlane64(nb, 0);
+    if (nb == ~0ull) {
+        if (lane_id() == 0) atomicOr(&A.ctr->error, PLL_ERR_ARENA);
+        return ~0ull;
+    }
+    for (uint32_t k = lane_id(); k < len; k += 64) A.arena[nb + k] = A.arena[off + k];
+    if (lane_id() == 0) {
+        A.loff[v] = nb;
+        A.lcap[v] = newcap;
+    }
+    return nb;
+}
+
+// Sharded queue enumeration: lane s (< nq) holds the count of shard s;
+// `pre` receives its exclusive prefix and the return value the total.
+__device__ inline uint32_t shard_prefix(uint32_t cnt_lane, uint32_t& pre) {
+    pre = wave_excl_scan32(cnt_lane);
+    return readlane32(pre + cnt_lane, 63);
+}
+
+// Shard holding global queue position i (wave-uniform i < total).
+__device__ inline uint32_t shard_of(uint32_t nq, uint32_t pre_lane, uint32_t i) {
+    const uint64_t m = ballot64(lane_id() < nq && pre_lane <= i);
+    return 63u - (uint32_t)__builtin_clzll(m);
+}
+
+// Wave-aggregated append of the lanes with `take` to a queue counter;
+// returns each taking lane's position (seg_base + index).
+__device__ inline uint32_t shard_append(uint32_t* counter, bool take, uint64_t seg_base) {
+    const uint64_t bal = ballot64(take);
+    if (!bal) return 0;
+    const uint32_t lane = lane_id();
+    const uint32_t leader = (uint32_t)__builtin_ctzll(bal);
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, (uint32_t)__builtin_popcountll(bal));
+    base = readlane32(base, leader);
+    return (uint32_t)(seg_base + base + __builtin_popcountll(bal & lanemask_lt()));
+}
+
+// Queue the row of active slot `slot` (list q) as kHeavy-edge items when
+// it is longer than kHeavy.
+__device__ inline void enqueue_heavy(const BuildArgs& A, const Exec& X, uint32_t q, uint32_t slot, uint64_t deg) {
+    if (deg <= kHeavy) return;
+    const uint32_t nch = (uint32_t)((deg + kHeavy - 1) / kHeavy);
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(&X.qs[X.my].hq[q], nch);
+    base = readlane32(base, 0);
+    for (uint32_t c = lane_id(); c < nch; c += 64) A.hq[q][X.my * A.hq_seg + base + c] = make_uint2(slot, c);
+}
+
+__device__ inline uint64_t rank_mask(uint32_t rel, uint32_t w) {
+    const uint32_t lo = w * 64u;
+    if (rel >= lo + 64u) return ~0ull;
+    if (rel <= lo) return 0ull;
+    return (1ull << (rel - lo)) - 1ull;
+}
+
+// Algorithm 4, line 4: delta L(u) = {(u,0)}, L(u) gets (u,0), L(u) -> H(u).
+// The initial active list holds batch vertex u_k in slot k.
+__device__ inline void phase_batch_init(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t bs, uint32_t bstamp) {
+    const uint32_t lane = lane_id();
+    for (uint32_t k = X.w; k < bs; k += X.nw) {
+        const uint32_t u = ib + k;
+        const uint32_t len = A.llen[u];
+        const uint32_t tpos = shard_append(&X.qs[X.my].touched, lane == 0, (uint64_t)X.my * X.seg);
+        if (lane == 0) {
+            A.touch_stamp[u] = bstamp;
+            A.touched[tpos] = u;
+            A.tstart[tpos] = len;
+        }
+        const uint64_t off = wave_reserve(A, X, u, A.loff[u], len, 1);
+        if (off == ~0ull) continue;
+        const uint32_t kw = 1u << (k >> 6);
+        if (lane == 0) {
+            A.arena[off + len] = pll_pack(u, 0);
+            A.llen[u] = len + 1;
+            A.T[(size_t)u * A.bstride + k] = 0;
+            atomicOr(&A.rowmask[u], kw);
+        }
+        for (uint32_t i = lane; i < len; i += 64) {
+            const uint32_t e = A.arena[off + i];
+            const uint32_t h = e >> 8;
+            A.T[(size_t)h * A.bstride + k] = (uint8_t)(e & 255u);
+            atomicOr(&A.rowmask[h], kw);
+        }
+        if (lane == 0) A.act_v[0][k] = u;
+        if (lane < A.W) A.act_delta[0][(size_t)k * A.W + lane] = (lane == (k >> 6)) ? (1ull << (k & 63)) : 0ull;
+        enqueue_heavy(A, X, 0, k, A.rrow[u + 1] - A.rrow[u]);
+    }
+}
+
+// Push delta L(a) (lane w < W holds word w in dl; nz marks the nonzero
+// words) along the CSR entries [beg, end) of the active vertex a.
+__device__ inline void push_edges(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t p, uint32_t rstamp,
+                                  uint32_t bstamp, uint64_t dl, uint64_t nz, uint64_t beg, uint64_t end) {
+    const uint32_t lane = lane_id();
+    for (uint64_t e0 = beg; e0 < end; e0 += 64) {
+        const uint64_t e = e0 + lane;
+        const uint32_t r = e < end ? A.rcol[e] : 0u;
+        bool any = false;
+        if (e < end && r > ib) {
+            const uint32_t rel = r - ib;
+            uint64_t todo = nz;
+            while (todo) {
+                const uint32_t w = (uint32_t)__builtin_ctzll(todo);
+                todo &= todo - 1;
+                uint64_t m = readlane64(dl, w) & rank_mask(rel, w);
+                if (m) {
+                    m &= ~A.C[(size_t)r * A.W + w];
+                    if (m) {
+                        atomicOr((unsigned long long*)&A.msgs[(size_t)r * A.W + w], (unsigned long long)m);
+                        any = true;
+                    }
+                }
+            }
+        }
+        // one receiver slot per vertex and round; the lane that wins the
+        // slot also records the vertex's first touch in this batch
+        bool enq = false;
+        if (any && A.recv_stamp[r] != rstamp) enq = atomicExch(&A.recv_stamp[r], rstamp) != rstamp;
+        bool first = false;
+        if (enq && A.touch_stamp[r] != bstamp) {
+            A.touch_stamp[r] = bstamp;
+            first = true;
+        }
+        if (ballot64(enq)) {
+            const uint32_t rp = shard_append(&X.qs[X.my].recv[p], enq, (uint64_t)X.my * X.seg);
+            if (enq) A.recv[rp] = r;
+            const uint32_t tp = shard_append(&X.qs[X.my].touched, first, (uint64_t)X.my * X.seg);
+            if (first) {
+                A.touched[tp] = r;
+                A.tstart[tp] = A.llen[r];
+            }
+        }
+    }
+}
+
+// Scatter phase (Algorithm 4, lines 6-10) over active list p (nact slots).
+// Batch vertex u_k may be sent to v only when u_k outranks v (rank ib + k
+// < v) and C(v) does not hold it yet.  Slots whose delta is empty are
+// skipped; rows longer than kHeavy were queued as items and are spread over
+// every wave after the per-slot pass.
+__device__ inline void phase_push(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t p, uint32_t nact,
+                                  uint32_t rstamp, uint32_t bstamp, PhaseStats& st) {
+    const uint32_t lane = lane_id();
+    if (X.zero_i < X.nq) X.qs[X.zero_i].hq[p ^ 1u] = 0;
+    const uint32_t* act_v = A.act_v[p];
+    const uint64_t* act_d = A.act_delta[p];
+    for (uint32_t i = X.w; i < nact; i += X.nw) {
+        const uint64_t dl = lane < A.W ? act_d[(size_t)i * A.W + lane] : 0ull;
+        const uint64_t nz = ballot64(dl != 0);
+        if (!nz) continue;
+        const uint32_t a = act_v[i];
+        const uint64_t beg = A.rrow[a], end = A.rrow[a + 1];
+        if (end - beg > kHeavy) continue;
+        if (lane == 0) st.edges += end - beg;
+        push_edges(A, X, ib, p, rstamp, bstamp, dl, nz, beg, end);
+    }
+    uint32_t pre;
+    const uint32_t nh = shard_prefix(lane < X.nq ? X.qs[lane].hq[p] : 0u, pre);
+    for (uint32_t t = X.w; t < nh; t += X.nw) {
+        const uint32_t s = shard_of(X.nq, pre, t);
+        const uint2 item = A.hq[p][s * A.hq_seg + (t - readlane32(pre, s))];
+        const uint64_t dl = lane < A.W ? act_d[(size_t)item.x * A.W + lane] : 0ull;
+        const uint64_t nz = ballot64(dl != 0);
+        const uint32_t a = act_v[item.x];
+        const uint64_t beg = A.rrow[a] + (uint64_t)item.y * kHeavy;
+        const uint64_t end = min(A.rrow[a + 1], beg + kHeavy);
+        if (lane == 0) st.edges += end - beg;
+        push_edges(A, X, ib, p, rstamp, bstamp, dl, nz, beg, end);
+    }
+}
+
+// Gather phase (Algorithm 4, lines 11-19) for round j: one wave per
+// receiver.  Receiver i (in shard order) becomes slot i of the next active
+// list (with an empty delta when nothing was accepted).
+template <int WM>
+__device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t bs, uint32_t j, uint32_t p,
+                                   bool relaxed, PhaseStats& st) {
+    const uint32_t lane = lane_id();
+    const uint32_t W = A.W;
+    const uint32_t q = p ^ 1u;
+    uint32_t pre;
+    const uint32_t nrecv = shard_prefix(lane < X.nq ? X.qs[lane].recv[p] : 0u, pre);
+    // clear the other parity's receiver counts for the next round's push
+    if (X.zero_i < X.nq) X.qs[X.zero_i].recv[q] = 0;
+    for (uint32_t i = X.w; i < nrecv; i += X.nw) {
+        const uint32_t s = shard_of(X.nq, pre, i);
+        const uint32_t v = A.recv[(size_t)s * X.seg + (i - readlane32(pre, s))];
+        uint64_t mine = 0;
+        if (lane < W) {
+            const size_t at = (size_t)v * W + lane;
+            mine = A.msgs[at];
+            A.msgs[at] = 0;
+            A.C[at] |= mine;
+        }
+        const uint32_t len = A.llen[v];
+        uint64_t off = A.loff[v];
+        const uint64_t pw = prune_scan<WM>(A, off, len, j, mine, relaxed, ib, st);
+        const uint64_t acc = lane < W ? (mine & ~pw) : 0ull;
+        const uint32_t cnt = (uint32_t)__builtin_popcountll(acc);
+        const uint32_t pos = wave_excl_scan32(cnt);
+        const uint32_t total = readlane32(pos + cnt, 63);
+        st.cand += __builtin_popcountll(mine);
+        if (lane == 0) A.act_v[q][i] = v;
+        if (lane < W) A.act_delta[q][(size_t)i * W + lane] = acc;
+        if (total == 0) continue;
+        if (j >= PLL_INF8) {
+            if (lane == 0) atomicOr(&A.ctr->error, PLL_ERR_DIST);
+            continue;
+        }
+        off = wave_reserve(A, X, v, off, len, total);
+        if (off == ~0ull) continue;
+        if (lane == 0) st.acc += total;
+        const bool in_batch = v - ib < bs;
+        const uint64_t lt = lanemask_lt();
+        uint64_t todo = ballot64(acc != 0);
+        while (todo) {
+            const uint32_t w = (uint32_t)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint64_t aw = readlane64(acc, w);
+            const uint32_t pwos = readlane32(pos, w);
+            if ((aw >> lane) & 1ull) {
+                const uint32_t k = w * 64u + lane;
+                A.arena[off + len + pwos + __builtin_popcountll(aw & lt)] = pll_pack(ib + k, j);
+                if (in_batch) {
+                    A.T[(size_t)(ib + k) * A.bstride + (v - ib)] = (uint8_t)j;
+                    atomicOr(&A.rowmask[ib + k], 1u << ((v - ib) >> 6));
+                }
+            }
+        }
+        if (lane == 0) A.llen[v] = len + total;
+        enqueue_heavy(A, X, q, i, A.rrow[v + 1] - A.rrow[v]);
+    }
+}
+
+// Batch end, one wave per touched vertex v: clear C(v) (line 22); sort the
+// entries this batch appended to L(v) by hub rank; with `recheck`, first
+// drop every such entry (u, d) that L(u) and L(v) already cover through
+// another hub at distance <= d (Section 5.1's recheck with the batch's
+// tables still in memory).  s_pres (W words) and s_dist (b bytes) are this
+// wave's LDS scratch.
+template <int WM>
+__device__ inline void phase_batch_end(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t bs, bool recheck,
+                                       uint64_t* s_pres, uint8_t* s_dist, PhaseStats& st) {
+    const uint32_t lane = lane_id();
+    const uint32_t W = A.W;
+    uint32_t pre;
+    const uint32_t ntouched = shard_prefix(lane < X.nq ? X.qs[lane].touched : 0u, pre);
+    for (uint32_t i = X.w; i < ntouched; i += X.nw) {
+        const uint32_t sh = shard_of(X.nq, pre, i);
+        const size_t at = (size_t)sh * X.seg + (i - readlane32(pre, sh));
+        const uint32_t v = A.touched[at];
+        const uint32_t ts = A.tstart[at];
+        const uint32_t len = A.llen[v];
+        const uint64_t off = A.loff[v];
+        if (lane < W) A.C[(size_t)v * W + lane] = 0;
+        const uint32_t tail = len - ts;
+        if (tail < 2 && !(recheck && tail >= 1)) continue;
+        if (lane < W) s_pres[lane] = 0;
+        wave_lds_sync();
+        for (uint32_t x = ts + lane; x < len; x += 64) {
+            const uint32_t e = A.arena[off + x];
+            const uint32_t k = (e >> 8) - ib;
+            s_dist[k] = (uint8_t)(e & 255u);
+            atomicOr((unsigned long long*)&s_pres[k >> 6], 1ull << (k & 63));
+        }
+        wave_lds_sync();
+        if (recheck) {
+            const bool in_batch = v - ib < bs;
+            uint32_t prev = 0;
+            for (;;) {
+                uint32_t mn = PLL_INF8;
+                for (uint32_t k = lane; k < bs; k += 64) {
+                    const uint32_t d = s_dist[k];
+                    if (((s_pres[k >> 6] >> (k & 63)) & 1ull) && d > prev) mn = min(mn, d);
+                }
+                mn = wave_min32(mn);
+                if (mn == PLL_INF8) break;
+                uint64_t cw = 0;
+                if (lane < W) {
+                    const uint64_t pw = s_pres[lane];
+                    for (uint32_t bit = 0; bit < 64; ++bit) {
+                        const uint32_t k = lane * 64u + bit;
+                        if (((pw >> bit) & 1ull) && s_dist[k] == mn) cw |= 1ull << bit;
+                    }
+                }
+                const uint64_t pr = prune_scan<WM>(A, off, len, mn, cw, false, ib, st);
+                if (lane < W && pr) s_pres[lane] &= ~pr;
+                st.removed += __builtin_popcountll(pr);
+                if (in_batch) {
+                    uint64_t todo = ballot64(pr != 0);
+                    while (todo) {
+                        const uint32_t w = (uint32_t)__builtin_ctzll(todo);
+                        todo &= todo - 1;
+                        if ((readlane64(pr, w) >> lane) & 1ull)
+                            A.T[(size_t)(ib + w * 64u + lane) * A.bstride + (v - ib)] = (uint8_t)PLL_INF8;
+                    }
+                }
+                wave_lds_sync();
+                prev = mn;
+            }
+        }
+        // emit the batch segment in ascending hub rank
+        const uint64_t pw = lane < W ? s_pres[lane] : 0ull;
+        const uint32_t cnt = (uint32_t)__builtin_popcountll(pw);
+        const uint32_t pos = wave_excl_scan32(cnt);
+        const uint32_t total = readlane32(pos + cnt, 63);
+        uint64_t todo = ballot64(pw != 0);
+        while (todo) {
+            const uint32_t w = (uint32_t)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint64_t aw = readlane64(pw, w);
+            const uint32_t base = readlane32(pos, w);
+            if ((aw >> lane) & 1ull) {
+                const uint32_t k = w * 64u + lane;
+                A.arena[off + ts + base + __builtin_popcountll(aw & lanemask_lt())] = pll_pack(ib + k, s_dist[k]);
+            }
+        }
+        if (lane == 0 && total != tail) A.llen[v] = ts + total;
+        wave_lds_sync();
+    }
+}
+
+// Reset the distance table rows written during the batch.
+__device__ inline void phase_clear_table(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t bs) {
+    const uint32_t lane = lane_id();
+    for (uint32_t k = X.w; k < bs; k += X.nw) {
+        const uint32_t u = ib + k;
+        const uint32_t len = A.llen[u];
+        const uint64_t off = A.loff[u];
+        for (uint32_t i = lane; i < len; i += 64) {
+            const uint32_t h = A.arena[off + i] >> 8;
+            A.T[(size_t)h * A.bstride + k] = (uint8_t)PLL_INF8;
+            A.rowmask[h] = 0;
+        }
+        if (lane == 0) A.rowmask[u] = 0;
+    }
+}
+
+}  // namespace pll

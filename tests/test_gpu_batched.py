@@ -1,0 +1,106 @@
+"""GPU parity of the many-graph build (pll_build_labels_batched): one
+persistent-kernel launch captured in a hipGraph, one workgroup per graph at
+a time.  Every graph's labels must equal the oracle's."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1906_12018_amd as pll
+import synth
+from gpu_util import DEV, assert_labels_equal, gpu_query, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_graphs():
+    return [
+        synth.ba_graph(2000, 4, 1), synth.path_graph(40), synth.star_graph(30), synth.complete_graph(9),
+        synth.random_tree(300, 2), synth.gnp_graph(200, 0.01, 3), synth.ba_graph(5000, 7, 11),
+        synth.csr_from_edges(1, np.zeros(0), np.zeros(0)),
+        synth.disjoint_union(synth.ba_graph(400, 3, 5), synth.path_graph(12)),
+        synth.ba_graph(700, 2, 13), synth.csr_from_edges(5, np.zeros(0), np.zeros(0)),
+    ]
+
+
+@pytest.mark.parametrize("b", [64, 200, 1024])
+def test_mixed_graphs_one_launch(b):
+    gs = mixed_graphs()
+    orders = [synth.degree_order(g) for g in gs]
+    idxs = pll.build_labels_batched([to_dev(g, o) for g, o in zip(gs, orders)], batch_size=b)
+    assert len(idxs) == len(gs)
+    for g, o, idx in zip(gs, orders, idxs):
+        want = oracle.pll_labels(g, o)
+        assert_labels_equal(idx, want, o)
+        info = idx.info()
+        assert info["candidates"] + g.n == want.counters["checks"]
+        assert info["accepted"] == want.total - g.n
+        u, v = synth.query_pairs(g.n, 2000, seed=2)
+        assert np.array_equal(gpu_query(idx, u, v), oracle.query(want, u, v))
+    # indexes share one output buffer: freeing some keeps the others valid
+    for idx in idxs[::2]:
+        idx.free()
+    g, o, idx = gs[1], orders[1], idxs[1]
+    assert_labels_equal(idx, oracle.pll_labels(g, o), o)
+
+
+def test_batched_recheck_and_relaxed():
+    gs = [synth.ba_graph(1500, 5, 21), synth.ba_graph(900, 3, 22)]
+    orders = [synth.degree_order(g) for g in gs]
+    idxs = pll.build_labels_batched([to_dev(g, o) for g, o in zip(gs, orders)], batch_size=128,
+                                    flags=pll.FLAG_RECHECK | pll.FLAG_RELAXED)
+    for g, o, idx in zip(gs, orders, idxs):
+        assert_labels_equal(idx, oracle.pll_labels(g, o), o)
+        assert idx.info()["recheck_removed"] > 0
+
+
+def test_batched_rejects_invalid_graph():
+    good = synth.ba_graph(300, 2, 1)
+    bad = synth.ba_graph(300, 2, 2)
+    bo = synth.degree_order(bad).copy()
+    bo[3] = bo[4]
+    with pytest.raises(pll.PllError) as e:
+        pll.build_labels_batched([to_dev(good, synth.degree_order(good)), to_dev(bad, bo)])
+    assert e.value.status == pll.PLL_EINVAL
+
+
+def test_batching_workload_256_graphs():
+    """The 256-graph workload (n log-uniform in [500, 20000], m in {2..8}) in
+    one launch; a sample of graphs (the largest, the smallest and a seeded
+    draw) against the oracle, and every graph against the single-graph GPU
+    build (the same labels, as pll.h promises)."""
+    specs = synth.batching_specs()
+    gs = [synth.ba_graph(n, m, sd) for n, m, sd in specs]
+    orders = [synth.degree_order(g) for g in gs]
+    idxs = pll.build_labels_batched([to_dev(g, o) for g, o in zip(gs, orders)])
+    sizes = np.array([g.n for g in gs])
+    pick = set(np.argsort(sizes)[-2:].tolist()) | set(np.argsort(sizes)[:2].tolist())
+    pick |= set(int(x) for x in synth.bounded(synth.splitmix64(8, 0, 6), len(gs)))
+    for i in sorted(pick):
+        want = oracle.pll_labels(gs[i], orders[i])
+        assert_labels_equal(idxs[i], want, orders[i])
+        u, v = synth.query_pairs(gs[i].n, 5000, seed=2)
+        assert np.array_equal(gpu_query(idxs[i], u, v), oracle.query(want, u, v))
+    for i in range(0, len(gs), 1):
+        single = pll.build_labels(*to_dev(gs[i], orders[i]))
+        a, b = single.export(), idxs[i].export()
+        import torch
+        torch.cuda.synchronize()
+        assert torch.equal(a.offsets, b.offsets) and torch.equal(a.hubs, b.hubs) and torch.equal(a.dists, b.dists), i
+        single.free()
+
+
+@pytest.mark.parametrize("gang_scale,max_gang", [(100, 1), (100, 4), (300, 16), (50, 16)])
+def test_gang_sizes_do_not_change_labels(gang_scale, max_gang):
+    """Graphs built by gangs of 1..16 workgroups (barriers between phases)
+    give the oracle's labels whatever the gang sizes."""
+    gs = [synth.ba_graph(6000, 6, 31), synth.ba_graph(3000, 8, 32), synth.ba_graph(800, 3, 33),
+          synth.gnp_graph(500, 0.02, 34)]
+    orders = [synth.degree_order(g) for g in gs]
+    idxs = pll.build_labels_batched([to_dev(g, o) for g, o in zip(gs, orders)], batch_size=512,
+                                    gang_scale=gang_scale, max_gang=max_gang)
+    gangs = [i.info()["gang"] for i in idxs]
+    assert max(gangs) <= max_gang
+    for g, o, idx in zip(gs, orders, idxs):
+        want = oracle.pll_labels(g, o)
+        assert_labels_equal(idx, want, o)
+        assert idx.info()["candidates"] + g.n == want.counters["checks"]

@@ -179,6 +179,74 @@ void pll_index_free(pll_index* idx);
 
 const char* pll_status_string(int status);
 
+/*
+ * Serving loop (continuous batching over resident indexes).
+ *
+ * A server keeps label indexes resident and answers query requests as they
+ * arrive: whenever one of its `slots` (a stream with staging buffers) is
+ * free, it packs the queued requests of one index, oldest first, into one
+ * device batch of at most max_batch_pairs pairs (a larger request spans
+ * several batches), so batches of different requests overlap on the device.
+ * Labeling requests (a graph in host memory) are built on their own stream
+ * once hipMemGetInfo reports room for the job's estimated working set plus
+ * mem_reserve; the new index becomes resident under a fresh index id.
+ * Times are seconds on the server's clock; latency = t_done - t_arrival.
+ * Host arrays of a request must stay valid until its result is polled.
+ * Calls from several host threads are safe.
+ */
+#define PLL_REQ_QUERY 0u
+#define PLL_REQ_BUILD 1u
+
+typedef struct pll_server pll_server;
+
+typedef struct {
+    uint32_t slots;            /* query batches in flight, 1..16 (0 = 4) */
+    uint32_t build_batch_size; /* b of builds run by the server (0 = 1024) */
+    uint64_t max_batch_pairs;  /* pairs per device batch (0 = 1,048,576) */
+    uint64_t mem_reserve;      /* device bytes left free when admitting a build (0 = 1 GiB) */
+    uint32_t reserved[4];      /* must be zero */
+} pll_server_opts;
+
+typedef struct {
+    double at;                 /* pll_server_replay: arrival, seconds after the replay starts */
+    uint32_t kind;             /* PLL_REQ_QUERY or PLL_REQ_BUILD */
+    uint32_t index_id;         /* query: resident index to ask */
+    uint64_t count;            /* query: pairs */
+    const uint32_t* h_u;       /* query: host arrays of `count` vertex ids */
+    const uint32_t* h_v;
+    uint32_t* h_out;           /* query: host array receiving the distances */
+    uint32_t n;                /* build: vertices */
+    uint32_t reserved0;
+    uint64_t nnz;              /* build: CSR entries */
+    const uint64_t* h_row_ptr; /* build: host CSR and order, as for pll_build_labels */
+    const uint32_t* h_col;
+    const uint32_t* h_order;
+} pll_request;
+
+typedef struct {
+    uint64_t id;
+    int32_t status;            /* PLL_OK or an error of the request */
+    uint32_t kind;
+    uint32_t index_id;         /* query: the index asked; build: the new resident index */
+    uint32_t batch_requests;   /* query: requests packed in the batch that carried its first pairs */
+    double t_arrival, t_admit, t_done;
+} pll_result;
+
+int pll_server_create(const pll_server_opts* opts, pll_server** out);
+/* Make `idx` resident.  With take_ownership the server frees it in pll_server_destroy; without it the
+   caller must keep `idx` alive (not pll_index_free it) until pll_server_destroy has returned. */
+int pll_server_add_index(pll_server* server, pll_index* idx, int take_ownership, uint32_t* index_id);
+/* The resident index with this id (owned by the server if the server built it). */
+int pll_server_index(pll_server* server, uint32_t index_id, pll_index** idx);
+/* Queue one request (arrival = now); *id identifies its result. */
+int pll_server_submit(pll_server* server, const pll_request* req, uint64_t* id);
+/* Up to `max` finished results; with `wait`, block until at least one is ready or nothing is outstanding. */
+int pll_server_poll(pll_server* server, pll_result* out, uint32_t max, uint32_t* got, int wait);
+/* Open-loop replay: submit reqs[i] at reqs[i].at seconds after the call, wait for all, results in request order. */
+int pll_server_replay(pll_server* server, uint64_t count, const pll_request* reqs, pll_result* results);
+/* Finish in-flight work, free the server and the indexes it owns. */
+void pll_server_destroy(pll_server* server);
+
 #ifdef __cplusplus
 }
 #endif

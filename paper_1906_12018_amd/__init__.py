@@ -30,7 +30,10 @@ DEFAULT_BATCH = 1024
 EXPORTED_SYMBOLS = (
     "pll_build_labels", "pll_query", "pll_index_info_get", "pll_export_labels",
     "pll_build_labels_batched", "pll_index_free", "pll_status_string",
+    "pll_server_create", "pll_server_add_index", "pll_server_index", "pll_server_submit", "pll_server_poll",
+    "pll_server_replay", "pll_server_destroy",
 )
+REQ_QUERY, REQ_BUILD = 0, 1
 
 
 class PllError(RuntimeError):
@@ -98,6 +101,50 @@ class GraphDesc(ctypes.Structure):
     ]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [
+        ("slots", ctypes.c_uint32),
+        ("build_batch_size", ctypes.c_uint32),
+        ("max_batch_pairs", ctypes.c_uint64),
+        ("mem_reserve", ctypes.c_uint64),
+        ("reserved", ctypes.c_uint32 * 4),
+    ]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("at", ctypes.c_double),
+        ("kind", ctypes.c_uint32),
+        ("index_id", ctypes.c_uint32),
+        ("count", ctypes.c_uint64),
+        ("h_u", ctypes.c_void_p),
+        ("h_v", ctypes.c_void_p),
+        ("h_out", ctypes.c_void_p),
+        ("n", ctypes.c_uint32),
+        ("reserved0", ctypes.c_uint32),
+        ("nnz", ctypes.c_uint64),
+        ("h_row_ptr", ctypes.c_void_p),
+        ("h_col", ctypes.c_void_p),
+        ("h_order", ctypes.c_void_p),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_uint64),
+        ("status", ctypes.c_int32),
+        ("kind", ctypes.c_uint32),
+        ("index_id", ctypes.c_uint32),
+        ("batch_requests", ctypes.c_uint32),
+        ("t_arrival", ctypes.c_double),
+        ("t_admit", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -125,6 +172,21 @@ def load_library(path: str = LIB_PATH):
     lib.pll_index_free.restype = None
     lib.pll_status_string.argtypes = [ctypes.c_int]
     lib.pll_status_string.restype = ctypes.c_char_p
+    lib.pll_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(P)]
+    lib.pll_server_create.restype = ctypes.c_int
+    lib.pll_server_add_index.argtypes = [P, P, ctypes.c_int, ctypes.POINTER(ctypes.c_uint32)]
+    lib.pll_server_add_index.restype = ctypes.c_int
+    lib.pll_server_index.argtypes = [P, ctypes.c_uint32, ctypes.POINTER(P)]
+    lib.pll_server_index.restype = ctypes.c_int
+    lib.pll_server_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.pll_server_submit.restype = ctypes.c_int
+    lib.pll_server_poll.argtypes = [P, ctypes.POINTER(Result), ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
+                                    ctypes.c_int]
+    lib.pll_server_poll.restype = ctypes.c_int
+    lib.pll_server_replay.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Request), ctypes.POINTER(Result)]
+    lib.pll_server_replay.restype = ctypes.c_int
+    lib.pll_server_destroy.argtypes = [P]
+    lib.pll_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -280,3 +342,133 @@ def graph_to_device(g, device="cuda"):
     rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr).view(np.int64)).to(device)
     cl = torch.from_numpy(np.ascontiguousarray(g.col).view(np.int32)).to(device)
     return rp, cl
+
+
+class Server:
+    """Continuous-batching query server over resident indexes (pll_server_*).
+
+    Query requests carry host numpy arrays (uint32 ids in, uint32 distances
+    out); the server keeps them alive until their results are polled."""
+
+    def __init__(self, slots: int = 4, max_batch_pairs: int = 0, mem_reserve: int = 0, build_batch_size: int = 0):
+        o = ServerOpts()
+        o.slots = slots
+        o.max_batch_pairs = max_batch_pairs
+        o.mem_reserve = mem_reserve
+        o.build_batch_size = build_batch_size
+        h = ctypes.c_void_p()
+        rc = load_library().pll_server_create(ctypes.byref(o), ctypes.byref(h))
+        if rc:
+            raise PllError(rc, "pll_server_create")
+        self._h = h
+        self._keep = {}
+        self._indexes = []  # non-owned indexes stay alive as long as the server
+
+    def add_index(self, index: Index, take_ownership: bool = False) -> int:
+        """Make `index` resident.  Without ownership the server keeps a
+        reference to the Python object, so its device memory outlives every
+        query the server runs on it."""
+        iid = ctypes.c_uint32()
+        rc = load_library().pll_server_add_index(self._h, index.handle, int(take_ownership), ctypes.byref(iid))
+        if rc:
+            raise PllError(rc, "pll_server_add_index")
+        if take_ownership:
+            index._h = ctypes.c_void_p(0)
+        else:
+            self._indexes.append(index)
+        return iid.value
+
+    def index(self, index_id: int) -> "Index":
+        """A non-owning view of a resident index (valid while the server lives)."""
+        h = ctypes.c_void_p()
+        rc = load_library().pll_server_index(self._h, index_id, ctypes.byref(h))
+        if rc:
+            raise PllError(rc, "pll_server_index")
+        view = Index(h.value, torch.device("cuda"))
+        view.free = lambda: None
+        return view
+
+    @staticmethod
+    def query_request(index_id: int, u, v, out, at: float = 0.0):
+        import numpy as np
+        u = np.ascontiguousarray(u, dtype=np.uint32)
+        v = np.ascontiguousarray(v, dtype=np.uint32)
+        assert out.dtype == np.uint32 and out.flags["C_CONTIGUOUS"] and out.shape == u.shape == v.shape
+        r = Request()
+        r.at = at
+        r.kind = REQ_QUERY
+        r.index_id = index_id
+        r.count = u.shape[0]
+        r.h_u, r.h_v, r.h_out = u.ctypes.data, v.ctypes.data, out.ctypes.data
+        return r, (u, v, out)
+
+    @staticmethod
+    def build_request(row_ptr, col, order, at: float = 0.0):
+        import numpy as np
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.uint64)
+        col = np.ascontiguousarray(col, dtype=np.uint32)
+        order = np.ascontiguousarray(order, dtype=np.uint32)
+        r = Request()
+        r.at = at
+        r.kind = REQ_BUILD
+        r.n = order.shape[0]
+        r.nnz = col.shape[0]
+        r.h_row_ptr, r.h_col, r.h_order = row_ptr.ctypes.data, col.ctypes.data if col.size else None, \
+            order.ctypes.data if order.size else None
+        return r, (row_ptr, col, order)
+
+    def submit(self, req_and_arrays) -> int:
+        r, arrays = req_and_arrays
+        rid = ctypes.c_uint64()
+        rc = load_library().pll_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid))
+        if rc:
+            raise PllError(rc, "pll_server_submit")
+        self._keep[rid.value] = arrays
+        return rid.value
+
+    def poll(self, wait: bool = False, max_results: int = 1024) -> list:
+        buf = (Result * max_results)()
+        got = ctypes.c_uint32()
+        rc = load_library().pll_server_poll(self._h, buf, max_results, ctypes.byref(got), int(wait))
+        if rc:
+            raise PllError(rc, "pll_server_poll")
+        out = []
+        for i in range(got.value):
+            d = buf[i].as_dict()
+            self._keep.pop(d["id"], None)
+            out.append(d)
+        return out
+
+    def wait(self, rid: int) -> dict:
+        while True:
+            for d in self.poll(wait=True):
+                if d["id"] == rid:
+                    return d
+
+    def replay(self, reqs_and_arrays) -> list:
+        """Open-loop replay: request i is submitted reqs[i].at seconds after
+        the call starts; returns the results in request order."""
+        n = len(reqs_and_arrays)
+        arr = (Request * max(n, 1))()
+        keep = []
+        for i, (r, arrays) in enumerate(reqs_and_arrays):
+            arr[i] = r
+            keep.append(arrays)
+        res = (Result * max(n, 1))()
+        rc = load_library().pll_server_replay(self._h, n, arr, res)
+        if rc:
+            raise PllError(rc, "pll_server_replay")
+        return [res[i].as_dict() for i in range(n)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().pll_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+            self._indexes.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,123 @@
+"""Autotuner for the many-graph build (one persistent launch).
+
+Tunes, per workload class, the launch parameters that do not change the
+labels: the batch size b (which sets the width of the per-batch distance-table
+tiles, 64*ceil(b/64) bytes per row, and of the candidate bit-vectors), the
+gang scale (how many workgroups each graph gets relative to its share of the
+estimated work, i.e. the work per wavefront) and the largest gang.  Every
+candidate is timed on the caller's graphs through the C ABI; a candidate
+whose label totals differ from the others is rejected (labels are invariant
+under all of these, so a difference would be a bug).  Results are cached in a
+JSON file keyed by a coarse signature of the workload.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import torch
+
+from . import DEFAULT_BATCH, FLAG_VALIDATE, build_labels_batched
+
+DEFAULT_CANDIDATES = [
+    dict(batch_size=b, gang_scale=s, max_gang=m)
+    for b in (256, 512, 1024)
+    for s, m in ((50, 16), (100, 16), (200, 16), (400, 16), (100, 4))
+]
+
+
+def cache_path() -> str:
+    return os.environ.get("PLL_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "pll_mi355x",
+                                                         "tune.json"))
+
+
+def workload_key(graphs) -> str:
+    """Coarse class of a list of (row_ptr, col, order) device tensors: graph
+    count, mean and largest vertex count and mean degree, each bucketed to a
+    power of two."""
+    ns = [int(g[2].numel()) for g in graphs]
+    nnz = [int(g[1].numel()) for g in graphs]
+    def b2(x):
+        return int(round(math.log2(max(x, 1))))
+    deg = sum(nnz) / max(sum(ns), 1)
+    return f"count{b2(len(ns))}_mean{b2(sum(ns) / max(len(ns), 1))}_max{b2(max(ns) if ns else 1)}_deg{b2(deg)}"
+
+
+def _load_cache() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save_cache(cache: dict) -> None:
+    p = cache_path()
+    try:
+        os.makedirs(os.path.dirname(p), exist_ok=True)
+        tmp = p + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, p)
+    except OSError:
+        pass
+
+
+def cached_config(graphs):
+    """The tuned launch parameters for this workload class, or None."""
+    ent = _load_cache().get(workload_key(graphs))
+    return dict(ent["best"]) if ent else None
+
+
+def tune_batched(graphs, candidates=None, reps: int = 2, flags: int = 0, save: bool = True, verbose: bool = False):
+    """Time every candidate on `graphs` (median of `reps` builds after one
+    warm-up build) and return {"best": params, "results": [...]}."""
+    candidates = candidates or DEFAULT_CANDIDATES
+    results, totals = [], None
+    for cand in candidates:
+        times = []
+        tot = None
+        for rep in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            idxs = build_labels_batched(graphs, flags=flags, **cand)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            t = [i.info()["total_entries"] for i in idxs]
+            for i in idxs:
+                i.free()
+            tot = t if tot is None else tot
+            if t != tot:
+                raise RuntimeError(f"label totals changed between runs of {cand}")
+            if rep > 0:
+                times.append(dt)
+        if totals is None:
+            totals = tot
+        elif tot != totals:
+            raise RuntimeError(f"candidate {cand} produced different labels")
+        times.sort()
+        med = times[len(times) // 2]
+        results.append(dict(params=cand, seconds=med))
+        if verbose:
+            print(f"tune {cand}: {med * 1e3:.1f} ms", flush=True)
+    best = min(results, key=lambda r: r["seconds"])
+    out = {"best": best["params"], "seconds": best["seconds"], "results": results}
+    if save:
+        cache = _load_cache()
+        cache[workload_key(graphs)] = out
+        _save_cache(cache)
+    return out
+
+
+def build_tuned(graphs, flags: int = FLAG_VALIDATE, tune_if_missing: bool = False, **kw):
+    """build_labels_batched with the cached parameters of this workload class
+    (tuning first when asked and nothing is cached)."""
+    cfg = cached_config(graphs)
+    if cfg is None and tune_if_missing:
+        cfg = tune_batched(graphs)["best"]
+    if cfg is None:
+        cfg = dict(batch_size=DEFAULT_BATCH)
+    cfg.update(kw)
+    return build_labels_batched(graphs, flags=flags, **cfg)

@@ -1,0 +1,475 @@
+// Serving loop: resident label indexes answer streams of query requests with
+// continuous batching, and labeling jobs are admitted by free device memory.
+//
+// A scheduler thread owns a pool of slots (one stream, pinned staging and
+// device buffers each).  Whenever a slot is free it packs the queued query
+// requests of one index, oldest first, into one device batch (a request
+// larger than the batch is carried by several batches), launches the
+// merge-join query kernel and copies results back on the slot's stream.
+// Completed batches are scattered to their requests.  Slots run
+// concurrently, so batches overlap on the device with each other and with
+// label builds, which a second thread runs on their own stream once
+// hipMemGetInfo reports enough free memory for the job.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "pll_internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Req {
+    uint64_t id = 0;
+    pll_request r{};
+    double t_arrival = 0, t_admit = -1, t_done = 0;
+    int status = PLL_OK;
+    uint64_t next = 0;       // first pair not yet given to a batch
+    uint64_t remaining = 0;  // pairs not yet answered
+    uint32_t batch_requests = 0;
+    uint32_t new_index = 0;
+};
+
+struct Member {
+    Req* req;
+    uint64_t src;    // first pair of the request carried by this batch
+    uint64_t dst;    // position in the batch
+    uint64_t count;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    uint32_t *h_u = nullptr, *h_v = nullptr, *h_out = nullptr;
+    uint32_t *d_u = nullptr, *d_v = nullptr, *d_out = nullptr;
+    uint64_t cap = 0;
+    bool busy = false;
+    std::vector<Member> members;
+};
+
+struct IndexEntry {
+    pll_index* idx = nullptr;
+    bool owned = false;
+};
+
+uint64_t build_bytes_estimate(uint32_t n, uint64_t nnz, uint32_t b) {
+    const uint64_t W = (b + 63) / 64;
+    const uint64_t work = n * (64 * W)                 // distance table
+                          + n * 8 * W * 4              // C, msgs, two active deltas
+                          + n * 4ull * PLL_SHARDS * 3  // sharded queues
+                          + n * 64ull                  // per-vertex arrays
+                          + 16 * nnz;                  // CSR copies
+    const uint64_t labels = 3 * (16ull * n + 4 * nnz * 8) * 4;  // label arena, generous
+    return work + labels;
+}
+
+}  // namespace
+
+struct pll_server {
+    int device = 0;
+    pll_server_opts opts{};
+    Clock::time_point t0;
+    std::mutex mu;
+    std::condition_variable cv, done_cv;
+    std::deque<Req*> queries;
+    std::deque<Req*> builds;
+    std::vector<Req*> completed;  // not yet polled
+    std::map<uint64_t, Req*> all;
+    std::map<uint32_t, IndexEntry> indexes;
+    uint32_t next_index = 1;
+    uint64_t next_id = 1;
+    uint64_t outstanding = 0;
+    bool stop = false;
+    std::vector<Slot> slots;
+    hipStream_t build_stream = nullptr;
+    std::thread sched, builder;
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+
+    void finish(Req* q, int status) {  // caller holds mu
+        q->status = status;
+        q->t_done = now();
+        completed.push_back(q);
+        --outstanding;
+        done_cv.notify_all();
+    }
+
+    // scheduler: retire finished batches, then fill free slots
+    void run_sched() {
+        (void)hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            bool any_busy = false;
+            for (Slot& s : slots) {
+                if (!s.busy) continue;
+                if (hipEventQuery(s.done) != hipSuccess) {
+                    any_busy = true;
+                    continue;
+                }
+                for (const Member& m : s.members) {
+                    std::memcpy(m.req->r.h_out + m.src, s.h_out + m.dst, sizeof(uint32_t) * m.count);
+                    m.req->remaining -= m.count;
+                    if (m.req->remaining == 0) finish(m.req, PLL_OK);
+                }
+                s.members.clear();
+                s.busy = false;
+            }
+            for (Slot& s : slots) {
+                if (s.busy || queries.empty()) continue;
+                fill_slot(s);
+                any_busy = any_busy || s.busy;
+            }
+            if (stop && queries.empty() && !any_busy) break;
+            if (any_busy)
+                cv.wait_for(lk, std::chrono::microseconds(20));
+            else
+                cv.wait_for(lk, std::chrono::milliseconds(2));
+        }
+    }
+
+    // pack queued requests of the head's index into slot s (mu held)
+    void fill_slot(Slot& s) {
+        Req* head = queries.front();
+        auto it = indexes.find(head->r.index_id);
+        if (it == indexes.end()) {
+            queries.pop_front();
+            finish(head, PLL_EINVAL);
+            return;
+        }
+        const uint32_t index_id = head->r.index_id;
+        const pll_index* idx = it->second.idx;
+        uint64_t used = 0;
+        uint32_t nreq = 0;
+        for (auto q = queries.begin(); q != queries.end() && used < s.cap;) {
+            Req* r = *q;
+            if (r->r.index_id != index_id) {
+                ++q;
+                continue;
+            }
+            const uint64_t take = std::min<uint64_t>(r->r.count - r->next, s.cap - used);
+            std::memcpy(s.h_u + used, r->r.h_u + r->next, sizeof(uint32_t) * take);
+            std::memcpy(s.h_v + used, r->r.h_v + r->next, sizeof(uint32_t) * take);
+            s.members.push_back(Member{r, r->next, used, take});
+            if (r->t_admit < 0) r->t_admit = now();
+            r->next += take;
+            used += take;
+            ++nreq;
+            if (r->next == r->r.count)
+                q = queries.erase(q);
+            else
+                break;  // the batch is full
+        }
+        for (const Member& m : s.members)
+            if (m.src == 0) m.req->batch_requests = nreq;
+        bool ok = hipMemcpyAsync(s.d_u, s.h_u, sizeof(uint32_t) * used, hipMemcpyHostToDevice, s.stream) == hipSuccess &&
+                  hipMemcpyAsync(s.d_v, s.h_v, sizeof(uint32_t) * used, hipMemcpyHostToDevice, s.stream) == hipSuccess &&
+                  pll_query_launch(idx, used, s.d_u, s.d_v, s.d_out, s.stream) == PLL_OK &&
+                  hipMemcpyAsync(s.h_out, s.d_out, sizeof(uint32_t) * used, hipMemcpyDeviceToHost, s.stream) == hipSuccess &&
+                  hipEventRecord(s.done, s.stream) == hipSuccess;
+        if (!ok) {
+            for (const Member& m : s.members) {
+                m.req->remaining -= m.count;
+                if (m.req->remaining == 0) finish(m.req, PLL_EDEVICE);
+            }
+            s.members.clear();
+            return;
+        }
+        s.busy = true;
+    }
+
+    // build worker: admit the oldest labeling job once memory allows
+    void run_builder() {
+        (void)hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            if (builds.empty()) {
+                if (stop) break;
+                cv.wait_for(lk, std::chrono::milliseconds(2));
+                continue;
+            }
+            Req* q = builds.front();
+            if (stop) {  // shutting down: jobs not started yet are dropped
+                builds.pop_front();
+                finish(q, PLL_ENOMEM);
+                continue;
+            }
+            const uint32_t b = opts.build_batch_size ? opts.build_batch_size : PLL_BMAX;
+            const uint64_t need = build_bytes_estimate(q->r.n, q->r.nnz, b) + opts.mem_reserve;
+            size_t free_b = 0, total_b = 0;
+            lk.unlock();
+            const bool mem_ok = hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b >= need;
+            lk.lock();
+            if (!mem_ok) {
+                if (need > total_b && total_b) {  // can never fit
+                    builds.pop_front();
+                    finish(q, PLL_ENOMEM);
+                } else {
+                    cv.wait_for(lk, std::chrono::milliseconds(1));
+                }
+                continue;
+            }
+            builds.pop_front();
+            q->t_admit = now();
+            lk.unlock();
+            pll_index* idx = nullptr;
+            int rc = build_from_host(q->r, b, &idx);
+            lk.lock();
+            if (rc == PLL_OK) {
+                const uint32_t id = next_index++;
+                indexes[id] = IndexEntry{idx, true};
+                q->new_index = id;
+            }
+            finish(q, rc);
+        }
+    }
+
+    int build_from_host(const pll_request& r, uint32_t b, pll_index** out) {
+        const uint64_t n = r.n, nnz = r.nnz;
+        if (n && (!r.h_row_ptr || !r.h_order || (nnz && !r.h_col))) return PLL_EINVAL;
+        uint64_t* d_rp = nullptr;
+        uint32_t *d_col = nullptr, *d_order = nullptr;
+        int rc = PLL_OK;
+        if (hipMalloc((void**)&d_rp, 8 * (n + 1)) != hipSuccess ||
+            hipMalloc((void**)&d_col, 4 * std::max<uint64_t>(nnz, 1)) != hipSuccess ||
+            hipMalloc((void**)&d_order, 4 * std::max<uint64_t>(n, 1)) != hipSuccess) {
+            rc = PLL_ENOMEM;
+        } else if ((n && (hipMemcpyAsync(d_rp, r.h_row_ptr, 8 * (n + 1), hipMemcpyHostToDevice, build_stream) != hipSuccess ||
+                          hipMemcpyAsync(d_order, r.h_order, 4 * n, hipMemcpyHostToDevice, build_stream) != hipSuccess)) ||
+                   (nnz && hipMemcpyAsync(d_col, r.h_col, 4 * nnz, hipMemcpyHostToDevice, build_stream) != hipSuccess)) {
+            rc = PLL_EDEVICE;
+        } else {
+            pll_build_opts o{};
+            o.batch_size = b;
+            o.flags = PLL_FLAG_VALIDATE;
+            rc = pll_build_one(r.n, r.nnz, d_rp, d_col, d_order, &o, build_stream, out);
+        }
+        (void)hipStreamSynchronize(build_stream);
+        if (d_rp) (void)hipFree(d_rp);
+        if (d_col) (void)hipFree(d_col);
+        if (d_order) (void)hipFree(d_order);
+        return rc;
+    }
+};
+
+namespace {
+
+void destroy_server(pll_server* s) {
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv.notify_all();
+    if (s->sched.joinable()) s->sched.join();
+    if (s->builder.joinable()) s->builder.join();
+    (void)hipSetDevice(s->device);
+    for (Slot& sl : s->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.h_u) (void)hipHostFree(sl.h_u);
+        if (sl.h_v) (void)hipHostFree(sl.h_v);
+        if (sl.h_out) (void)hipHostFree(sl.h_out);
+        if (sl.d_u) (void)hipFree(sl.d_u);
+        if (sl.d_v) (void)hipFree(sl.d_v);
+        if (sl.d_out) (void)hipFree(sl.d_out);
+    }
+    if (s->build_stream) (void)hipStreamDestroy(s->build_stream);
+    for (auto& kv : s->indexes)
+        if (kv.second.owned) pll_index_free(kv.second.idx);
+    for (auto& kv : s->all) delete kv.second;
+    delete s;
+}
+
+int submit_locked(pll_server* s, const pll_request* req, double arrival, uint64_t* id) {
+    if (req->kind == PLL_REQ_QUERY) {
+        if (req->count && (!req->h_u || !req->h_v || !req->h_out)) return PLL_EINVAL;
+    } else if (req->kind != PLL_REQ_BUILD) {
+        return PLL_EINVAL;
+    }
+    Req* q = new (std::nothrow) Req{};
+    if (!q) return PLL_ENOMEM;
+    q->id = s->next_id++;
+    q->r = *req;
+    q->t_arrival = arrival;
+    q->remaining = req->count;
+    s->all[q->id] = q;
+    ++s->outstanding;
+    if (req->kind == PLL_REQ_QUERY) {
+        if (req->count == 0) {
+            q->t_admit = s->now();
+            s->finish(q, PLL_OK);
+        } else {
+            s->queries.push_back(q);
+        }
+    } else {
+        s->builds.push_back(q);
+    }
+    if (id) *id = q->id;
+    return PLL_OK;
+}
+
+void fill_result(const Req* q, pll_result* r) {
+    r->id = q->id;
+    r->status = q->status;
+    r->kind = q->r.kind;
+    r->index_id = q->r.kind == PLL_REQ_BUILD ? q->new_index : q->r.index_id;
+    r->batch_requests = q->batch_requests;
+    r->t_arrival = q->t_arrival;
+    r->t_admit = q->t_admit;
+    r->t_done = q->t_done;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pll_server_create(const pll_server_opts* opts, pll_server** out) {
+    if (!out) return PLL_EINVAL;
+    *out = nullptr;
+    pll_server_opts o{};
+    if (opts) o = *opts;
+    for (uint32_t r : o.reserved)
+        if (r) return PLL_EINVAL;
+    const uint32_t nslots = o.slots ? o.slots : 4;
+    if (nslots > 16) return PLL_EINVAL;
+    const uint64_t cap = o.max_batch_pairs ? o.max_batch_pairs : (1ull << 20);
+    if (o.mem_reserve == 0) o.mem_reserve = 1ull << 30;
+    pll_server* s = new (std::nothrow) pll_server{};
+    if (!s) return PLL_ENOMEM;
+    s->opts = o;
+    s->t0 = Clock::now();
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return PLL_EDEVICE;
+    }
+    s->slots.resize(nslots);
+    bool ok = hipStreamCreateWithFlags(&s->build_stream, hipStreamNonBlocking) == hipSuccess;
+    for (Slot& sl : s->slots) {
+        sl.cap = cap;
+        ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
+             hipHostMalloc((void**)&sl.h_u, 4 * cap, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void**)&sl.h_v, 4 * cap, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void**)&sl.h_out, 4 * cap, hipHostMallocDefault) == hipSuccess &&
+             hipMalloc((void**)&sl.d_u, 4 * cap) == hipSuccess && hipMalloc((void**)&sl.d_v, 4 * cap) == hipSuccess &&
+             hipMalloc((void**)&sl.d_out, 4 * cap) == hipSuccess;
+    }
+    if (!ok) {
+        destroy_server(s);
+        return PLL_ENOMEM;
+    }
+    try {
+        s->sched = std::thread([s] { s->run_sched(); });
+        s->builder = std::thread([s] { s->run_builder(); });
+    } catch (...) {
+        destroy_server(s);
+        return PLL_ENOMEM;
+    }
+    *out = s;
+    return PLL_OK;
+}
+
+int pll_server_add_index(pll_server* s, pll_index* idx, int take_ownership, uint32_t* index_id) {
+    if (!s || !idx || !index_id) return PLL_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    const uint32_t id = s->next_index++;
+    s->indexes[id] = IndexEntry{idx, take_ownership != 0};
+    *index_id = id;
+    return PLL_OK;
+}
+
+int pll_server_index(pll_server* s, uint32_t index_id, pll_index** idx) {
+    if (!s || !idx) return PLL_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->indexes.find(index_id);
+    if (it == s->indexes.end()) return PLL_EINVAL;
+    *idx = it->second.idx;
+    return PLL_OK;
+}
+
+int pll_server_submit(pll_server* s, const pll_request* req, uint64_t* id) {
+    if (!s || !req) return PLL_EINVAL;
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        rc = submit_locked(s, req, s->now(), id);
+    }
+    s->cv.notify_all();
+    return rc;
+}
+
+int pll_server_poll(pll_server* s, pll_result* out, uint32_t max, uint32_t* got, int wait) {
+    if (!s || !got || (max && !out)) return PLL_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (wait)
+        s->done_cv.wait(lk, [s] { return !s->completed.empty() || s->outstanding == 0; });
+    uint32_t k = 0;
+    while (k < max && !s->completed.empty()) {
+        Req* q = s->completed.front();
+        s->completed.erase(s->completed.begin());
+        fill_result(q, &out[k++]);
+        s->all.erase(q->id);
+        delete q;
+    }
+    *got = k;
+    return PLL_OK;
+}
+
+int pll_server_replay(pll_server* s, uint64_t count, const pll_request* reqs, pll_result* results) {
+    if (!s || (count && (!reqs || !results))) return PLL_EINVAL;
+    std::vector<uint64_t> ids(count, 0);
+    const double start = s->now();
+    for (uint64_t i = 0; i < count; ++i) {
+        const double due = start + reqs[i].at;
+        for (;;) {  // open loop: wait for the arrival time, never for earlier requests
+            const double t = s->now();
+            if (t >= due) break;
+            if (due - t > 2e-4)
+                std::this_thread::sleep_for(std::chrono::duration<double>(due - t - 1e-4));
+        }
+        int rc;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            rc = submit_locked(s, &reqs[i], due, &ids[i]);
+        }
+        s->cv.notify_all();
+        if (rc != PLL_OK) return rc;
+    }
+    // collect every replayed request
+    std::map<uint64_t, uint64_t> pos;
+    for (uint64_t i = 0; i < count; ++i) pos[ids[i]] = i;
+    uint64_t left = count;
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (left) {
+        s->done_cv.wait(lk, [s] { return !s->completed.empty(); });
+        for (auto it = s->completed.begin(); it != s->completed.end();) {
+            Req* q = *it;
+            auto p = pos.find(q->id);
+            if (p == pos.end()) {
+                ++it;
+                continue;
+            }
+            fill_result(q, &results[p->second]);
+            it = s->completed.erase(it);
+            s->all.erase(q->id);
+            delete q;
+            --left;
+        }
+    }
+    return PLL_OK;
+}
+
+void pll_server_destroy(pll_server* s) {
+    if (s) destroy_server(s);
+}
+
+}  // extern "C"

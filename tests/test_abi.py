@@ -48,7 +48,8 @@ def test_struct_layouts_match_header():
 #include <stdio.h>
 #include "pll.h"
 int main(void) {
-  printf("%zu %zu %zu\n", sizeof(pll_build_opts), sizeof(pll_index_info), sizeof(pll_graph_desc));
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(pll_build_opts), sizeof(pll_index_info), sizeof(pll_graph_desc),
+         sizeof(pll_server_opts), sizeof(pll_request), sizeof(pll_result));
   return 0;
 }
 '''
@@ -62,7 +63,8 @@ int main(void) {
     if r.returncode != 0:
         pytest.skip("cannot compile the layout probe: " + r.stderr[:200])
     sizes = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
-    assert sizes == [ctypes.sizeof(pll.BuildOpts), ctypes.sizeof(pll.IndexInfo), ctypes.sizeof(pll.GraphDesc)]
+    assert sizes == [ctypes.sizeof(pll.BuildOpts), ctypes.sizeof(pll.IndexInfo), ctypes.sizeof(pll.GraphDesc),
+                     ctypes.sizeof(pll.ServerOpts), ctypes.sizeof(pll.Request), ctypes.sizeof(pll.Result)]
 
 
 def test_binding_rejects_host_tensors():

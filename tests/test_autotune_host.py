@@ -1,0 +1,24 @@
+"""Host-side parts of the autotuner (no GPU): workload keys and the cache."""
+import torch
+
+from paper_1906_12018_amd import autotune
+
+
+def fake(n, nnz):
+    return (torch.zeros(n + 1, dtype=torch.int64), torch.zeros(nnz, dtype=torch.int32), torch.zeros(n, dtype=torch.int32))
+
+
+def test_workload_key_buckets():
+    a = autotune.workload_key([fake(1000, 8000), fake(3000, 24000)])
+    b = autotune.workload_key([fake(1100, 8800), fake(2900, 23200)])
+    c = autotune.workload_key([fake(100000, 800000)])
+    assert a == b and a != c
+
+
+def test_cache_roundtrip(tmp_path, monkeypatch):
+    monkeypatch.setenv("PLL_TUNE_CACHE", str(tmp_path / "t.json"))
+    gs = [fake(500, 2000)]
+    assert autotune.cached_config(gs) is None
+    cache = {autotune.workload_key(gs): {"best": {"batch_size": 512, "gang_scale": 100, "max_gang": 8}}}
+    autotune._save_cache(cache)
+    assert autotune.cached_config(gs) == {"batch_size": 512, "gang_scale": 100, "max_gang": 8}

@@ -104,3 +104,18 @@ def test_gang_sizes_do_not_change_labels(gang_scale, max_gang):
         want = oracle.pll_labels(g, o)
         assert_labels_equal(idx, want, o)
         assert idx.info()["candidates"] + g.n == want.counters["checks"]
+
+
+def test_autotuner_picks_a_candidate_and_caches(tmp_path, monkeypatch):
+    from paper_1906_12018_amd import autotune
+    monkeypatch.setenv("PLL_TUNE_CACHE", str(tmp_path / "tune.json"))
+    gs = [synth.ba_graph(n, 3, 40 + n) for n in (900, 1500, 2500)]
+    orders = [synth.degree_order(g) for g in gs]
+    dev = [to_dev(g, o) for g, o in zip(gs, orders)]
+    cands = [dict(batch_size=256, gang_scale=100, max_gang=16), dict(batch_size=1024, gang_scale=200, max_gang=4)]
+    res = autotune.tune_batched(dev, candidates=cands, reps=1)
+    assert res["best"] in cands and len(res["results"]) == 2
+    assert autotune.cached_config(dev) == res["best"]
+    idxs = autotune.build_tuned(dev)
+    for g, o, idx in zip(gs, orders, idxs):
+        assert_labels_equal(idx, oracle.pll_labels(g, o), o)

@@ -1,0 +1,108 @@
+"""GPU tests of the serving loop (pll_server_*): continuous batching over
+resident indexes, labeling jobs admitted by free memory, and every result
+the same alone and in the mix (integer distances: tolerance 0)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1906_12018_amd as pll
+import synth
+from gpu_util import assert_labels_equal, build
+
+pytestmark = pytest.mark.gpu
+
+
+def sizes(count, seed, hi=20000):
+    x = synth.uniform01(synth.splitmix64(seed, 0, count))
+    return np.maximum(1, np.round(np.exp(x * np.log(hi)))).astype(np.int64)
+
+
+def make_queries(g, count, seed):
+    out = []
+    for i, s in enumerate(sizes(count, seed)):
+        u, v = synth.query_pairs(g.n, int(s), seed=seed * 1000 + i)
+        out.append((u, v))
+    return out
+
+
+@pytest.fixture(scope="module")
+def two_indexes():
+    ga, gb = synth.ba_graph(5000, 5, 1), synth.ba_graph(2000, 4, 1)
+    oa, ob = synth.degree_order(ga), synth.degree_order(gb)
+    return (ga, oa, oracle.pll_labels(ga, oa)), (gb, ob, oracle.pll_labels(gb, ob))
+
+
+def test_alone_equals_mix(two_indexes):
+    (ga, oa, la), (gb, ob, lb) = two_indexes
+    srv = pll.Server(slots=4, max_batch_pairs=1 << 16)
+    ia = srv.add_index(build(ga, oa))
+    ib = srv.add_index(build(gb, ob))
+    qa, qb = make_queries(ga, 40, 7), make_queries(gb, 40, 8)
+    work = [(ia, u, v) for u, v in qa] + [(ib, u, v) for u, v in qb]
+    order = np.argsort(synth.splitmix64(9, 0, len(work)), kind="stable")
+    work = [work[i] for i in order]
+    # alone: one request at a time on an idle server
+    alone = []
+    for iid, u, v in work:
+        out = np.zeros(len(u), dtype=np.uint32)
+        rid = srv.submit(pll.Server.query_request(iid, u, v, out))
+        assert srv.wait(rid)["status"] == pll.PLL_OK
+        alone.append(out)
+    # in the mix: open-loop arrivals every 50 us, with two labeling jobs
+    g1, g2 = synth.ba_graph(3000, 3, 77), synth.ba_graph(1200, 6, 78)
+    o1, o2 = synth.degree_order(g1), synth.degree_order(g2)
+    mix, outs = [], []
+    for k, (iid, u, v) in enumerate(work):
+        out = np.zeros(len(u), dtype=np.uint32)
+        outs.append(out)
+        mix.append(pll.Server.query_request(iid, u, v, out, at=5e-5 * k))
+        if k in (10, 50):
+            g, o = (g1, o1) if k == 10 else (g2, o2)
+            mix.append(pll.Server.build_request(g.row_ptr, g.col, o, at=5e-5 * k))
+    res = srv.replay(mix)
+    assert all(r["status"] == pll.PLL_OK for r in res)
+    for a, b in zip(alone, outs):
+        assert np.array_equal(a, b)
+    # and against the oracle
+    for (iid, u, v), out in zip(work, outs):
+        lab = la if iid == ia else lb
+        assert np.array_equal(out, oracle.query(lab, u, v))
+    # requests were packed together while others were on the device
+    q_res = [r for r in res if r["kind"] == pll.REQ_QUERY]
+    assert max(r["batch_requests"] for r in q_res) > 1
+    assert all(r["t_done"] >= r["t_admit"] >= r["t_arrival"] - 1e-6 for r in q_res)
+    # the built indexes are resident and exact
+    b_res = [r for r in res if r["kind"] == pll.REQ_BUILD]
+    assert len(b_res) == 2
+    for r, (g, o) in zip(b_res, [(g1, o1), (g2, o2)]):
+        idx = srv.index(r["index_id"])
+        assert_labels_equal(idx, oracle.pll_labels(g, o), o)
+        u, v = synth.query_pairs(g.n, 3000, seed=3)
+        out = np.zeros(3000, dtype=np.uint32)
+        rid = srv.submit(pll.Server.query_request(r["index_id"], u, v, out))
+        assert srv.wait(rid)["status"] == pll.PLL_OK
+        assert np.array_equal(out, oracle.query(oracle.pll_labels(g, o), u, v))
+    srv.close()
+
+
+def test_request_larger_than_a_batch(two_indexes):
+    (ga, oa, la), _ = two_indexes
+    srv = pll.Server(slots=2, max_batch_pairs=1000)
+    iid = srv.add_index(build(ga, oa), take_ownership=True)
+    u, v = synth.query_pairs(ga.n, 7777, seed=4)
+    out = np.zeros(len(u), dtype=np.uint32)
+    rid = srv.submit(pll.Server.query_request(iid, u, v, out))
+    assert srv.wait(rid)["status"] == pll.PLL_OK
+    assert np.array_equal(out, oracle.query(la, u, v))
+    srv.close()
+
+
+def test_unknown_index_and_unfittable_build():
+    srv = pll.Server(slots=1, mem_reserve=1 << 60)
+    out = np.zeros(4, dtype=np.uint32)
+    rid = srv.submit(pll.Server.query_request(99, np.zeros(4), np.zeros(4), out))
+    assert srv.wait(rid)["status"] == pll.PLL_EINVAL
+    g = synth.ba_graph(300, 2, 1)
+    rid = srv.submit(pll.Server.build_request(g.row_ptr, g.col, synth.degree_order(g)))
+    assert srv.wait(rid)["status"] == pll.PLL_ENOMEM
+    srv.close()

@@ -62,6 +62,101 @@ def cpu_baseline(g, order, total_entries):
                       f"1 run, {dt:.2f} s", "seconds": dt}
 
 
+def serve_mode(args):
+    """Serving workload: R-MAT scale-20 index resident; open-loop Poisson
+    arrivals of query requests with sizes log-uniform in [1, 65536] pairs,
+    a fraction of arrivals being labeling jobs for Barabasi-Albert graphs
+    (n log-uniform in [1000, 50000], m in {2..8}).  The offered rate is a
+    fraction of the saturation rate measured with one burst of the same
+    query requests.  Latency = completion - arrival, per request."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1906_12018_amd as pll
+
+    dev = torch.device("cuda:0")
+    g = synth.rmat_graph(args.serve_scale)
+    order = synth.degree_order(g)
+    rp, cl = pll.graph_to_device(g, dev)
+    od = torch.from_numpy(order.view(np.int32)).to(dev)
+    idx = pll.build_labels(rp, cl, od, flags=0)
+    torch.cuda.synchronize()
+    N = args.serve_requests
+    x = synth.splitmix64(4, 0, 4 * N)
+    sizes = np.maximum(1, np.round(np.exp(synth.uniform01(x[0::4]) * np.log(65536)))).astype(np.int64)
+    is_build = synth.uniform01(x[1::4]) < args.serve_build_frac
+    pool = 1 << 24
+    pu, pv = synth.query_pairs(g.n, pool, seed=5)
+    pout = np.zeros(pool, dtype=np.uint32)
+    starts = synth.bounded(x[2::4], pool - 65536).astype(np.int64)
+    # labeling jobs (host CSR), generated once and reused by every load level
+    nb = int(is_build.sum())
+    bx = synth.splitmix64(6, 0, 2 * max(nb, 1))
+    jobs = []
+    for i in range(nb):
+        n = int(round(np.exp(np.log(1000) + synth.uniform01(bx[2 * i:2 * i + 1])[0] * (np.log(50000) - np.log(1000)))))
+        m = 2 + int(synth.bounded(bx[2 * i + 1:2 * i + 2], 7)[0])
+        bg = synth.ba_graph(n, m, 5000 + i)
+        jobs.append((bg.row_ptr, bg.col, synth.degree_order(bg)))
+    srv = pll.Server(slots=args.serve_slots)
+    iid = srv.add_index(idx, take_ownership=False)
+
+    def requests(at):
+        reqs, bi = [], 0
+        for i in range(N):
+            if is_build[i]:
+                rp_, cl_, od_ = jobs[bi]
+                bi += 1
+                reqs.append(pll.Server.build_request(rp_, cl_, od_, at=at[i]))
+            else:
+                a, c = int(starts[i]), int(sizes[i])
+                reqs.append(pll.Server.query_request(iid, pu[a:a + c], pv[a:a + c], pout[a:a + c], at=at[i]))
+        return reqs
+
+    def summarize(res, wall):
+        q = [r for r in res if r["kind"] == pll.REQ_QUERY]
+        b = [r for r in res if r["kind"] == pll.REQ_BUILD]
+        lat = np.array([r["t_done"] - r["t_arrival"] for r in q]) * 1e3
+        pairs = int(sum(sizes[i] for i in range(N) if not is_build[i]))
+        out = {"query_requests": len(q), "pairs": pairs, "wall_s": wall, "pairs_per_s": pairs / wall,
+               "requests_per_s": len(q) / wall, "p50_ms": float(np.percentile(lat, 50)),
+               "p99_ms": float(np.percentile(lat, 99)), "mean_batch_requests":
+               float(np.mean([r["batch_requests"] for r in q if r["batch_requests"]]))}
+        if b:
+            bl = np.array([r["t_done"] - r["t_arrival"] for r in b]) * 1e3
+            out.update({"builds": len(b), "build_p50_ms": float(np.percentile(bl, 50)),
+                        "build_p99_ms": float(np.percentile(bl, 99)),
+                        "build_errors": int(sum(r["status"] != 0 for r in b))})
+        return out
+
+    # saturation: every query request at t = 0
+    sat_mask = ~is_build
+    burst = [r for r, keep in zip(requests(np.zeros(N)), sat_mask) if keep]
+    t0 = time.perf_counter()
+    res = srv.replay(burst)
+    wall = max(r["t_done"] for r in res) - min(r["t_arrival"] for r in res)
+    sat = len(burst) / wall
+    levels = {}
+    for frac in args.serve_loads:
+        rate = frac * sat
+        gaps = -np.log(1.0 - synth.uniform01(synth.splitmix64(7, 0, N))) / rate
+        at = np.cumsum(gaps) - gaps[0]
+        t0 = time.perf_counter()
+        res = srv.replay(requests(at))
+        wall = max(r["t_done"] for r in res) - min(r["t_arrival"] for r in res)
+        levels[f"{int(round(frac * 100))}%"] = summarize(res, wall)
+        levels[f"{int(round(frac * 100))}%"]["offered_requests_per_s"] = rate
+    srv.close()
+    info = idx.info()
+    idx.free()
+    line = {"mode": "serve", "workload": f"rmat{args.serve_scale} resident, {N} requests, "
+            f"{args.serve_build_frac:.0%} labeling jobs", "index_entries": info["total_entries"],
+            "label_bytes": info["label_bytes"], "saturation_requests_per_s": sat,
+            "saturation_pairs_per_s": int(sizes[sat_mask].sum()) / (len(burst) / sat), "levels": levels,
+            "slots": args.serve_slots, "data": "synthetic"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,11 +165,21 @@ def main():
     ap.add_argument("--workload", default="rmat16", choices=sorted(WORKLOADS))
     ap.add_argument("--batch-size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="build", choices=["build", "serve"])
+    ap.add_argument("--serve-scale", type=int, default=20)
+    ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--serve-build-frac", type=float, default=0.01)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 0.95])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
         sys.exit(2)
+
+    if args.mode == "serve":
+        serve_mode(args)
+        return
 
     import numpy as np
     import torch

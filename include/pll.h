@@ -143,9 +143,13 @@ int pll_build_labels(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const 
 
 /*
  * Exact distances for `count` pairs (Section 2.1, the 2-hop query).
- *   d_u, d_v    uint32[count] vertex ids; an id >= n is undefined behaviour
+ *   d_u, d_v    uint32[count] vertex ids; an id >= n has no label, so its
+ *               pairs answer PLL_DIST_INF
  *   d_out       uint32[count]; PLL_DIST_INF when v is unreachable from u
  * Asynchronous on `stream`; the index must outlive the enqueued work.
+ * Lanes per pair follow opts->query_lanes of the build: 1 runs a scalar
+ * two-pointer merge per lane; G in {4..64} lets G lanes merge the two lists
+ * in windows of 4G entries; 0 picks G from the mean label length.
  */
 int pll_query(const pll_index* idx, uint64_t count, const uint32_t* d_u, const uint32_t* d_v, uint32_t* d_out,
               hipStream_t stream);

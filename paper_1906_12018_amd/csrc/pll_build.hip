@@ -769,7 +769,8 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     uint64_t total = 0;
     TRY_HIP(hipMemcpyAsync(&total, d_off + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     TRY_HIP(hipStreamSynchronize(s));
-    uint32_t* d_ent = M.get<uint32_t>(total ? total : 1);
+    // whole 4-entry chunks: the query kernel reads labels in aligned 16-byte loads
+    uint32_t* d_ent = M.get<uint32_t>(std::max<uint64_t>((total + 3) & ~3ull, 4));
     uint32_t* d_order = M.get<uint32_t>(n);
     if (M.err != hipSuccess) return status_of(M.err);
     k_final_copy<<<std::min<uint32_t>(blocks_for_waves(n), 1024), kBlock, 0, s>>>(n, rank, A.loff, A.llen, A.arena,
@@ -844,7 +845,7 @@ int pll_build_one(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uin
     if (n == 0) {
         DevAllocs M;
         idx->d_off = M.get<uint64_t>(1);
-        idx->d_ent = M.get<uint32_t>(1);
+        idx->d_ent = M.get<uint32_t>(4);
         idx->d_order = M.get<uint32_t>(1);
         if (M.err != hipSuccess) {
             rc = status_of(M.err);

@@ -315,13 +315,15 @@ __global__ void __launch_bounds__(kMultiBlock) k_multi_build(const GraphJob* __r
             wg_scan(A.touch_stamp, n, J.out_off, s_wsum, &s_carry);
             if (tid == 0) {
                 const unsigned long long total = J.out_off[n];
-                const unsigned long long base = atomicAdd(&ctl->out_top, total);
+                // regions start on 16-byte boundaries and span whole 4-entry
+                // chunks: the query kernel reads labels in aligned 16-byte loads
+                const unsigned long long base = atomicAdd(&ctl->out_top, (total + 3) & ~3ull);
                 gc->out_base = base;
                 results[g].out_base = base;
                 results[g].total = total;
                 results[g].batches = batches;
                 results[g].rounds = rounds;
-                if (base + total > ctl->out_cap) atomicOr(&ctr->error, PLL_ERR_ARENA);
+                if (base + ((total + 3) & ~3ull) > ctl->out_cap) atomicOr(&ctr->error, PLL_ERR_ARENA);
             }
         }
         if (gang_sync(gc, G, k, ctr, spin_limit, &s_flag)) continue;
@@ -447,7 +449,7 @@ std::vector<uint32_t> gang_sizes(uint32_t count, const pll_graph_desc* graphs, u
 }
 
 int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint32_t flags, uint32_t scale_pct,
-                  uint32_t max_gang, uint64_t arena_total, uint64_t out_cap, hipStream_t caller, pll_index** outs,
+                  uint32_t max_gang, uint32_t query_lanes, uint64_t arena_total, uint64_t out_cap, hipStream_t caller, pll_index** outs,
                   bool* retry) {
     *retry = false;
     // the work runs on a private stream (a capturable one; the caller's may be
@@ -689,6 +691,7 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
         idx->d_ent = (uint32_t*)store->ptr + R.out_base;
         idx->d_order = orders[g];
         idx->store = store;
+        idx->query_lanes = query_lanes;
         pll_index_info& I = idx->info;
         I.n = graphs[g].n;
         I.batch_size = b;
@@ -728,6 +731,8 @@ int pll_build_multi(uint32_t count, const pll_graph_desc* graphs, const pll_buil
     if ((o.flags & PLL_FLAG_RELAXED) && !(o.flags & PLL_FLAG_RECHECK)) return PLL_EINVAL;
     if (o.flags & ~(PLL_FLAG_VALIDATE | PLL_FLAG_RECHECK | PLL_FLAG_RELAXED | PLL_FLAG_PROFILE)) return PLL_EINVAL;
     if (o.max_gang > kMaxGang) return PLL_EINVAL;
+    const uint32_t ql = o.query_lanes;
+    if (!(ql == 0 || ql == 1 || ql == 4 || ql == 8 || ql == 16 || ql == 32 || ql == 64)) return PLL_EINVAL;
     uint64_t sum_est = 0;
     for (uint32_t g = 0; g < count; ++g) {
         const pll_graph_desc& d = graphs[g];
@@ -744,7 +749,7 @@ int pll_build_multi(uint32_t count, const pll_graph_desc* graphs, const pll_buil
     int rc = PLL_OK;
     for (uint32_t attempt = 1; attempt <= 6; ++attempt) {
         bool retry = false;
-        rc = multi_attempt(count, graphs, b, o.flags, scale, o.max_gang, arena, out_cap, stream, outs, &retry);
+        rc = multi_attempt(count, graphs, b, o.flags, scale, o.max_gang, o.query_lanes, arena, out_cap, stream, outs, &retry);
         if (rc == PLL_OK) {
             const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             for (uint32_t g = 0; g < count; ++g) {

@@ -1,22 +1,43 @@
 // Batched exact distance queries (the 2-hop query of Section 2.1):
 // Dis(u,v) = min over common hubs h of d(u,h) + d(h,v), found by merging the
 // two hub-rank-sorted label lists.  Labels are packed (hub rank << 8) | dist.
+//
+// Two kernels:
+//  * k_query_lane: one lane per pair, a scalar two-pointer merge.  Kept for
+//    tiny labels and as the simplest form of the operation.
+//  * k_query_group<G>: G lanes per pair merge the lists window by window.  A
+//    window is 4G consecutive entries of one list, read as one aligned 16-byte
+//    load per lane (label arrays are padded to whole 4-entry chunks).  The
+//    v-window is published in LDS; every valid u-entry binary-searches it for
+//    its hub, and the window whose last list entry has the smaller hub moves
+//    on (both when equal).  Every common hub lies in a pair of windows that
+//    meet: a window only moves on once every entry of the other list that
+//    could match it has been seen, and once the window holding a list's end
+//    moves on the pair is done, so neither list is read past the point where
+//    the sequential merge stops.  The pair's minimum is reduced across the
+//    group at the end.
 #include "pll_internal.h"
 
 namespace {
 
 constexpr int kBlock = 256;
+constexpr uint32_t kAfter = 0xFFFFFFFFu;  // sorts after every key
 
-// One lane per pair: two-pointer merge.
 __global__ void __launch_bounds__(kBlock) k_query_lane(const uint64_t* __restrict__ off,
-                                                       const uint32_t* __restrict__ ent, uint64_t count,
+                                                       const uint32_t* __restrict__ ent, uint32_t n, uint64_t count,
                                                        const uint32_t* __restrict__ qu,
                                                        const uint32_t* __restrict__ qv, uint32_t* __restrict__ out) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t u = qu[i], v = qv[i];
-        uint64_t a = off[u], ae = off[u + 1], b = off[v], be = off[v + 1];
         uint32_t best = PLL_DIST_INF;
+        uint64_t a = 0, ae = 0, b = 0, be = 0;
+        if (u < n && v < n) {  // an id out of range has no label: no common hub
+            a = off[u];
+            ae = off[u + 1];
+            b = off[v];
+            be = off[v + 1];
+        }
         if (a < ae && b < be) {
             uint32_t ea = ent[a], eb = ent[b];
             for (;;) {
@@ -39,13 +60,185 @@ __global__ void __launch_bounds__(kBlock) k_query_lane(const uint64_t* __restric
     }
 }
 
+// Lane `gl`'s four entries of a window (base pointer w, 16-byte aligned),
+// as sortable keys: an entry becomes ((hub rank + 1) << 8) | dist, window
+// positions before lo become 0 and positions at or after hi become kAfter, so
+// the window stays sorted.  Positions are relative to the window start.
+__device__ __forceinline__ void load_window(const uint32_t* __restrict__ w, int32_t lo, int32_t hi, uint32_t gl,
+                                            uint32_t k[4]) {
+    const int32_t c = 4 * (int32_t)gl;
+    uint4 x = make_uint4(kAfter, kAfter, kAfter, kAfter);
+    if (c < hi) x = *reinterpret_cast<const uint4*>(w + c);
+    const uint32_t raw[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int32_t q = c + j;
+        k[j] = q < lo ? 0u : (q >= hi ? kAfter : raw[j] + 256u);
+    }
+}
+
+// Values shared by a group; with one pair per wave they are wave-uniform and
+// kept in scalar registers.
+template <int G>
+__device__ __forceinline__ uint32_t group_uniform(uint32_t x) {
+    if constexpr (G == 64)
+        return __builtin_amdgcn_readfirstlane(x);
+    else
+        return x;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t group_uniform(uint64_t x) {
+    if constexpr (G == 64)
+        return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32)) << 32) |
+               __builtin_amdgcn_readfirstlane((uint32_t)x);
+    else
+        return x;
+}
+
+// LDS position of window entry q: one dword of padding after every 32, so
+// the probes of a binary search (power-of-two strides) spread over the banks.
+__device__ __forceinline__ uint32_t lds_pos(uint32_t q) { return q + (q >> 5); }
+
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_query_group(const uint64_t* __restrict__ off,
+                                                        const uint32_t* __restrict__ ent, uint32_t n, uint64_t count,
+                                                        const uint32_t* __restrict__ qu,
+                                                        const uint32_t* __restrict__ qv, uint32_t* __restrict__ out) {
+    static_assert(G >= 4 && G <= 64 && (G & (G - 1)) == 0, "group size");
+    constexpr int32_t kWin = 4 * G;
+    constexpr uint32_t kWinLds = kWin + kWin / 32;  // padded window in LDS
+    __shared__ uint32_t s_win[(kBlock / G) * kWinLds];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t gl = lane & (G - 1);
+    const uint32_t gfirst = lane & ~(uint32_t)(G - 1);
+    uint32_t* win = s_win + (threadIdx.x / G) * kWinLds;
+    const uint64_t stride = (uint64_t)gridDim.x * (kBlock / G);
+    for (uint64_t p = group_uniform<G>(blockIdx.x * (uint64_t)(kBlock / G) + threadIdx.x / G); p < count;
+         p += stride) {
+        const uint32_t u = qu[p], v = qv[p];
+        uint64_t a = 0, ae = 0, b = 0, be = 0;
+        if (u < n && v < n) {  // an id out of range has no label: no common hub
+            a = off[u];
+            ae = off[u + 1];
+            b = off[v];
+            be = off[v + 1];
+        }
+        uint32_t best = PLL_DIST_INF;
+        // windows: base pointers on 4-entry boundaries; list bounds relative
+        // to the window start (lists are shorter than 2^31 entries)
+        const uint32_t* wa = ent + (a & ~3ull);
+        const uint32_t* wb = ent + (b & ~3ull);
+        int32_t a_lo = (int32_t)(a & 3), a_hi = (int32_t)(ae - (a & ~3ull));
+        int32_t b_lo = (int32_t)(b & 3), b_hi = (int32_t)(be - (b & ~3ull));
+        if (!(a < ae && b < be)) a_hi = 0;  // an empty list: no common hub
+        uint32_t ka[4], kb[4];
+        if (a_hi > 0) {
+            load_window(wa, a_lo, a_hi, gl, ka);
+            load_window(wb, b_lo, b_hi, gl, kb);
+        }
+        while (a_hi > 0 && b_hi > 0) {  // uniform over the group
+            a_lo = (int32_t)group_uniform<G>((uint32_t)a_lo);
+            a_hi = (int32_t)group_uniform<G>((uint32_t)a_hi);
+            b_lo = (int32_t)group_uniform<G>((uint32_t)b_lo);
+            b_hi = (int32_t)group_uniform<G>((uint32_t)b_hi);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) win[lds_pos(4 * gl + j)] = kb[j];
+            // hub of the last list entry inside each window
+            const int32_t la = min(a_hi, kWin) - 1, lb = min(b_hi, kWin) - 1;
+            uint32_t ta = ka[0], tb = kb[0];
+#pragma unroll
+            for (int j = 1; j < 4; ++j) {
+                ta = (la & 3) == j ? ka[j] : ta;
+                tb = (lb & 3) == j ? kb[j] : tb;
+            }
+            const uint32_t last_a = (uint32_t)__shfl((int)ta, (int)(gfirst + (la >> 2))) >> 8;
+            const uint32_t last_b = (uint32_t)__shfl((int)tb, (int)(gfirst + (lb >> 2))) >> 8;
+            wave_lds_sync();
+            // lower bound of each u-key in the v-window; the four searches
+            // advance together so their LDS reads overlap
+            uint32_t key[4], pos[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                key[j] = ka[j] & ~255u;
+                pos[j] = 0;
+            }
+#pragma unroll
+            for (int32_t step = kWin / 2; step >= 1; step >>= 1) {
+                uint32_t probe[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) probe[j] = win[lds_pos(pos[j] + step - 1)];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) pos[j] += probe[j] < key[j] ? step : 0;
+            }
+            // a hit needs a valid u-key (not a 0 or kAfter filler), the same
+            // hub, and a position inside the v list
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t w = win[lds_pos(pos[j])];
+                const int32_t q = 4 * (int32_t)gl + j;
+                const bool hit = q >= a_lo && q < a_hi && (int32_t)pos[j] < b_hi && (w >> 8) == (key[j] >> 8);
+                best = hit ? min(best, (ka[j] & 255u) + (w & 255u)) : best;
+            }
+            wave_lds_sync();
+            // a window moves on once the other list has been seen up to its
+            // last hub; the list whose window held its end is then exhausted
+            if (last_a <= last_b) {
+                wa += kWin;
+                a_lo -= kWin;
+                a_hi -= kWin;
+                if (a_hi > 0) load_window(wa, a_lo, a_hi, gl, ka);
+            }
+            if (last_b <= last_a) {
+                wb += kWin;
+                b_lo -= kWin;
+                b_hi -= kWin;
+                if (b_hi > 0) load_window(wb, b_lo, b_hi, gl, kb);
+            }
+        }
+#pragma unroll
+        for (int s = G / 2; s >= 1; s >>= 1) best = min(best, (uint32_t)__shfl_xor((int)best, s, G));
+        if (gl == 0) out[p] = best;
+    }
+}
+
+template <int G>
+void launch_group(const pll_index* idx, uint64_t count, const uint32_t* d_u, const uint32_t* d_v, uint32_t* d_out,
+                  hipStream_t stream) {
+    constexpr uint64_t per_block = kBlock / G;
+    uint64_t blocks = (count + per_block - 1) / per_block;
+    if (blocks > (1u << 20)) blocks = 1u << 20;
+    k_query_group<G><<<(uint32_t)blocks, kBlock, 0, stream>>>(idx->d_off, idx->d_ent, idx->n, count, d_u, d_v, d_out);
+}
+
+// Lanes per pair when the index leaves it open: the window (4 entries per
+// lane) should hold about one average label.
+uint32_t query_lanes_auto(const pll_index* idx) {
+    const uint64_t mean = idx->n ? idx->total / idx->n : 0;
+    uint32_t g = 4;
+    while (g < 64 && 4ull * g < mean) g *= 2;
+    return g;
+}
+
 }  // namespace
 
 int pll_query_launch(const pll_index* idx, uint64_t count, const uint32_t* d_u, const uint32_t* d_v,
                      uint32_t* d_out, hipStream_t stream) {
     if (count == 0) return PLL_OK;
-    uint64_t blocks = (count + kBlock - 1) / kBlock;
-    if (blocks > 65536) blocks = 65536;
-    k_query_lane<<<(uint32_t)blocks, kBlock, 0, stream>>>(idx->d_off, idx->d_ent, count, d_u, d_v, d_out);
+    const uint32_t g = idx->query_lanes ? idx->query_lanes : query_lanes_auto(idx);
+    switch (g) {
+        case 1: {
+            uint64_t blocks = (count + kBlock - 1) / kBlock;
+            if (blocks > 65536) blocks = 65536;
+            k_query_lane<<<(uint32_t)blocks, kBlock, 0, stream>>>(idx->d_off, idx->d_ent, idx->n, count, d_u, d_v, d_out);
+            break;
+        }
+        case 4: launch_group<4>(idx, count, d_u, d_v, d_out, stream); break;
+        case 8: launch_group<8>(idx, count, d_u, d_v, d_out, stream); break;
+        case 16: launch_group<16>(idx, count, d_u, d_v, d_out, stream); break;
+        case 32: launch_group<32>(idx, count, d_u, d_v, d_out, stream); break;
+        case 64: launch_group<64>(idx, count, d_u, d_v, d_out, stream); break;
+        default: return PLL_EINVAL;
+    }
     return hipGetLastError() == hipSuccess ? PLL_OK : PLL_EDEVICE;
 }

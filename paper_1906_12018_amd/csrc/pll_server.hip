@@ -8,8 +8,9 @@
 // merge-join query kernel and copies results back on the slot's stream.
 // Completed batches are scattered to their requests.  Slots run
 // concurrently, so batches overlap on the device with each other and with
-// label builds, which a second thread runs on their own stream once
-// hipMemGetInfo reports enough free memory for the job.
+// label builds, which a second thread runs on their own stream: it admits
+// queued labeling jobs while hipMemGetInfo reports room for them and labels
+// all admitted jobs in one launch.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -186,9 +187,14 @@ struct pll_server {
         s.busy = true;
     }
 
-    // build worker: admit the oldest labeling job once memory allows
+    // build worker: admit queued labeling jobs, oldest first, while their
+    // estimated footprint fits in free device memory (less the reserve), and
+    // label everything admitted together: one many-graph persistent launch
+    // for small graphs, the grid-wide single-graph build for a lone or large
+    // one.  A job that could never fit on the device fails with ENOMEM.
     void run_builder() {
         (void)hipSetDevice(device);
+        const uint32_t b = opts.build_batch_size ? opts.build_batch_size : PLL_BMAX;
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
             if (builds.empty()) {
@@ -196,67 +202,135 @@ struct pll_server {
                 cv.wait_for(lk, std::chrono::milliseconds(2));
                 continue;
             }
-            Req* q = builds.front();
             if (stop) {  // shutting down: jobs not started yet are dropped
+                Req* q = builds.front();
                 builds.pop_front();
                 finish(q, PLL_ENOMEM);
                 continue;
             }
-            const uint32_t b = opts.build_batch_size ? opts.build_batch_size : PLL_BMAX;
-            const uint64_t need = build_bytes_estimate(q->r.n, q->r.nnz, b) + opts.mem_reserve;
             size_t free_b = 0, total_b = 0;
             lk.unlock();
-            const bool mem_ok = hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b >= need;
+            const bool info_ok = hipMemGetInfo(&free_b, &total_b) == hipSuccess;
             lk.lock();
-            if (!mem_ok) {
-                if (need > total_b && total_b) {  // can never fit
+            std::vector<Req*> take;
+            uint64_t need_sum = opts.mem_reserve;
+            while (info_ok && !builds.empty() && take.size() < kMaxJobsPerLaunch) {
+                Req* q = builds.front();
+                const uint64_t need = build_bytes_estimate(q->r.n, q->r.nnz, b);
+                if (need + opts.mem_reserve > total_b) {  // can never fit
                     builds.pop_front();
                     finish(q, PLL_ENOMEM);
-                } else {
-                    cv.wait_for(lk, std::chrono::milliseconds(1));
+                    continue;
                 }
+                if (need_sum + need > free_b) break;
+                need_sum += need;
+                builds.pop_front();
+                q->t_admit = now();
+                take.push_back(q);
+            }
+            if (take.empty()) {
+                cv.wait_for(lk, std::chrono::milliseconds(1));
                 continue;
             }
-            builds.pop_front();
-            q->t_admit = now();
             lk.unlock();
-            pll_index* idx = nullptr;
-            int rc = build_from_host(q->r, b, &idx);
+            std::vector<pll_index*> idx(take.size(), nullptr);
+            std::vector<int> rc(take.size(), PLL_OK);
+            build_jobs(take, b, idx.data(), rc.data());
             lk.lock();
-            if (rc == PLL_OK) {
-                const uint32_t id = next_index++;
-                indexes[id] = IndexEntry{idx, true};
-                q->new_index = id;
+            for (size_t i = 0; i < take.size(); ++i) {
+                if (rc[i] == PLL_OK) {
+                    const uint32_t id = next_index++;
+                    indexes[id] = IndexEntry{idx[i], true};
+                    take[i]->new_index = id;
+                }
+                finish(take[i], rc[i]);
             }
-            finish(q, rc);
         }
     }
 
-    int build_from_host(const pll_request& r, uint32_t b, pll_index** out) {
-        const uint64_t n = r.n, nnz = r.nnz;
-        if (n && (!r.h_row_ptr || !r.h_order || (nnz && !r.h_col))) return PLL_EINVAL;
-        uint64_t* d_rp = nullptr;
-        uint32_t *d_col = nullptr, *d_order = nullptr;
-        int rc = PLL_OK;
-        if (hipMalloc((void**)&d_rp, 8 * (n + 1)) != hipSuccess ||
-            hipMalloc((void**)&d_col, 4 * std::max<uint64_t>(nnz, 1)) != hipSuccess ||
-            hipMalloc((void**)&d_order, 4 * std::max<uint64_t>(n, 1)) != hipSuccess) {
-            rc = PLL_ENOMEM;
-        } else if ((n && (hipMemcpyAsync(d_rp, r.h_row_ptr, 8 * (n + 1), hipMemcpyHostToDevice, build_stream) != hipSuccess ||
-                          hipMemcpyAsync(d_order, r.h_order, 4 * n, hipMemcpyHostToDevice, build_stream) != hipSuccess)) ||
-                   (nnz && hipMemcpyAsync(d_col, r.h_col, 4 * nnz, hipMemcpyHostToDevice, build_stream) != hipSuccess)) {
-            rc = PLL_EDEVICE;
-        } else {
-            pll_build_opts o{};
-            o.batch_size = b;
-            o.flags = PLL_FLAG_VALIDATE;
-            rc = pll_build_one(r.n, r.nnz, d_rp, d_col, d_order, &o, build_stream, out);
+    static constexpr size_t kMaxJobsPerLaunch = 256;
+    static constexpr uint32_t kLargeGraph = 1u << 16;  // built alone, grid-wide
+
+    // device staging for the host CSRs of admitted jobs (grows, kept)
+    void* stage = nullptr;
+    uint64_t stage_cap = 0;
+
+    static uint64_t up256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+    // upload the CSRs of `jobs` and label them; rc[i] is job i's status
+    void build_jobs(const std::vector<Req*>& jobs, uint32_t b, pll_index** idx, int* rc) {
+        const size_t k = jobs.size();
+        uint64_t bytes = 0;
+        for (Req* q : jobs) {
+            const pll_request& r = q->r;
+            if (r.n && (!r.h_row_ptr || !r.h_order || (r.nnz && !r.h_col))) continue;
+            bytes += up256(8 * (uint64_t(r.n) + 1)) + up256(4 * r.nnz) + up256(4 * uint64_t(r.n));
+        }
+        if (bytes > stage_cap) {
+            if (stage) (void)hipFree(stage);
+            stage = nullptr;
+            stage_cap = 0;
+            if (hipMalloc(&stage, bytes) != hipSuccess) {
+                stage = nullptr;
+                for (size_t i = 0; i < k; ++i) rc[i] = PLL_ENOMEM;
+                return;
+            }
+            stage_cap = bytes;
+        }
+        std::vector<pll_graph_desc> desc(k);
+        std::vector<size_t> small;  // jobs for the many-graph launch
+        char* p = static_cast<char*>(stage);
+        for (size_t i = 0; i < k; ++i) {
+            const pll_request& r = jobs[i]->r;
+            if (r.n && (!r.h_row_ptr || !r.h_order || (r.nnz && !r.h_col))) {
+                rc[i] = PLL_EINVAL;
+                continue;
+            }
+            pll_graph_desc& d = desc[i];
+            d.n = r.n;
+            d.nnz = r.nnz;
+            d.d_row_ptr = reinterpret_cast<const uint64_t*>(p);
+            p += up256(8 * (uint64_t(r.n) + 1));
+            d.d_col = reinterpret_cast<const uint32_t*>(p);
+            p += up256(4 * r.nnz);
+            d.d_order = reinterpret_cast<const uint32_t*>(p);
+            p += up256(4 * uint64_t(r.n));
+            const bool ok =
+                (!r.n || (hipMemcpyAsync(const_cast<uint64_t*>(d.d_row_ptr), r.h_row_ptr, 8 * (uint64_t(r.n) + 1),
+                                         hipMemcpyHostToDevice, build_stream) == hipSuccess &&
+                          hipMemcpyAsync(const_cast<uint32_t*>(d.d_order), r.h_order, 4 * uint64_t(r.n),
+                                         hipMemcpyHostToDevice, build_stream) == hipSuccess)) &&
+                (!r.nnz || hipMemcpyAsync(const_cast<uint32_t*>(d.d_col), r.h_col, 4 * r.nnz, hipMemcpyHostToDevice,
+                                          build_stream) == hipSuccess);
+            if (!ok) {
+                rc[i] = PLL_EDEVICE;
+                continue;
+            }
+            if (r.n < kLargeGraph) small.push_back(i);
+        }
+        pll_build_opts o{};
+        o.batch_size = b;
+        o.flags = PLL_FLAG_VALIDATE;
+        bool batched = false;
+        if (small.size() > 1) {
+            std::vector<pll_graph_desc> sd(small.size());
+            std::vector<pll_index*> so(small.size(), nullptr);
+            for (size_t j = 0; j < small.size(); ++j) sd[j] = desc[small[j]];
+            if (pll_build_multi(uint32_t(small.size()), sd.data(), &o, build_stream, so.data()) == PLL_OK) {
+                for (size_t j = 0; j < small.size(); ++j) idx[small[j]] = so[j];
+                batched = true;
+            }
+            // on failure every job is built alone below, so that only the
+            // offending job reports the error
+        }
+        for (size_t i = 0; i < k; ++i) {
+            if (rc[i] != PLL_OK || idx[i]) continue;
+            if (batched && jobs[i]->r.n < kLargeGraph) continue;
+            const pll_request& r = jobs[i]->r;
+            rc[i] = pll_build_one(r.n, r.nnz, desc[i].d_row_ptr, desc[i].d_col, desc[i].d_order, &o, build_stream,
+                                  &idx[i]);
         }
         (void)hipStreamSynchronize(build_stream);
-        if (d_rp) (void)hipFree(d_rp);
-        if (d_col) (void)hipFree(d_col);
-        if (d_order) (void)hipFree(d_order);
-        return rc;
     }
 };
 
@@ -282,6 +356,8 @@ void destroy_server(pll_server* s) {
         if (sl.d_v) (void)hipFree(sl.d_v);
         if (sl.d_out) (void)hipFree(sl.d_out);
     }
+    if (s->build_stream) (void)hipStreamSynchronize(s->build_stream);
+    if (s->stage) (void)hipFree(s->stage);
     if (s->build_stream) (void)hipStreamDestroy(s->build_stream);
     for (auto& kv : s->indexes)
         if (kv.second.owned) pll_index_free(kv.second.idx);

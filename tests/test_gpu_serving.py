@@ -48,17 +48,20 @@ def test_alone_equals_mix(two_indexes):
         rid = srv.submit(pll.Server.query_request(iid, u, v, out))
         assert srv.wait(rid)["status"] == pll.PLL_OK
         alone.append(out)
-    # in the mix: open-loop arrivals every 50 us, with two labeling jobs
+    # in the mix: the first 40 requests arrive in one burst (more than the
+    # slots, so later ones must be packed), the rest every 50 us, with two
+    # labeling jobs among them
     g1, g2 = synth.ba_graph(3000, 3, 77), synth.ba_graph(1200, 6, 78)
     o1, o2 = synth.degree_order(g1), synth.degree_order(g2)
     mix, outs = [], []
     for k, (iid, u, v) in enumerate(work):
         out = np.zeros(len(u), dtype=np.uint32)
         outs.append(out)
-        mix.append(pll.Server.query_request(iid, u, v, out, at=5e-5 * k))
+        at = 5e-5 * max(k - 40, 0)
+        mix.append(pll.Server.query_request(iid, u, v, out, at=at))
         if k in (10, 50):
             g, o = (g1, o1) if k == 10 else (g2, o2)
-            mix.append(pll.Server.build_request(g.row_ptr, g.col, o, at=5e-5 * k))
+            mix.append(pll.Server.build_request(g.row_ptr, g.col, o, at=at))
     res = srv.replay(mix)
     assert all(r["status"] == pll.PLL_OK for r in res)
     for a, b in zip(alone, outs):
@@ -105,4 +108,33 @@ def test_unknown_index_and_unfittable_build():
     g = synth.ba_graph(300, 2, 1)
     rid = srv.submit(pll.Server.build_request(g.row_ptr, g.col, synth.degree_order(g)))
     assert srv.wait(rid)["status"] == pll.PLL_ENOMEM
+    srv.close()
+
+
+def test_labeling_jobs_admitted_together():
+    """Jobs queued together are labeled in one many-graph launch; a job with
+    an invalid rank order fails alone (EINVAL) and the others are exact; a
+    graph of 2^16 or more vertices takes the single-graph build."""
+    gs = [synth.ba_graph(n, m, 90 + i) for i, (n, m) in enumerate([(1000, 2), (4000, 5), (2500, 8), (1500, 3),
+                                                                   (3000, 4)])]
+    gs.append(synth.rmat_graph(16, seed=3))
+    orders = [synth.degree_order(g) for g in gs]
+    bad = orders[3].copy()
+    bad[0] = bad[1]
+    srv = pll.Server(slots=2)
+    reqs = [pll.Server.build_request(g.row_ptr, g.col, bad if i == 3 else o) for i, (g, o) in enumerate(zip(gs, orders))]
+    res = srv.replay(reqs)
+    for i, (r, g, o) in enumerate(zip(res, gs, orders)):
+        if i == 3:
+            assert r["status"] == pll.PLL_EINVAL
+            continue
+        assert r["status"] == pll.PLL_OK, (i, r)
+        want = oracle.pll_labels(g, o)
+        idx = srv.index(r["index_id"])
+        assert_labels_equal(idx, want, o)
+        u, v = synth.query_pairs(g.n, 4000, seed=11)
+        out = np.zeros(4000, dtype=np.uint32)
+        rid = srv.submit(pll.Server.query_request(r["index_id"], u, v, out))
+        assert srv.wait(rid)["status"] == pll.PLL_OK
+        assert np.array_equal(out, oracle.query(want, u, v))
     srv.close()

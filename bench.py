@@ -64,11 +64,13 @@ def cpu_baseline(g, order, total_entries):
 
 def serve_mode(args):
     """Serving workload: R-MAT scale-20 index resident; open-loop Poisson
-    arrivals of query requests with sizes log-uniform in [1, 65536] pairs,
-    a fraction of arrivals being labeling jobs for Barabasi-Albert graphs
-    (n log-uniform in [1000, 50000], m in {2..8}).  The offered rate is a
-    fraction of the saturation rate measured with one burst of the same
-    query requests.  Latency = completion - arrival, per request."""
+    arrivals (stream 4) of query requests with sizes log-uniform in [1, 65536]
+    pairs, a fraction of arrivals being labeling jobs for Barabasi-Albert
+    graphs (n log-uniform in [1000, 50000], m in {2..8}) admitted by free
+    memory.  Saturation = the request rate of one burst of the whole mix; the
+    load levels offer fractions of it.  Latency = completion - arrival.  Each
+    level runs on a fresh server (the indexes its labeling jobs built are
+    dropped with it)."""
     import numpy as np
     import torch
     import synth
@@ -92,16 +94,18 @@ def serve_mode(args):
     # labeling jobs (host CSR), generated once and reused by every load level
     nb = int(is_build.sum())
     bx = synth.splitmix64(6, 0, 2 * max(nb, 1))
+    lo, hi = np.log(1000), np.log(50000)
     jobs = []
     for i in range(nb):
-        n = int(round(np.exp(np.log(1000) + synth.uniform01(bx[2 * i:2 * i + 1])[0] * (np.log(50000) - np.log(1000)))))
+        n = int(round(np.exp(lo + synth.uniform01(bx[2 * i:2 * i + 1])[0] * (hi - lo))))
         m = 2 + int(synth.bounded(bx[2 * i + 1:2 * i + 2], 7)[0])
         bg = synth.ba_graph(n, m, 5000 + i)
         jobs.append((bg.row_ptr, bg.col, synth.degree_order(bg)))
-    srv = pll.Server(slots=args.serve_slots)
-    iid = srv.add_index(idx, take_ownership=False)
+    pairs = int(sizes[~is_build].sum())
 
-    def requests(at):
+    def run(at):
+        srv = pll.Server(slots=args.serve_slots)
+        iid = srv.add_index(idx, take_ownership=False)
         reqs, bi = [], 0
         for i in range(N):
             if is_build[i]:
@@ -111,49 +115,46 @@ def serve_mode(args):
             else:
                 a, c = int(starts[i]), int(sizes[i])
                 reqs.append(pll.Server.query_request(iid, pu[a:a + c], pv[a:a + c], pout[a:a + c], at=at[i]))
-        return reqs
+        res = srv.replay(reqs)
+        srv.close()
+        wall = max(r["t_done"] for r in res) - min(r["t_arrival"] for r in res)
+        return res, wall
 
     def summarize(res, wall):
         q = [r for r in res if r["kind"] == pll.REQ_QUERY]
         b = [r for r in res if r["kind"] == pll.REQ_BUILD]
         lat = np.array([r["t_done"] - r["t_arrival"] for r in q]) * 1e3
-        pairs = int(sum(sizes[i] for i in range(N) if not is_build[i]))
         out = {"query_requests": len(q), "pairs": pairs, "wall_s": wall, "pairs_per_s": pairs / wall,
-               "requests_per_s": len(q) / wall, "p50_ms": float(np.percentile(lat, 50)),
-               "p99_ms": float(np.percentile(lat, 99)), "mean_batch_requests":
-               float(np.mean([r["batch_requests"] for r in q if r["batch_requests"]]))}
+               "query_requests_per_s": len(q) / wall, "p50_ms": float(np.percentile(lat, 50)),
+               "p99_ms": float(np.percentile(lat, 99)),
+               "mean_requests_per_batch": float(np.mean([r["batch_requests"] for r in q if r["batch_requests"]])),
+               "query_errors": int(sum(r["status"] != 0 for r in q))}
         if b:
             bl = np.array([r["t_done"] - r["t_arrival"] for r in b]) * 1e3
-            out.update({"builds": len(b), "build_p50_ms": float(np.percentile(bl, 50)),
-                        "build_p99_ms": float(np.percentile(bl, 99)),
-                        "build_errors": int(sum(r["status"] != 0 for r in b))})
+            out.update({"labeling_jobs": len(b), "labeling_jobs_per_s": len(b) / wall,
+                        "labeling_p50_ms": float(np.percentile(bl, 50)),
+                        "labeling_p99_ms": float(np.percentile(bl, 99)),
+                        "labeling_errors": int(sum(r["status"] != 0 for r in b))})
         return out
 
-    # saturation: every query request at t = 0
-    sat_mask = ~is_build
-    burst = [r for r, keep in zip(requests(np.zeros(N)), sat_mask) if keep]
-    t0 = time.perf_counter()
-    res = srv.replay(burst)
-    wall = max(r["t_done"] for r in res) - min(r["t_arrival"] for r in res)
-    sat = len(burst) / wall
-    levels = {}
+    res, wall = run(np.zeros(N))
+    sat = N / wall
+    levels = {"burst": summarize(res, wall)}
     for frac in args.serve_loads:
         rate = frac * sat
-        gaps = -np.log(1.0 - synth.uniform01(synth.splitmix64(7, 0, N))) / rate
+        gaps = -np.log(1.0 - synth.uniform01(synth.splitmix64(4, 4 * N, N))) / rate
         at = np.cumsum(gaps) - gaps[0]
-        t0 = time.perf_counter()
-        res = srv.replay(requests(at))
-        wall = max(r["t_done"] for r in res) - min(r["t_arrival"] for r in res)
-        levels[f"{int(round(frac * 100))}%"] = summarize(res, wall)
-        levels[f"{int(round(frac * 100))}%"]["offered_requests_per_s"] = rate
-    srv.close()
+        res, wall = run(at)
+        key = f"{int(round(frac * 100))}%"
+        levels[key] = summarize(res, wall)
+        levels[key]["offered_requests_per_s"] = rate
     info = idx.info()
     idx.free()
-    line = {"mode": "serve", "workload": f"rmat{args.serve_scale} resident, {N} requests, "
-            f"{args.serve_build_frac:.0%} labeling jobs", "index_entries": info["total_entries"],
-            "label_bytes": info["label_bytes"], "saturation_requests_per_s": sat,
-            "saturation_pairs_per_s": int(sizes[sat_mask].sum()) / (len(burst) / sat), "levels": levels,
-            "slots": args.serve_slots, "data": "synthetic"}
+    line = {"mode": "serve", "workload": f"rmat{args.serve_scale} index resident; {N} requests, "
+            f"{nb} of them labeling jobs; query sizes log-uniform in [1, 65536]",
+            "index_entries": info["total_entries"], "label_bytes": info["label_bytes"],
+            "saturation_requests_per_s": sat, "levels": levels, "slots": args.serve_slots,
+            "data": "synthetic"}
     print(json.dumps(line), flush=True)
 
 
@@ -167,8 +168,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="build", choices=["build", "serve"])
     ap.add_argument("--serve-scale", type=int, default=20)
-    ap.add_argument("--serve-requests", type=int, default=20000)
-    ap.add_argument("--serve-build-frac", type=float, default=0.01)
+    ap.add_argument("--serve-requests", type=int, default=100000)
+    ap.add_argument("--serve-build-frac", type=float, default=0.02)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 0.95])
     args = ap.parse_args()

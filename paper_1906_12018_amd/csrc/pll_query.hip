@@ -6,16 +6,18 @@
 //  * k_query_lane: one lane per pair, a scalar two-pointer merge.  Kept for
 //    tiny labels and as the simplest form of the operation.
 //  * k_query_group<G>: G lanes per pair merge the lists window by window.  A
-//    window is 4G consecutive entries of one list, read as one aligned 16-byte
-//    load per lane (label arrays are padded to whole 4-entry chunks).  The
-//    v-window is published in LDS; every valid u-entry binary-searches it for
-//    its hub, and the window whose last list entry has the smaller hub moves
-//    on (both when equal).  Every common hub lies in a pair of windows that
-//    meet: a window only moves on once every entry of the other list that
-//    could match it has been seen, and once the window holding a list's end
-//    moves on the pair is done, so neither list is read past the point where
-//    the sequential merge stops.  The pair's minimum is reduced across the
-//    group at the end.
+//    u-window is 2G consecutive entries of L(u) and a v-window 4G entries of
+//    L(v), read as one aligned 8- or 16-byte load per lane (label arrays are
+//    padded to whole 4-entry chunks).  The v-window is published in LDS;
+//    every valid u-entry binary-searches it for its hub, and the window whose
+//    last list entry has the smaller hub moves on (both when equal).  Every
+//    common hub lies in a pair of windows that meet: a window only moves on
+//    once every entry of the other list that could match it has been seen,
+//    and once the window holding a list's end moves on the pair is done, so
+//    neither list is read past the point where the sequential merge stops.
+//    The pair's minimum is reduced across the group at the end.
+#include <atomic>
+
 #include "pll_internal.h"
 
 namespace {
@@ -60,21 +62,46 @@ __global__ void __launch_bounds__(kBlock) k_query_lane(const uint64_t* __restric
     }
 }
 
-// Lane `gl`'s four entries of a window (base pointer w, 16-byte aligned),
-// as sortable keys: an entry becomes ((hub rank + 1) << 8) | dist, window
-// positions before lo become 0 and positions at or after hi become kAfter, so
-// the window stays sorted.  Positions are relative to the window start.
+// Lane gl's E entries of a window of E*G entries starting at w (w aligned to
+// E entries, so the load is one aligned 4E-byte load), as sortable keys: an
+// entry becomes ((hub rank + 1) << 8) | dist, window positions before lo
+// become 0 and positions at or after hi become kAfter, so the window stays
+// sorted.  Positions are relative to the window start.
+template <int E>
 __device__ __forceinline__ void load_window(const uint32_t* __restrict__ w, int32_t lo, int32_t hi, uint32_t gl,
-                                            uint32_t k[4]) {
-    const int32_t c = 4 * (int32_t)gl;
-    uint4 x = make_uint4(kAfter, kAfter, kAfter, kAfter);
-    if (c < hi) x = *reinterpret_cast<const uint4*>(w + c);
-    const uint32_t raw[4] = {x.x, x.y, x.z, x.w};
+                                            uint32_t k[E]) {
+    static_assert(E == 2 || E == 4, "entries per lane");
+    const int32_t c = E * (int32_t)gl;
+    uint32_t raw[E];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < E; ++j) raw[j] = kAfter;
+    if (c < hi) {
+        if constexpr (E == 4) {
+            const uint4 x = *reinterpret_cast<const uint4*>(w + c);
+            raw[0] = x.x;
+            raw[1] = x.y;
+            raw[2] = x.z;
+            raw[3] = x.w;
+        } else {
+            const uint2 x = *reinterpret_cast<const uint2*>(w + c);
+            raw[0] = x.x;
+            raw[1] = x.y;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
         const int32_t q = c + j;
         k[j] = q < lo ? 0u : (q >= hi ? kAfter : raw[j] + 256u);
     }
+}
+
+// k[j] for a group-uniform j.
+template <int E>
+__device__ __forceinline__ uint32_t pick(const uint32_t k[E], int32_t j) {
+    uint32_t t = k[0];
+#pragma unroll
+    for (int i = 1; i < E; ++i) t = j == i ? k[i] : t;
+    return t;
 }
 
 // Values shared by a group; with one pair per wave they are wave-uniform and
@@ -96,9 +123,11 @@ __device__ __forceinline__ uint64_t group_uniform(uint64_t x) {
         return x;
 }
 
-// LDS position of window entry q: one dword of padding after every 32, so
-// the probes of a binary search (power-of-two strides) spread over the banks.
-__device__ __forceinline__ uint32_t lds_pos(uint32_t q) { return q + (q >> 5); }
+// u-windows hold 2 entries per lane and v-windows 4: each lane binary-searches
+// two u-keys in the 4G-entry v-window per step (fewer keys per step cost less
+// VALU work than four; measured best on both R-MAT scales).
+constexpr int kEntriesU = 2;
+constexpr int kEntriesV = 4;
 
 template <int G>
 __global__ void __launch_bounds__(kBlock) k_query_group(const uint64_t* __restrict__ off,
@@ -106,13 +135,12 @@ __global__ void __launch_bounds__(kBlock) k_query_group(const uint64_t* __restri
                                                         const uint32_t* __restrict__ qu,
                                                         const uint32_t* __restrict__ qv, uint32_t* __restrict__ out) {
     static_assert(G >= 4 && G <= 64 && (G & (G - 1)) == 0, "group size");
-    constexpr int32_t kWin = 4 * G;
-    constexpr uint32_t kWinLds = kWin + kWin / 32;  // padded window in LDS
-    __shared__ uint32_t s_win[(kBlock / G) * kWinLds];
+    constexpr int32_t kWinU = kEntriesU * G, kWinV = kEntriesV * G;
+    __shared__ uint4 s_win[kBlock];
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t gl = lane & (G - 1);
     const uint32_t gfirst = lane & ~(uint32_t)(G - 1);
-    uint32_t* win = s_win + (threadIdx.x / G) * kWinLds;
+    const uint32_t* win = reinterpret_cast<const uint32_t*>(s_win + (threadIdx.x & ~(uint32_t)(G - 1)));
     const uint64_t stride = (uint64_t)gridDim.x * (kBlock / G);
     for (uint64_t p = group_uniform<G>(blockIdx.x * (uint64_t)(kBlock / G) + threadIdx.x / G); p < count;
          p += stride) {
@@ -125,58 +153,53 @@ __global__ void __launch_bounds__(kBlock) k_query_group(const uint64_t* __restri
             be = off[v + 1];
         }
         uint32_t best = PLL_DIST_INF;
-        // windows: base pointers on 4-entry boundaries; list bounds relative
-        // to the window start (lists are shorter than 2^31 entries)
-        const uint32_t* wa = ent + (a & ~3ull);
-        const uint32_t* wb = ent + (b & ~3ull);
-        int32_t a_lo = (int32_t)(a & 3), a_hi = (int32_t)(ae - (a & ~3ull));
-        int32_t b_lo = (int32_t)(b & 3), b_hi = (int32_t)(be - (b & ~3ull));
+        // windows: base pointers aligned to the entries per lane; list bounds
+        // relative to the window start (lists are shorter than 2^31 entries)
+        constexpr uint64_t kAlignU = kEntriesU - 1, kAlignV = kEntriesV - 1;
+        const uint32_t* wa = ent + (a & ~kAlignU);
+        const uint32_t* wb = ent + (b & ~kAlignV);
+        int32_t a_lo = (int32_t)(a & kAlignU), a_hi = (int32_t)(ae - (a & ~kAlignU));
+        int32_t b_lo = (int32_t)(b & kAlignV), b_hi = (int32_t)(be - (b & ~kAlignV));
         if (!(a < ae && b < be)) a_hi = 0;  // an empty list: no common hub
-        uint32_t ka[4], kb[4];
+        uint32_t ka[kEntriesU], kb[kEntriesV];
         if (a_hi > 0) {
-            load_window(wa, a_lo, a_hi, gl, ka);
-            load_window(wb, b_lo, b_hi, gl, kb);
+            load_window<kEntriesU>(wa, a_lo, a_hi, gl, ka);
+            load_window<kEntriesV>(wb, b_lo, b_hi, gl, kb);
         }
         while (a_hi > 0 && b_hi > 0) {  // uniform over the group
             a_lo = (int32_t)group_uniform<G>((uint32_t)a_lo);
             a_hi = (int32_t)group_uniform<G>((uint32_t)a_hi);
             b_lo = (int32_t)group_uniform<G>((uint32_t)b_lo);
             b_hi = (int32_t)group_uniform<G>((uint32_t)b_hi);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) win[lds_pos(4 * gl + j)] = kb[j];
+            s_win[threadIdx.x] = make_uint4(kb[0], kb[1], kb[2], kb[3]);
             // hub of the last list entry inside each window
-            const int32_t la = min(a_hi, kWin) - 1, lb = min(b_hi, kWin) - 1;
-            uint32_t ta = ka[0], tb = kb[0];
-#pragma unroll
-            for (int j = 1; j < 4; ++j) {
-                ta = (la & 3) == j ? ka[j] : ta;
-                tb = (lb & 3) == j ? kb[j] : tb;
-            }
-            const uint32_t last_a = (uint32_t)__shfl((int)ta, (int)(gfirst + (la >> 2))) >> 8;
-            const uint32_t last_b = (uint32_t)__shfl((int)tb, (int)(gfirst + (lb >> 2))) >> 8;
+            const int32_t la = min(a_hi, kWinU) - 1, lb = min(b_hi, kWinV) - 1;
+            const uint32_t ta = pick<kEntriesU>(ka, la % kEntriesU), tb = pick<kEntriesV>(kb, lb % kEntriesV);
+            const uint32_t last_a = (uint32_t)__shfl((int)ta, (int)(gfirst + la / kEntriesU)) >> 8;
+            const uint32_t last_b = (uint32_t)__shfl((int)tb, (int)(gfirst + lb / kEntriesV)) >> 8;
             wave_lds_sync();
-            // lower bound of each u-key in the v-window; the four searches
-            // advance together so their LDS reads overlap
-            uint32_t key[4], pos[4];
+            // lower bound of each u-key in the v-window; the searches advance
+            // together so their LDS reads overlap
+            uint32_t key[kEntriesU], pos[kEntriesU];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < kEntriesU; ++j) {
                 key[j] = ka[j] & ~255u;
                 pos[j] = 0;
             }
 #pragma unroll
-            for (int32_t step = kWin / 2; step >= 1; step >>= 1) {
-                uint32_t probe[4];
+            for (int32_t step = kWinV / 2; step >= 1; step >>= 1) {
+                uint32_t probe[kEntriesU];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) probe[j] = win[lds_pos(pos[j] + step - 1)];
+                for (int j = 0; j < kEntriesU; ++j) probe[j] = win[pos[j] + step - 1];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) pos[j] += probe[j] < key[j] ? step : 0;
+                for (int j = 0; j < kEntriesU; ++j) pos[j] += probe[j] < key[j] ? step : 0;
             }
             // a hit needs a valid u-key (not a 0 or kAfter filler), the same
             // hub, and a position inside the v list
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t w = win[lds_pos(pos[j])];
-                const int32_t q = 4 * (int32_t)gl + j;
+            for (int j = 0; j < kEntriesU; ++j) {
+                const uint32_t w = win[pos[j]];
+                const int32_t q = kEntriesU * (int32_t)gl + j;
                 const bool hit = q >= a_lo && q < a_hi && (int32_t)pos[j] < b_hi && (w >> 8) == (key[j] >> 8);
                 best = hit ? min(best, (ka[j] & 255u) + (w & 255u)) : best;
             }
@@ -184,16 +207,16 @@ __global__ void __launch_bounds__(kBlock) k_query_group(const uint64_t* __restri
             // a window moves on once the other list has been seen up to its
             // last hub; the list whose window held its end is then exhausted
             if (last_a <= last_b) {
-                wa += kWin;
-                a_lo -= kWin;
-                a_hi -= kWin;
-                if (a_hi > 0) load_window(wa, a_lo, a_hi, gl, ka);
+                wa += kWinU;
+                a_lo -= kWinU;
+                a_hi -= kWinU;
+                if (a_hi > 0) load_window<kEntriesU>(wa, a_lo, a_hi, gl, ka);
             }
             if (last_b <= last_a) {
-                wb += kWin;
-                b_lo -= kWin;
-                b_hi -= kWin;
-                if (b_hi > 0) load_window(wb, b_lo, b_hi, gl, kb);
+                wb += kWinV;
+                b_lo -= kWinV;
+                b_hi -= kWinV;
+                if (b_hi > 0) load_window<kEntriesV>(wb, b_lo, b_hi, gl, kb);
             }
         }
 #pragma unroll
@@ -202,12 +225,30 @@ __global__ void __launch_bounds__(kBlock) k_query_group(const uint64_t* __restri
     }
 }
 
+// Grid: a multiple of the workgroups that fit on the device at once (every
+// group loops over pairs).  Short lists leave waves idle sooner, so more
+// workgroups than fit at once balance better; measured: 32x for one pair per
+// wave, 8x for smaller groups.
 template <int G>
 void launch_group(const pll_index* idx, uint64_t count, const uint32_t* d_u, const uint32_t* d_v, uint32_t* d_out,
                   hipStream_t stream) {
+    static std::atomic<uint64_t> cap_cache[64];
     constexpr uint64_t per_block = kBlock / G;
     uint64_t blocks = (count + per_block - 1) / per_block;
-    if (blocks > (1u << 20)) blocks = 1u << 20;
+    const int dev = idx->device;
+    uint64_t cap = dev >= 0 && dev < 64 ? cap_cache[dev].load(std::memory_order_relaxed) : 0;
+    if (cap == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query_group<G>, kBlock, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1 ||
+            cus < 1) {
+            per_cu = 8;
+            cus = 256;
+        }
+        cap = (uint64_t)per_cu * cus * (G == 64 ? 32 : 8);
+        if (dev >= 0 && dev < 64) cap_cache[dev].store(cap, std::memory_order_relaxed);
+    }
+    if (blocks > cap) blocks = cap;
     k_query_group<G><<<(uint32_t)blocks, kBlock, 0, stream>>>(idx->d_off, idx->d_ent, idx->n, count, d_u, d_v, d_out);
 }
 

@@ -49,6 +49,115 @@ def consumed_entries(off, hubs_rank, rank, u, v):
     return int(cu.sum() + cv.sum())
 
 
+# Sources whose text fixes each measured kernel; the HBM traffic recorded in
+# profiles/hbm_traffic.txt is used only while their hash is unchanged.
+PKG_CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1906_12018_amd", "csrc")
+KERNEL_SOURCES = {
+    "k_check": ["pll_build.hip", "pll_phases.h", "pll_internal.h"],
+    "k_query_group": ["pll_query.hip", "pll_internal.h"],
+}
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic.txt")
+
+
+def sources_hash(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(PKG_CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes (FETCH_SIZE + WRITE_SIZE, calibrated) per unit recorded for
+    this kernel and workload, or None when absent or taken from other
+    sources."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    want = sources_hash(kernel)
+    for line in lines:
+        if not line.startswith("traffic kernel="):
+            continue
+        kv = dict(t.split("=", 1) for t in line.split()[1:])
+        if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("sources") == want:
+            return {"bytes": float(kv["fetch_bytes"]) + float(kv["write_bytes"]),
+                    "fetch_bytes": float(kv["fetch_bytes"]), "write_bytes": float(kv["write_bytes"]),
+                    "per": kv.get("per", "launch")}
+    return None
+
+
+def calibrate():
+    """A plain elementwise kernel of known traffic for the counter scale:
+    reads 256 MiB and writes 256 MiB (y = x + 1 over 2^26 int32)."""
+    import torch
+    x = torch.empty(1 << 26, dtype=torch.int32, device="cuda:0")
+    x.fill_(1)
+    torch.cuda.synchronize()
+    y = x + 1
+    torch.cuda.synchronize()
+    del x, y
+
+
+def query_mode(args):
+    """Queries alone: build the workload's index once, then time --steps
+    launches of the configured pair batch (HIP events on the launching
+    stream)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1906_12018_amd as pll
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    g = make_graph(w)
+    order = synth.degree_order(g)
+    rp, cl = pll.graph_to_device(g, dev)
+    od = torch.from_numpy(order.view(np.int32)).to(dev)
+    idx = pll.build_labels(rp, cl, od, batch_size=args.batch_size, flags=0)
+    u, v = synth.query_pairs(g.n, w["pairs"], seed=2)
+    du = torch.from_numpy(u.view(np.int32)).to(dev)
+    dv = torch.from_numpy(v.view(np.int32)).to(dev)
+    out = torch.empty_like(du)
+    for _ in range(args.warmup):
+        idx.query(du, dv, out=out)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        idx.query(du, dv, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    cons = consumed_for(idx, g, order, u, v)
+    q_bytes = w["pairs"] * (8 + 32 + 4) + 4 * cons
+    med = float(np.median(ms))
+    gbs = q_bytes / (med / 1e3) / 1e9
+    tr = measured_traffic("k_query_group", args.workload)
+    print(json.dumps({"mode": "query", "workload": args.workload, "pairs": w["pairs"], "steps": args.steps,
+                      "ms_p50": med, "ms_p99": float(np.percentile(ms, 99)), "queries_per_s": w["pairs"] / (med / 1e3),
+                      "roofline": {"kernel": "k_query_group", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                                   "traffic": tr["bytes"] if tr else None,
+                                   "bytes_per_launch": q_bytes, "entries_consumed": cons},
+                      "label_entries": idx.info()["total_entries"]}), flush=True)
+    idx.free()
+
+
+def consumed_for(idx, g, order, u, v):
+    import numpy as np
+    import torch
+    ex = idx.export()
+    torch.cuda.synchronize()
+    off = ex.offsets.cpu().numpy().view(np.uint64).astype(np.int64)
+    hubs = ex.hubs.cpu().numpy().view(np.uint32)
+    rank = np.empty(g.n, dtype=np.int64)
+    rank[order.astype(np.int64)] = np.arange(g.n)
+    return consumed_entries(off, rank[hubs.astype(np.int64)], rank, u.astype(np.int64), v.astype(np.int64))
+
+
 def cpu_baseline(g, order, total_entries):
     """The oracle's sequential PLL (Algorithm 1) on the host, one thread, on
     the whole graph (the R-MAT scale-16 build takes roughly 10-20 s)."""
@@ -166,7 +275,9 @@ def main():
     ap.add_argument("--workload", default="rmat16", choices=sorted(WORKLOADS))
     ap.add_argument("--batch-size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="build", choices=["build", "serve"])
+    ap.add_argument("--mode", default="build", choices=["build", "query", "serve"])
+    ap.add_argument("--calibrate", action="store_true",
+                    help="finish with a 256 MiB read + 256 MiB write elementwise kernel (counter scale)")
     ap.add_argument("--serve-scale", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=100000)
     ap.add_argument("--serve-build-frac", type=float, default=0.02)
@@ -180,6 +291,11 @@ def main():
 
     if args.mode == "serve":
         serve_mode(args)
+        return
+    if args.mode == "query":
+        query_mode(args)
+        if args.calibrate:
+            calibrate()
         return
 
     import numpy as np
@@ -241,17 +357,12 @@ def main():
     check_bytes = (4 * info["check_entries_read"] + 64 * info["check_table_reads"]
                    + 4 * info["accepted"])
     check_gbs = check_bytes / (check_ms / 1e3) / 1e9
-    ex = idx.export()
-    torch.cuda.synchronize()
-    off = ex.offsets.cpu().numpy().view(np.uint64).astype(np.int64)
-    hubs = ex.hubs.cpu().numpy().view(np.uint32)
-    rank = np.empty(g.n, dtype=np.int64)
-    rank[order.astype(np.int64)] = np.arange(g.n)
-    hub_rank = rank[hubs.astype(np.int64)]
-    cons = consumed_entries(off, hub_rank, rank, u.astype(np.int64), v.astype(np.int64))
+    cons = consumed_for(idx, g, order, u, v)
     q_bytes = w["pairs"] * (8 + 32 + 4) + 4 * cons
     q_gbs = q_bytes / (np.median(query_ms) / 1e3) / 1e9
 
+    tr_check = measured_traffic("k_check", args.workload)
+    tr_query = measured_traffic("k_query_group", args.workload)
     res = {
         "metric": "index build s + label entries/s; batched queries/s with p50/p99 latency",
         "value": value,
@@ -277,18 +388,22 @@ def main():
         "build_phase_ms": {k: round(x, 3) for k, x in info["phase_ms"].items()},
         "rounds": info["rounds"], "batches": info["batches"], "candidates": info["candidates"],
         "roofline": {"kernel": "k_check", "bound": "hbm", "achieved": check_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": check_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": check_gbs / HBM_PEAK_GBS,
+                     "traffic": tr_check["bytes"] if tr_check else None,
                      "launches_per_step": check_launches,
                      "avg_launch_us": check_ms * 1e3 / max(check_launches, 1),
                      "bytes_per_step": check_bytes},
-        "roofline_query": {"kernel": "k_query", "bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": q_gbs / HBM_PEAK_GBS, "traffic": None,
+        "roofline_query": {"kernel": "k_query_group", "bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": q_gbs / HBM_PEAK_GBS,
+                           "traffic": tr_query["bytes"] if tr_query else None,
                            "bytes_per_launch": q_bytes, "entries_consumed": cons},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(g, order, total)
     idx.free()
     print(json.dumps(res), flush=True)
+    if args.calibrate:
+        calibrate()
 
 
 if __name__ == "__main__":

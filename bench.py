@@ -146,6 +146,63 @@ def query_mode(args):
     idx.free()
 
 
+def batched_mode(args):
+    """Many-graph build: 256 Barabasi-Albert graphs (n log-uniform in [500,
+    20000], m in {2..8}, each with its own degree order) labeled in one
+    persistent launch per build.  The autotuner picks (batch size, gang
+    scale, largest gang) on these graphs first (cache under --tune-cache);
+    then --steps builds with the chosen parameters are timed end to end
+    (device-resident CSRs; host wall time around each call)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1906_12018_amd as pll
+    from paper_1906_12018_amd import autotune
+
+    dev = torch.device("cuda:0")
+    specs = synth.batching_specs()
+    graphs = [synth.ba_graph(n, m, sd) for n, m, sd in specs]
+    orders = [synth.degree_order(g) for g in graphs]
+    dgs = []
+    for g, o in zip(graphs, orders):
+        rp, cl = pll.graph_to_device(g, dev)
+        dgs.append((rp, cl, torch.from_numpy(o.view(np.int32)).to(dev)))
+    torch.cuda.synchronize()
+    if args.tune_cache:
+        os.environ["PLL_TUNE_CACHE"] = args.tune_cache
+    t0 = time.perf_counter()
+    tuned = autotune.tune_batched(dgs, reps=2, flags=0)
+    tune_s = time.perf_counter() - t0
+    cfg = tuned["best"]
+    ms, total = [], None
+    for it in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        idxs = pll.build_labels_batched(dgs, flags=0, **cfg)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tot = sum(i.info()["total_entries"] for i in idxs)
+        total = tot if total is None else total
+        assert tot == total, "builds disagree"
+        for i in idxs:
+            i.free()
+        if it >= args.warmup:
+            ms.append(dt * 1e3)
+    # the same graphs one call at a time (single-graph path), for reference
+    t0 = time.perf_counter()
+    for rp, cl, od in dgs:
+        pll.build_labels(rp, cl, od, flags=0).free()
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3
+    med = float(np.median(ms))
+    print(json.dumps({"mode": "batched", "workload": "256 BA graphs, n log-uniform [500, 20000], m in {2..8}",
+                      "vertices": int(sum(g.n for g in graphs)), "edges": int(sum(g.num_edges for g in graphs)),
+                      "label_entries": total, "build_ms_p50": med, "entries_per_s": total / (med / 1e3),
+                      "tuned": cfg, "tune_s": tune_s,
+                      "candidates": [{"params": r["params"], "ms": r["seconds"] * 1e3} for r in tuned["results"]],
+                      "sequential_single_graph_ms": seq_ms, "steps": args.steps}), flush=True)
+
+
 def consumed_for(idx, g, order, u, v):
     import numpy as np
     import torch
@@ -212,7 +269,7 @@ def serve_mode(args):
         jobs.append((bg.row_ptr, bg.col, synth.degree_order(bg)))
     pairs = int(sizes[~is_build].sum())
 
-    def run(at):
+    def run(at, with_jobs=True):
         srv = pll.Server(slots=args.serve_slots)
         iid = srv.add_index(idx, take_ownership=False)
         reqs, bi = [], 0
@@ -220,7 +277,8 @@ def serve_mode(args):
             if is_build[i]:
                 rp_, cl_, od_ = jobs[bi]
                 bi += 1
-                reqs.append(pll.Server.build_request(rp_, cl_, od_, at=at[i]))
+                if with_jobs:
+                    reqs.append(pll.Server.build_request(rp_, cl_, od_, at=at[i]))
             else:
                 a, c = int(starts[i]), int(sizes[i])
                 reqs.append(pll.Server.query_request(iid, pu[a:a + c], pv[a:a + c], pout[a:a + c], at=at[i]))
@@ -233,8 +291,10 @@ def serve_mode(args):
         q = [r for r in res if r["kind"] == pll.REQ_QUERY]
         b = [r for r in res if r["kind"] == pll.REQ_BUILD]
         lat = np.array([r["t_done"] - r["t_arrival"] for r in q]) * 1e3
-        out = {"query_requests": len(q), "pairs": pairs, "wall_s": wall, "pairs_per_s": pairs / wall,
-               "query_requests_per_s": len(q) / wall, "p50_ms": float(np.percentile(lat, 50)),
+        qspan = max(r["t_done"] for r in q) - min(r["t_arrival"] for r in q)
+        out = {"query_requests": len(q), "pairs": pairs, "wall_s": wall, "query_span_s": qspan,
+               "pairs_per_s": pairs / qspan, "query_requests_per_s": len(q) / qspan,
+               "p50_ms": float(np.percentile(lat, 50)),
                "p99_ms": float(np.percentile(lat, 99)),
                "mean_requests_per_batch": float(np.mean([r["batch_requests"] for r in q if r["batch_requests"]])),
                "query_errors": int(sum(r["status"] != 0 for r in q))}
@@ -246,12 +306,14 @@ def serve_mode(args):
                         "labeling_errors": int(sum(r["status"] != 0 for r in b))})
         return out
 
-    res, wall = run(np.zeros(N))
-    sat = N / wall
-    levels = {"burst": summarize(res, wall)}
+    # saturation of the query stream: every query request at t = 0, no jobs
+    res, _ = run(np.zeros(N), with_jobs=False)
+    qwall = max(r["t_done"] for r in res) - min(r["t_arrival"] for r in res)
+    sat = len(res) / qwall
+    levels = {"queries_only_burst": summarize(res, qwall)}
     for frac in args.serve_loads:
-        rate = frac * sat
-        gaps = -np.log(1.0 - synth.uniform01(synth.splitmix64(4, 4 * N, N))) / rate
+        rate = frac * sat  # offered rate of query requests; labeling jobs ride on the same arrival process
+        gaps = -np.log(1.0 - synth.uniform01(synth.splitmix64(4, 4 * N, N))) / (rate / (1.0 - args.serve_build_frac))
         at = np.cumsum(gaps) - gaps[0]
         res, wall = run(at)
         key = f"{int(round(frac * 100))}%"
@@ -262,7 +324,7 @@ def serve_mode(args):
     line = {"mode": "serve", "workload": f"rmat{args.serve_scale} index resident; {N} requests, "
             f"{nb} of them labeling jobs; query sizes log-uniform in [1, 65536]",
             "index_entries": info["total_entries"], "label_bytes": info["label_bytes"],
-            "saturation_requests_per_s": sat, "levels": levels, "slots": args.serve_slots,
+            "query_saturation_requests_per_s": sat, "levels": levels, "slots": args.serve_slots,
             "data": "synthetic"}
     print(json.dumps(line), flush=True)
 
@@ -275,7 +337,8 @@ def main():
     ap.add_argument("--workload", default="rmat16", choices=sorted(WORKLOADS))
     ap.add_argument("--batch-size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="build", choices=["build", "query", "serve"])
+    ap.add_argument("--mode", default="build", choices=["build", "query", "batched", "serve"])
+    ap.add_argument("--tune-cache", default="", help="batched mode: autotuner cache file")
     ap.add_argument("--calibrate", action="store_true",
                     help="finish with a 256 MiB read + 256 MiB write elementwise kernel (counter scale)")
     ap.add_argument("--serve-scale", type=int, default=20)
@@ -291,6 +354,9 @@ def main():
 
     if args.mode == "serve":
         serve_mode(args)
+        return
+    if args.mode == "batched":
+        batched_mode(args)
         return
     if args.mode == "query":
         query_mode(args)

@@ -89,7 +89,9 @@ typedef struct {
     uint32_t gang_scale;    /* batched build: percent applied to each graph's work-proportional number of
                                workgroups (0 = 100) */
     uint32_t max_gang;      /* batched build: most workgroups on one graph, 1..16 (0 = 16) */
-    uint32_t reserved[5];   /* must be zero */
+    uint32_t max_workgroups; /* batched build: most workgroups in the persistent launch (0 = as many as fit
+                                on the device at once); a smaller launch leaves room for concurrent work */
+    uint32_t reserved[4];   /* must be zero */
 } pll_build_opts;
 
 typedef struct {
@@ -208,7 +210,9 @@ typedef struct {
     uint32_t build_batch_size; /* b of builds run by the server (0 = 1024) */
     uint64_t max_batch_pairs;  /* pairs per device batch (0 = 1,048,576) */
     uint64_t mem_reserve;      /* device bytes left free when admitting a build (0 = 1 GiB) */
-    uint32_t reserved[4];      /* must be zero */
+    uint32_t build_workgroups; /* max_workgroups of the server's many-graph builds (0 = 128): the rest of the
+                                  device stays free for query batches */
+    uint32_t reserved[3];      /* must be zero */
 } pll_server_opts;
 
 typedef struct {

@@ -51,7 +51,8 @@ class BuildOpts(ctypes.Structure):
         ("query_lanes", ctypes.c_uint32),
         ("gang_scale", ctypes.c_uint32),
         ("max_gang", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 5),
+        ("max_workgroups", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 4),
     ]
 
 
@@ -107,7 +108,8 @@ class ServerOpts(ctypes.Structure):
         ("build_batch_size", ctypes.c_uint32),
         ("max_batch_pairs", ctypes.c_uint64),
         ("mem_reserve", ctypes.c_uint64),
-        ("reserved", ctypes.c_uint32 * 4),
+        ("build_workgroups", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 3),
     ]
 
 
@@ -209,7 +211,7 @@ def _dev(t: torch.Tensor, dtype: torch.dtype, name: str) -> torch.Tensor:
 
 
 def _opts(batch_size: int, flags: int, arena_entries: int, query_lanes: int, gang_scale: int = 0,
-          max_gang: int = 0) -> BuildOpts:
+          max_gang: int = 0, max_workgroups: int = 0) -> BuildOpts:
     o = BuildOpts()
     o.batch_size = batch_size
     o.flags = flags
@@ -217,6 +219,7 @@ def _opts(batch_size: int, flags: int, arena_entries: int, query_lanes: int, gan
     o.query_lanes = query_lanes
     o.gang_scale = gang_scale
     o.max_gang = max_gang
+    o.max_workgroups = max_workgroups
     return o
 
 
@@ -311,7 +314,7 @@ def build_labels(row_ptr: torch.Tensor, col: torch.Tensor, order: torch.Tensor, 
 
 def build_labels_batched(graphs, batch_size: int = DEFAULT_BATCH, flags: int = FLAG_VALIDATE,
                          arena_entries: int = 0, query_lanes: int = 0, gang_scale: int = 0, max_gang: int = 0,
-                         stream=None) -> list:
+                         max_workgroups: int = 0, stream=None) -> list:
     """Build many graphs in one persistent launch; ``graphs`` is a list of
     (row_ptr, col, order) device tensors.  Returns one :class:`Index` per
     graph."""
@@ -328,7 +331,7 @@ def build_labels_batched(graphs, batch_size: int = DEFAULT_BATCH, flags: int = F
         descs[i].d_col = cl.data_ptr()
         descs[i].d_order = od.data_ptr()
     outs = (ctypes.c_void_p * max(len(graphs), 1))()
-    o = _opts(batch_size, flags, arena_entries, query_lanes, gang_scale, max_gang)
+    o = _opts(batch_size, flags, arena_entries, query_lanes, gang_scale, max_gang, max_workgroups)
     rc = load_library().pll_build_labels_batched(len(graphs), descs, ctypes.byref(o), _stream_handle(stream), outs)
     if rc:
         raise PllError(rc, "pll_build_labels_batched")
@@ -350,8 +353,10 @@ class Server:
     Query requests carry host numpy arrays (uint32 ids in, uint32 distances
     out); the server keeps them alive until their results are polled."""
 
-    def __init__(self, slots: int = 4, max_batch_pairs: int = 0, mem_reserve: int = 0, build_batch_size: int = 0):
+    def __init__(self, slots: int = 4, max_batch_pairs: int = 0, mem_reserve: int = 0, build_batch_size: int = 0,
+                 build_workgroups: int = 0):
         o = ServerOpts()
+        o.build_workgroups = build_workgroups
         o.slots = slots
         o.max_batch_pairs = max_batch_pairs
         o.mem_reserve = mem_reserve

@@ -22,9 +22,9 @@ import torch
 from . import DEFAULT_BATCH, FLAG_VALIDATE, build_labels_batched
 
 DEFAULT_CANDIDATES = [
-    dict(batch_size=b, gang_scale=s, max_gang=m)
+    dict(batch_size=b, gang_scale=s, max_gang=16)
     for b in (256, 512, 1024)
-    for s, m in ((50, 16), (100, 16), (200, 16), (400, 16), (100, 4))
+    for s in (200, 400, 800, 1600, 3200)
 ]
 
 

@@ -449,7 +449,7 @@ std::vector<uint32_t> gang_sizes(uint32_t count, const pll_graph_desc* graphs, u
 }
 
 int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint32_t flags, uint32_t scale_pct,
-                  uint32_t max_gang, uint32_t query_lanes, uint64_t arena_total, uint64_t out_cap, hipStream_t caller, pll_index** outs,
+                  uint32_t max_gang, uint32_t query_lanes, uint32_t max_workgroups, uint64_t arena_total, uint64_t out_cap, hipStream_t caller, pll_index** outs,
                   bool* retry) {
     *retry = false;
     // the work runs on a private stream (a capturable one; the caller's may be
@@ -470,8 +470,9 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
 
     const uint32_t W = (b + 63) / 64;
     const uint64_t bstride = 64ull * W;
-    const int resident = resident_for(W);
+    int resident = resident_for(W);
     if (resident <= 0) return PLL_EDEVICE;
+    if (max_workgroups) resident = std::min<int>(resident, (int)max_workgroups);
     const std::vector<uint32_t> G = gang_sizes(count, graphs, (uint32_t)resident, scale_pct, max_gang);
 
     std::vector<GraphJob> jobs(count);
@@ -749,7 +750,7 @@ int pll_build_multi(uint32_t count, const pll_graph_desc* graphs, const pll_buil
     int rc = PLL_OK;
     for (uint32_t attempt = 1; attempt <= 6; ++attempt) {
         bool retry = false;
-        rc = multi_attempt(count, graphs, b, o.flags, scale, o.max_gang, o.query_lanes, arena, out_cap, stream, outs, &retry);
+        rc = multi_attempt(count, graphs, b, o.flags, scale, o.max_gang, o.query_lanes, o.max_workgroups, arena, out_cap, stream, outs, &retry);
         if (rc == PLL_OK) {
             const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             for (uint32_t g = 0; g < count; ++g) {

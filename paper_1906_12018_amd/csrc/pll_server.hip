@@ -249,6 +249,7 @@ struct pll_server {
     }
 
     static constexpr size_t kMaxJobsPerLaunch = 256;
+    static constexpr uint32_t kBuildWorkgroups = 128;  // of 1,024 threads: a quarter of the device's wave slots
     static constexpr uint32_t kLargeGraph = 1u << 16;  // built alone, grid-wide
 
     // device staging for the host CSRs of admitted jobs (grows, kept)
@@ -311,6 +312,7 @@ struct pll_server {
         pll_build_opts o{};
         o.batch_size = b;
         o.flags = PLL_FLAG_VALIDATE;
+        o.max_workgroups = opts.build_workgroups ? opts.build_workgroups : kBuildWorkgroups;
         bool batched = false;
         if (small.size() > 1) {
             std::vector<pll_graph_desc> sd(small.size());
@@ -488,14 +490,14 @@ int pll_server_poll(pll_server* s, pll_result* out, uint32_t max, uint32_t* got,
     std::unique_lock<std::mutex> lk(s->mu);
     if (wait)
         s->done_cv.wait(lk, [s] { return !s->completed.empty() || s->outstanding == 0; });
-    uint32_t k = 0;
-    while (k < max && !s->completed.empty()) {
-        Req* q = s->completed.front();
-        s->completed.erase(s->completed.begin());
-        fill_result(q, &out[k++]);
+    const uint32_t k = (uint32_t)std::min<size_t>(max, s->completed.size());
+    for (uint32_t i = 0; i < k; ++i) {
+        Req* q = s->completed[i];
+        fill_result(q, &out[i]);
         s->all.erase(q->id);
         delete q;
     }
+    s->completed.erase(s->completed.begin(), s->completed.begin() + k);
     *got = k;
     return PLL_OK;
 }
@@ -525,22 +527,24 @@ int pll_server_replay(pll_server* s, uint64_t count, const pll_request* reqs, pl
     for (uint64_t i = 0; i < count; ++i) pos[ids[i]] = i;
     uint64_t left = count;
     std::unique_lock<std::mutex> lk(s->mu);
+    std::vector<Req*> others;  // finished requests that are not this replay's
     while (left) {
         s->done_cv.wait(lk, [s] { return !s->completed.empty(); });
-        for (auto it = s->completed.begin(); it != s->completed.end();) {
-            Req* q = *it;
+        std::vector<Req*> done;
+        done.swap(s->completed);
+        for (Req* q : done) {
             auto p = pos.find(q->id);
             if (p == pos.end()) {
-                ++it;
+                others.push_back(q);
                 continue;
             }
             fill_result(q, &results[p->second]);
-            it = s->completed.erase(it);
             s->all.erase(q->id);
             delete q;
             --left;
         }
     }
+    s->completed.insert(s->completed.begin(), others.begin(), others.end());
     return PLL_OK;
 }
 

@@ -106,6 +106,19 @@ def test_gang_sizes_do_not_change_labels(gang_scale, max_gang):
         assert idx.info()["candidates"] + g.n == want.counters["checks"]
 
 
+def test_small_persistent_launch():
+    """A launch capped at a few workgroups (max_workgroups) still builds
+    every graph exactly: gangs shrink to fit and take graphs in turn."""
+    gs = [synth.ba_graph(3000, 5, 61), synth.ba_graph(700, 2, 62), synth.star_graph(50), synth.ba_graph(1800, 7, 63)]
+    orders = [synth.degree_order(g) for g in gs]
+    for cap in (1, 3):
+        idxs = pll.build_labels_batched([to_dev(g, o) for g, o in zip(gs, orders)], batch_size=256,
+                                        max_workgroups=cap)
+        for g, o, idx in zip(gs, orders, idxs):
+            assert idx.info()["gang"] <= cap
+            assert_labels_equal(idx, oracle.pll_labels(g, o), o)
+
+
 def test_autotuner_picks_a_candidate_and_caches(tmp_path, monkeypatch):
     from paper_1906_12018_amd import autotune
     monkeypatch.setenv("PLL_TUNE_CACHE", str(tmp_path / "tune.json"))

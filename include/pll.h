@@ -67,6 +67,8 @@ extern "C" {
 #define PLL_FLAG_RECHECK 0x2u  /* run the batch-end label-cleaning recheck (Section 5.1) and count what it removes */
 #define PLL_FLAG_RELAXED 0x4u  /* testing: the round check ignores hubs of the current batch; needs PLL_FLAG_RECHECK
                                   to restore the canonical labels */
+#define PLL_FLAG_PERSISTENT 0x10u /* run the batches in one persistent launch with grid-wide barriers between
+                                    phases, instead of one launch per phase and a host read-back per round */
 #define PLL_FLAG_PROFILE 0x8u  /* time each build phase with HIP events on `stream` (pll_index_info.phase_ms) */
 
 /* Build phases timed under PLL_FLAG_PROFILE (indexes into pll_index_info.phase_ms / phase_launches). */
@@ -76,7 +78,9 @@ extern "C" {
 #define PLL_PHASE_CHECK 3    /* gather: pruning checks, appends, next frontier */
 #define PLL_PHASE_END 4      /* batch end: clear C, recheck, sort, clear the table */
 #define PLL_PHASE_FINAL 5    /* finalize: label CSR by vertex id */
-#define PLL_NUM_PHASES 6
+#define PLL_PHASE_LOOP 6     /* PLL_FLAG_PERSISTENT: the batch-loop launches as a whole (INIT..END run inside them
+                                and are then timed with the device wall clock, barrier waits included) */
+#define PLL_NUM_PHASES 7
 
 typedef struct pll_index pll_index;
 

@@ -23,8 +23,8 @@ LIB_PATH = os.path.join(_PKG, "libpll.so")
 
 PLL_OK, PLL_EINVAL, PLL_ENOMEM, PLL_ENOSPC, PLL_EDIST, PLL_EDEVICE = 0, 1, 2, 3, 4, 5
 DIST_INF = 0xFFFFFFFF
-FLAG_VALIDATE, FLAG_RECHECK, FLAG_RELAXED, FLAG_PROFILE = 0x1, 0x2, 0x4, 0x8
-PHASES = ("prep", "init", "push", "check", "end", "final")
+FLAG_VALIDATE, FLAG_RECHECK, FLAG_RELAXED, FLAG_PROFILE, FLAG_PERSISTENT = 0x1, 0x2, 0x4, 0x8, 0x10
+PHASES = ("prep", "init", "push", "check", "end", "final", "loop")
 DEFAULT_BATCH = 1024
 
 EXPORTED_SYMBOLS = (
@@ -76,8 +76,8 @@ class IndexInfo(ctypes.Structure):
         ("build_ms", ctypes.c_double),
         ("check_entries_read", ctypes.c_uint64),
         ("check_table_reads", ctypes.c_uint64),
-        ("phase_ms", ctypes.c_double * 6),
-        ("phase_launches", ctypes.c_uint64 * 6),
+        ("phase_ms", ctypes.c_double * 7),
+        ("phase_launches", ctypes.c_uint64 * 7),
     ]
 
     def as_dict(self) -> dict:
@@ -294,7 +294,8 @@ class Index:
 
 
 def build_labels(row_ptr: torch.Tensor, col: torch.Tensor, order: torch.Tensor, batch_size: int = DEFAULT_BATCH,
-                 flags: int = FLAG_VALIDATE, arena_entries: int = 0, query_lanes: int = 0, stream=None) -> Index:
+                 flags: int = FLAG_VALIDATE, arena_entries: int = 0, query_lanes: int = 0, max_workgroups: int = 0,
+                 stream=None) -> Index:
     """Canonical 2-hop labels of the CSR graph (row_ptr int64 [n+1], col
     int32 [nnz], order int32 [n]: order[k] = vertex of rank k)."""
     row_ptr = _dev(row_ptr, torch.int64, "row_ptr")
@@ -304,7 +305,7 @@ def build_labels(row_ptr: torch.Tensor, col: torch.Tensor, order: torch.Tensor, 
     if row_ptr.numel() != n + 1:
         raise PllError(PLL_EINVAL, "row_ptr must have n+1 entries")
     h = ctypes.c_void_p()
-    o = _opts(batch_size, flags, arena_entries, query_lanes)
+    o = _opts(batch_size, flags, arena_entries, query_lanes, max_workgroups=max_workgroups)
     rc = load_library().pll_build_labels(n, col.numel(), row_ptr.data_ptr(), col.data_ptr(), order.data_ptr(),
                                          ctypes.byref(o), _stream_handle(stream), ctypes.byref(h))
     if rc:

@@ -486,6 +486,7 @@ int read_counters(const DevCounters* d, DevCounters* h, hipStream_t s) {
 }
 
 int device_error_status(uint32_t err) {
+    if (err & PLL_ERR_TIMEOUT) return PLL_EDEVICE;
     if (err & (PLL_ERR_BOUNDS | PLL_ERR_CSR | PLL_ERR_ORDER)) return PLL_EINVAL;
     if (err & PLL_ERR_DIST) return PLL_EDIST;
     if (err & PLL_ERR_ARENA) return PLL_ENOSPC;
@@ -596,8 +597,8 @@ int relayout_arena(DevAllocs& M, BuildArgs& A, uint64_t*& spare_off, uint32_t* c
 
 // One complete build attempt with a given initial arena size.
 int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* order,
-                  uint32_t b, uint32_t flags, uint64_t arena_hint, bool arena_fixed, hipStream_t s,
-                  pll_index* idx, uint64_t* used_arena) {
+                  uint32_t b, uint32_t flags, uint64_t arena_hint, bool arena_fixed, uint32_t max_workgroups,
+                  hipStream_t s, pll_index* idx, uint64_t* used_arena) {
     DevAllocs M;
     HostCounters HC;
     PhaseProfiler P;
@@ -695,8 +696,39 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     const bool trace = trace_env && trace_env[0] == '1';
     unsigned long long last[PLL_NUM_ST] = {};
 
-    // --- batches (a1-a7)
-    for (uint32_t ib = 0; ib < n; ib += b) {
+    // --- batches (a1-a7): one launch per phase with a read-back per round,
+    // or (PLL_FLAG_PERSISTENT) one persistent launch that hands back to the
+    // host only for arena compaction
+    uint32_t grid_workgroups = 0;
+    if (flags & PLL_FLAG_PERSISTENT) {
+        TRY_HIP(hipStreamSynchronize(s));
+        P.resolve();
+        for (uint32_t ib = 0; ib < n;) {
+            BatchRun R{};
+            hipEvent_t l0 = P.mark(), l1 = P.mark();  // recorded again around the launch
+            rc = pll_run_batches(A, ib, b, flags, &bstamp, &rstamp, !arena_fixed, max_workgroups, s, l0, l1, &R);
+            if (rc) return rc;
+            P.span(PLL_PHASE_LOOP, l0, l1, 1);
+            P.resolve();
+            rc = read_counters(ctr, h, s);
+            if (rc) return rc;
+            if (h->error) return device_error_status(h->error);
+            rounds += R.rounds;
+            batches += R.batches;
+            grid_workgroups = R.grid;
+            for (int ph = PLL_PHASE_INIT; ph <= PLL_PHASE_END && P.on; ++ph) {
+                P.ms[ph] += R.ms[ph];
+                P.launches[ph] += R.counts[ph];
+            }
+            if (R.next_ib <= ib) return PLL_EDEVICE;  // no progress: cannot happen
+            ib = R.next_ib;
+            if (ib < n) {
+                rc = relayout_arena(M, A, spare_off, tmp32, scan_scratch, false, A.region_cap * 2, 0, s);
+                if (rc) return rc;
+            }
+        }
+    }
+    for (uint32_t ib = 0; !(flags & PLL_FLAG_PERSISTENT) && ib < n; ib += b) {
         const uint32_t bs = std::min(b, n - ib);
         ++bstamp;
         ++batches;
@@ -803,7 +835,7 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     I.accepted = sum_stat(h, PLL_ST_ACC);
     I.edges_scanned = sum_stat(h, PLL_ST_EDGES);
     I.recheck_removed = sum_stat(h, PLL_ST_RECHECK);
-    I.gang = 1;
+    I.gang = grid_workgroups ? grid_workgroups : 1;
     I.check_entries_read = sum_stat(h, PLL_ST_READ);
     I.check_table_reads = sum_stat(h, PLL_ST_TABLE);
     for (int ph = 0; ph < PLL_NUM_PHASES; ++ph) {
@@ -827,7 +859,8 @@ int pll_build_one(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uin
     const uint32_t b = o.batch_size ? o.batch_size : PLL_BMAX;
     if (b > PLL_BMAX || n >= PLL_MAX_N) return PLL_EINVAL;
     if ((o.flags & PLL_FLAG_RELAXED) && !(o.flags & PLL_FLAG_RECHECK)) return PLL_EINVAL;
-    if (o.flags & ~(PLL_FLAG_VALIDATE | PLL_FLAG_RECHECK | PLL_FLAG_RELAXED | PLL_FLAG_PROFILE)) return PLL_EINVAL;
+    if (o.flags & ~(PLL_FLAG_VALIDATE | PLL_FLAG_RECHECK | PLL_FLAG_RELAXED | PLL_FLAG_PROFILE | PLL_FLAG_PERSISTENT))
+        return PLL_EINVAL;
     const uint32_t ql = o.query_lanes;
     if (!(ql == 0 || ql == 1 || ql == 4 || ql == 8 || ql == 16 || ql == 32 || ql == 64)) return PLL_EINVAL;
     if (n > 0 && (!d_row_ptr || !d_order || (nnz && !d_col))) return PLL_EINVAL;
@@ -865,7 +898,8 @@ int pll_build_one(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uin
         uint64_t cap = fixed ? o.arena_entries : std::max<uint64_t>(1ull << 20, 4 * nnz + 16ull * n);
         for (uint32_t attempt = 1;; ++attempt) {
             uint64_t used = 0;
-            rc = build_attempt(n, nnz, d_row_ptr, d_col, d_order, b, o.flags, cap, fixed, stream, idx, &used);
+            rc = build_attempt(n, nnz, d_row_ptr, d_col, d_order, b, o.flags, cap, fixed, o.max_workgroups, stream,
+                               idx, &used);
             idx->info.build_attempts = attempt;
             idx->info.arena_entries = used;
             if (rc == PLL_ENOSPC && !fixed && attempt < 8) {

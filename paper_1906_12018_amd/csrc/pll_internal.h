@@ -21,6 +21,8 @@ __host__ __device__ inline uint32_t pll_pack(uint32_t hub_rank, uint32_t d) { re
 #define PLL_ERR_BOUNDS 0x4u
 #define PLL_ERR_CSR 0x8u
 #define PLL_ERR_ORDER 0x10u
+#define PLL_ERR_TIMEOUT 0x20u  // a persistent launch waited too long at a barrier
+#define PLL_ERR_STOP 0x40u     // not an error: a persistent launch hands back to the host
 
 // Device-scope atomics on one address serialise (about 12 ns each on
 // MI355X), so every counter that many waves update is split into
@@ -165,6 +167,27 @@ __device__ inline void wave_lds_sync() {
 }
 
 // ---- host helpers --------------------------------------------------------------------------------
+
+// Result of one persistent batch-loop launch (pll_rounds.hip).
+struct BatchRun {
+    uint32_t next_ib;  // first batch not run (n when every batch ran)
+    uint32_t grid;     // workgroups of the launch
+    unsigned long long batches, rounds;
+    double ms[PLL_NUM_PHASES];                 // device wall-clock time per phase
+    unsigned long long counts[PLL_NUM_PHASES];  // phase instances
+};
+
+// Run batches from ib0 on in one persistent launch (stamps continue from
+// *bstamp / *rstamp and are updated); stops early after a batch whose arena
+// region is half used when `compact` is set.  Synchronous on `s`.
+// ev_begin / ev_end (may be null) are recorded on `s` right around the launch.
+int pll_run_batches(const BuildArgs& A, uint32_t ib0, uint32_t b, uint32_t flags, uint32_t* bstamp,
+                    uint32_t* rstamp, bool compact, uint32_t max_workgroups, hipStream_t s, hipEvent_t ev_begin,
+                    hipEvent_t ev_end, BatchRun* out);
+
+// Persistent launches of this process are serialised by this mutex.
+#include <mutex>
+std::mutex& pll_persistent_mutex();
 
 int pll_build_one(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
                   const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out);

@@ -29,7 +29,6 @@ using pll::PhaseStats;
 constexpr int kMultiBlock = 1024;  // 16 waves per workgroup
 constexpr int kMultiWaves = kMultiBlock / PLL_WAVE;
 constexpr uint32_t kMaxGang = 16;
-constexpr uint32_t PLL_ERR_TIMEOUT = 0x20u;
 
 // Per-graph gang control block (zero-filled before the launch).
 struct alignas(128) GangCtl {
@@ -632,8 +631,13 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
             rc = PLL_EDEVICE;
             break;
         }
-        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess ||
-            hipGraphLaunch(exec, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            rc = PLL_EDEVICE;
+            break;
+        }
+        // persistent launches of this process run one at a time
+        std::lock_guard<std::mutex> lock(pll_persistent_mutex());
+        if (hipGraphLaunch(exec, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
             rc = PLL_EDEVICE;
             break;
         }

@@ -200,3 +200,40 @@ def test_query_on_side_stream():
         out = idx.query(du, dv, stream=s)
     s.synchronize()
     assert np.array_equal(out.cpu().numpy().view(np.uint32), oracle.query(want, u, v))
+
+
+@pytest.mark.parametrize("b", [5, 130])
+@pytest.mark.parametrize("gi", range(len(small_cases())))
+def test_persistent_rounds_match(gi, b):
+    """The persistent batch loop (PLL_FLAG_PERSISTENT: one launch, grid
+    barriers between phases) gives the oracle's labels and the same counters
+    as the per-phase launches."""
+    g = small_cases()[gi]
+    order = synth.degree_order(g)
+    want = oracle.pll_labels(g, order)
+    idx = build(g, order, batch_size=b, flags=pll.FLAG_VALIDATE | pll.FLAG_PERSISTENT)
+    assert_labels_equal(idx, want, order)
+    check_counters(idx, g, order, b, want)
+    idx.free()
+
+
+@pytest.mark.parametrize("cap", [1, 2, 7])
+def test_persistent_loop_with_few_workgroups(cap):
+    """The grid barrier with fewer workgroups than barrier shards, and a
+    single workgroup doing every phase."""
+    g = synth.ba_graph(2000, 4, 1)
+    order = synth.degree_order(g)
+    want = oracle.pll_labels(g, order)
+    idx = build(g, order, batch_size=300, max_workgroups=cap, flags=pll.FLAG_VALIDATE | pll.FLAG_PERSISTENT)
+    assert idx.info()["gang"] == cap
+    assert_labels_equal(idx, want, order)
+    check_counters(idx, g, order, 300, want)
+
+
+def test_persistent_flag_is_accepted_and_unknown_flags_are_not():
+    g = synth.ba_graph(100, 2, 1)
+    order = synth.degree_order(g)
+    build(g, order, flags=pll.FLAG_PERSISTENT).free()
+    with pytest.raises(pll.PllError) as e:
+        build(g, order, flags=0x400)
+    assert e.value.status == pll.PLL_EINVAL

@@ -44,3 +44,13 @@ def test_rmat16_queries_match_bfs_sample(rmat16):
         d = oracle.bfs(g, int(s))
         got = gpu_query(idx, np.full(g.n, s, dtype=np.uint32), np.arange(g.n, dtype=np.uint32))
         assert np.array_equal(got, d)
+
+
+def test_rmat16_persistent_loop(rmat16):
+    """The persistent batch loop on the full graph, including its hand-backs
+    to the host for label-arena compaction."""
+    g, order, want = rmat16
+    idx = build(g, order, batch_size=1024, flags=pll.FLAG_PROFILE | pll.FLAG_PERSISTENT)
+    assert_labels_equal(idx, want, order)
+    info = check_counters(idx, g, order, 1024, want)
+    assert info["phase_launches"]["loop"] >= 1

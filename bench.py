@@ -5,7 +5,11 @@ One step = one full label build (pll_build_labels: checks, relabel, every
 batch and round, finalize) of the R-MAT scale-16 graph (65,536 vertices, edge
 factor 16, a,b,c,d = .57,.19,.19,.05, seed 1, degree order, b = 1024) from a
 device-resident CSR, followed by one batched query of 10^6 uniform pairs
-(seed 2).  Prints one JSON line.
+(seed 2).  Prints one JSON line.  The timed steps build without per-phase
+events; --steps profiled builds follow, and their HIP events give the
+kernel times of the roofline entry.  Other modes: --mode query (queries
+alone), --mode batched (the 256-graph one-launch build), --mode serve (the
+serving loop), each printing its own JSON line.
 """
 from __future__ import annotations
 
@@ -381,14 +385,16 @@ def main():
     out = torch.empty_like(du)
     torch.cuda.synchronize()
 
-    flags = pll.FLAG_PROFILE
+    # timed steps: builds without per-phase events (the events add about a
+    # fifth to an R-MAT-16 build); then the same number of profiled builds
+    # whose HIP events on the build stream give the per-kernel times
     build_ms, query_ms, step_ms, infos = [], [], [], []
     ref = None
     for it in range(args.warmup + args.steps):
         timed = it >= args.warmup
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        idx = pll.build_labels(rp, cl, od, batch_size=args.batch_size, flags=flags)
+        idx = pll.build_labels(rp, cl, od, batch_size=args.batch_size, flags=0)
         t1 = time.perf_counter()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -408,8 +414,14 @@ def main():
             infos.append(info)
         if it < args.warmup + args.steps - 1:
             idx.free()
+    prof = []
+    for _ in range(args.steps):
+        pidx = pll.build_labels(rp, cl, od, batch_size=args.batch_size, flags=pll.FLAG_PROFILE)
+        prof.append(pidx.info())
+        assert prof[-1]["total_entries"] == ref[0], "profiled build disagrees"
+        pidx.free()
 
-    info = infos[-1]
+    info = prof[-1]
     total = info["total_entries"]
     K = args.steps
     sum_build_s = sum(build_ms) / 1e3
@@ -418,7 +430,7 @@ def main():
 
     # roofline, dominant kernel: the pruning check (k_check), bytes per the
     # kernel's traffic model, time from HIP events on the build stream
-    check_ms = np.mean([i["phase_ms"]["check"] for i in infos])
+    check_ms = np.mean([i["phase_ms"]["check"] for i in prof])
     check_launches = info["phase_launches"]["check"]
     check_bytes = (4 * info["check_entries_read"] + 64 * info["check_table_reads"]
                    + 4 * info["accepted"])
@@ -452,13 +464,16 @@ def main():
         "query_batch_ms_p50": float(np.percentile(query_ms, 50)),
         "query_batch_ms_p99": float(np.percentile(query_ms, 99)),
         "build_phase_ms": {k: round(x, 3) for k, x in info["phase_ms"].items()},
+        "profiled_build_s": float(np.median([i["build_ms"] for i in prof]) / 1e3),
         "rounds": info["rounds"], "batches": info["batches"], "candidates": info["candidates"],
         "roofline": {"kernel": "k_check", "bound": "hbm", "achieved": check_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": check_gbs / HBM_PEAK_GBS,
                      "traffic": tr_check["bytes"] if tr_check else None,
                      "launches_per_step": check_launches,
                      "avg_launch_us": check_ms * 1e3 / max(check_launches, 1),
-                     "bytes_per_step": check_bytes},
+                     "bytes_per_step": check_bytes,
+                     "timing": "HIP events around every k_check launch on the build stream, over --steps "
+                               "profiled builds run right after the timed steps"},
         "roofline_query": {"kernel": "k_query_group", "bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": q_gbs / HBM_PEAK_GBS,
                            "traffic": tr_query["bytes"] if tr_query else None,

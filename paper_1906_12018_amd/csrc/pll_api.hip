@@ -22,10 +22,17 @@ void free_index(pll_index* idx) {
     int cur = -1;
     bool switched = false;
     if (hipGetDevice(&cur) == hipSuccess && cur != idx->device) switched = hipSetDevice(idx->device) == hipSuccess;
-    (void)hipFree(idx->d_off);
-    (void)hipFree(idx->d_order);
+    if (idx->meta) {
+        if (idx->meta->refs.fetch_sub(1) == 1) {
+            (void)hipFree(idx->meta->ptr);
+            delete idx->meta;
+        }
+    } else {
+        (void)hipFree(idx->d_off);
+        (void)hipFree(idx->d_order);
+    }
     if (idx->store) {
-        if (--idx->store->refs == 0) {
+        if (idx->store->refs.fetch_sub(1) == 1) {
             (void)hipFree(idx->store->ptr);
             delete idx->store;
         }

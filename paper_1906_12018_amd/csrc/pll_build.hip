@@ -378,33 +378,47 @@ __global__ void __launch_bounds__(kBlock) k_final_copy(uint32_t n, const uint32_
 
 // ---- host driver --------------------------------------------------------------------------------
 
+// Buffers of one build: workspace from the caching allocator (returned once
+// the stream has drained), outputs from hipMalloc (kept with forget()).
 struct DevAllocs {
-    std::vector<void*> ptrs;
+    std::vector<void*> ws, outs;
+    hipStream_t s = nullptr;
     hipError_t err = hipSuccess;
     template <class T>
     T* get(size_t count) {
         if (err != hipSuccess) return nullptr;
         void* p = nullptr;
-        size_t bytes = count * sizeof(T);
-        if (bytes < 256) bytes = 256;
-        err = hipMalloc(&p, bytes);
+        err = pll_ws_alloc(&p, std::max<size_t>(count * sizeof(T), 256));
         if (err != hipSuccess) return nullptr;
-        ptrs.push_back(p);
+        ws.push_back(p);
+        return static_cast<T*>(p);
+    }
+    template <class T>
+    T* get_out(size_t count) {
+        if (err != hipSuccess) return nullptr;
+        void* p = nullptr;
+        err = hipMalloc(&p, std::max<size_t>(count * sizeof(T), 256));
+        if (err != hipSuccess) return nullptr;
+        outs.push_back(p);
         return static_cast<T*>(p);
     }
     void forget(void* p) {
-        for (auto& q : ptrs)
+        for (auto& q : outs)
             if (q == p) q = nullptr;
     }
+    // return a workspace block early (the stream must have drained)
     void drop(void* p) {
-        for (auto& q : ptrs)
+        for (auto& q : ws)
             if (q == p) {
-                (void)hipFree(q);
+                pll_ws_free(q);
                 q = nullptr;
             }
     }
     ~DevAllocs() {
-        for (void* p : ptrs)
+        (void)hipStreamSynchronize(s);
+        for (void* p : ws)
+            if (p) pll_ws_free(p);
+        for (void* p : outs)
             if (p) (void)hipFree(p);
     }
 };
@@ -420,7 +434,7 @@ inline int status_of(hipError_t e) { return e == hipErrorOutOfMemory ? PLL_ENOME
 struct HostCounters {
     DevCounters* p = nullptr;
     ~HostCounters() {
-        if (p) (void)hipHostFree(p);
+        if (p) pll_pinned_free(p);
     }
 };
 
@@ -600,11 +614,12 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
                   uint32_t b, uint32_t flags, uint64_t arena_hint, bool arena_fixed, uint32_t max_workgroups,
                   hipStream_t s, pll_index* idx, uint64_t* used_arena) {
     DevAllocs M;
+    M.s = s;
     HostCounters HC;
     PhaseProfiler P;
     P.on = (flags & PLL_FLAG_PROFILE) != 0;
     P.s = s;
-    TRY_HIP(hipHostMalloc((void**)&HC.p, sizeof(DevCounters), hipHostMallocDefault));
+    TRY_HIP(pll_pinned_alloc((void**)&HC.p, sizeof(DevCounters)));
     DevCounters* h = HC.p;
     const uint32_t W = (b + 63) / 64;
     const uint32_t bstride = 64 * W;
@@ -795,15 +810,15 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     P.resolve();
     hipEvent_t e_fin = P.mark();
     k_final_lens<<<blocks_for_threads(n), kBlock, 0, s>>>(n, rank, A.llen, tmp32, ctr);
-    uint64_t* d_off = M.get<uint64_t>((size_t)n + 1);
+    uint64_t* d_off = M.get_out<uint64_t>((size_t)n + 1);
     if (M.err != hipSuccess) return status_of(M.err);
     TRY_HIP(scan_u32_to_u64(tmp32, n, d_off, scan_scratch, s));
     uint64_t total = 0;
     TRY_HIP(hipMemcpyAsync(&total, d_off + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     TRY_HIP(hipStreamSynchronize(s));
     // whole 4-entry chunks: the query kernel reads labels in aligned 16-byte loads
-    uint32_t* d_ent = M.get<uint32_t>(std::max<uint64_t>((total + 3) & ~3ull, 4));
-    uint32_t* d_order = M.get<uint32_t>(n);
+    uint32_t* d_ent = M.get_out<uint32_t>(std::max<uint64_t>((total + 3) & ~3ull, 4));
+    uint32_t* d_order = M.get_out<uint32_t>(n);
     if (M.err != hipSuccess) return status_of(M.err);
     k_final_copy<<<std::min<uint32_t>(blocks_for_waves(n), 1024), kBlock, 0, s>>>(n, rank, A.loff, A.llen, A.arena,
                                                                                    d_off, d_ent, ctr);
@@ -877,9 +892,10 @@ int pll_build_one(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uin
     int rc = PLL_OK;
     if (n == 0) {
         DevAllocs M;
-        idx->d_off = M.get<uint64_t>(1);
-        idx->d_ent = M.get<uint32_t>(4);
-        idx->d_order = M.get<uint32_t>(1);
+        M.s = stream;
+        idx->d_off = M.get_out<uint64_t>(1);
+        idx->d_ent = M.get_out<uint32_t>(4);
+        idx->d_order = M.get_out<uint32_t>(1);
         if (M.err != hipSuccess) {
             rc = status_of(M.err);
         } else if (hipMemsetAsync(idx->d_off, 0, sizeof(uint64_t), stream) != hipSuccess ||

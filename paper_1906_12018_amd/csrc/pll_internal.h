@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "pll.h"
 
 #define PLL_WAVE 64
@@ -185,6 +187,15 @@ int pll_run_batches(const BuildArgs& A, uint32_t ib0, uint32_t b, uint32_t flags
                     uint32_t* rstamp, bool compact, uint32_t max_workgroups, hipStream_t s, hipEvent_t ev_begin,
                     hipEvent_t ev_end, BatchRun* out);
 
+// Caching allocators (pll_alloc.hip).  A workspace block goes back with
+// pll_ws_free only after the work using it has completed; index outputs are
+// plain hipMalloc memory (indexes free them with hipFree).
+hipError_t pll_ws_alloc(void** out, size_t bytes);
+void pll_ws_free(void* p);
+size_t pll_ws_cached(int device);  // bytes held in the cache of a device
+hipError_t pll_pinned_alloc(void** out, size_t bytes);
+void pll_pinned_free(void* p);
+
 // Persistent launches of this process are serialised by this mutex.
 #include <mutex>
 std::mutex& pll_persistent_mutex();
@@ -201,7 +212,7 @@ int pll_build_multi(uint32_t count, const pll_graph_desc* graphs, const pll_buil
 // released when the last of those indexes is freed.
 struct pll_shared_store {
     void* ptr;
-    int refs;
+    std::atomic<int> refs;  // indexes still using it (they may be freed from different threads)
     int device;
 };
 
@@ -215,5 +226,6 @@ struct pll_index {
     uint32_t* d_order;  // [n], rank -> vertex id
     uint32_t query_lanes;
     pll_shared_store* store;  // non-null when d_ent points into a shared allocation
+    pll_shared_store* meta;   // non-null when d_off and d_order point into a shared allocation
     pll_index_info info;
 };

@@ -375,10 +375,15 @@ __global__ void k_fill32(uint32_t* p, uint64_t words, uint32_t value) {
         p[i] = value;
 }
 
+// Workspace block of one launch, returned to the cache once the launch's
+// stream has drained.
 struct Buf {
     void* p = nullptr;
+    hipStream_t* s = nullptr;
     ~Buf() {
-        if (p) (void)hipFree(p);
+        if (!p) return;
+        if (s && *s) (void)hipStreamSynchronize(*s);
+        pll_ws_free(p);
     }
 };
 
@@ -451,20 +456,28 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
                   uint32_t max_gang, uint32_t query_lanes, uint32_t max_workgroups, uint64_t arena_total, uint64_t out_cap, hipStream_t caller, pll_index** outs,
                   bool* retry) {
     *retry = false;
-    // the work runs on a private stream (a capturable one; the caller's may be
-    // the legacy default stream) ordered after the caller's pending work
+    // the work is captured on the caller's stream, or, for the legacy
+    // default stream (which cannot be captured), on a private stream ordered
+    // after the caller's pending work.  No extra stream otherwise: streams
+    // beyond the hardware queues share one, and work behind a long launch waits.
     struct StreamGuard {
         hipStream_t s = nullptr;
         hipEvent_t e = nullptr;
+        bool own = false;
         ~StreamGuard() {
             if (e) (void)hipEventDestroy(e);
-            if (s) (void)hipStreamDestroy(s);
+            if (own && s) (void)hipStreamDestroy(s);
         }
     } SG;
-    if (hipStreamCreateWithFlags(&SG.s, hipStreamNonBlocking) != hipSuccess) return PLL_EDEVICE;
-    if (hipEventCreateWithFlags(&SG.e, hipEventDisableTiming) != hipSuccess) return PLL_EDEVICE;
-    if (hipEventRecord(SG.e, caller) != hipSuccess || hipStreamWaitEvent(SG.s, SG.e, 0) != hipSuccess)
-        return PLL_EDEVICE;
+    if (caller) {
+        SG.s = caller;
+    } else {
+        SG.own = true;
+        if (hipStreamCreateWithFlags(&SG.s, hipStreamNonBlocking) != hipSuccess) return PLL_EDEVICE;
+        if (hipEventCreateWithFlags(&SG.e, hipEventDisableTiming) != hipSuccess) return PLL_EDEVICE;
+        if (hipEventRecord(SG.e, caller) != hipSuccess || hipStreamWaitEvent(SG.s, SG.e, 0) != hipSuccess)
+            return PLL_EDEVICE;
+    }
     hipStream_t s = SG.s;
 
     const uint32_t W = (b + 63) / 64;
@@ -532,36 +545,45 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
     for (uint32_t g : gorder)
         for (uint32_t m = 0; m < G[g]; ++m) slots.push_back(make_uint2(g, m));
 
-    Buf Z, TT, O, JB, SL, RS, CT, DC, AR, OUT;
+    Buf Z, TT, O, JB, SL, RS, CT, DC, AR;
+    for (Buf* bf : {&Z, &TT, &O, &JB, &SL, &RS, &CT, &DC, &AR}) bf->s = &SG.s;
     const uint64_t region_cap = std::max<uint64_t>(4096, arena_total / PLL_SHARDS);
-    if (hipMalloc(&Z.p, std::max<uint64_t>(zb, 256)) != hipSuccess ||
-        hipMalloc(&TT.p, std::max<uint64_t>(tb, 256)) != hipSuccess ||
-        hipMalloc(&O.p, std::max<uint64_t>(ob, 256)) != hipSuccess ||
-        hipMalloc(&AR.p, sizeof(uint32_t) * region_cap * PLL_SHARDS) != hipSuccess ||
-        hipMalloc(&OUT.p, sizeof(uint32_t) * std::max<uint64_t>(out_cap, 64)) != hipSuccess ||
-        hipMalloc(&JB.p, sizeof(GraphJob) * count) != hipSuccess ||
-        hipMalloc(&SL.p, sizeof(uint2) * slots.size()) != hipSuccess ||
-        hipMalloc(&RS.p, sizeof(GraphResult) * count) != hipSuccess || hipMalloc(&CT.p, sizeof(MultiCtl)) != hipSuccess ||
-        hipMalloc(&DC.p, sizeof(DevCounters)) != hipSuccess)
+    if (pll_ws_alloc(&Z.p, std::max<uint64_t>(zb, 256)) != hipSuccess ||
+        pll_ws_alloc(&TT.p, std::max<uint64_t>(tb, 256)) != hipSuccess ||
+        pll_ws_alloc(&O.p, std::max<uint64_t>(ob, 256)) != hipSuccess ||
+        pll_ws_alloc(&AR.p, sizeof(uint32_t) * region_cap * PLL_SHARDS) != hipSuccess ||
+        pll_ws_alloc(&JB.p, sizeof(GraphJob) * count) != hipSuccess ||
+        pll_ws_alloc(&SL.p, sizeof(uint2) * slots.size()) != hipSuccess ||
+        pll_ws_alloc(&RS.p, sizeof(GraphResult) * count) != hipSuccess ||
+        pll_ws_alloc(&CT.p, sizeof(MultiCtl)) != hipSuccess || pll_ws_alloc(&DC.p, sizeof(DevCounters)) != hipSuccess)
         return PLL_ENOMEM;
+    // outputs the indexes keep: the label store, and one block holding every
+    // graph's offsets and order (both shared, reference-counted)
+    struct OutMem {
+        void* p = nullptr;
+        hipStream_t* s = nullptr;
+        ~OutMem() {
+            if (!p) return;
+            if (s && *s) (void)hipStreamSynchronize(*s);
+            (void)hipFree(p);
+        }
+    } OUT, META;
+    OUT.s = META.s = &SG.s;
+    if (hipMalloc(&OUT.p, sizeof(uint32_t) * std::max<uint64_t>(out_cap, 64)) != hipSuccess) return PLL_ENOMEM;
+    uint64_t meta_bytes = 0;
+    for (uint32_t g = 0; g < count; ++g)
+        meta_bytes += align_up(8 * ((uint64_t)graphs[g].n + 1), 256) + align_up(4 * std::max<uint64_t>(graphs[g].n, 1), 256);
+    if (hipMalloc(&META.p, std::max<uint64_t>(meta_bytes, 256)) != hipSuccess) return PLL_ENOMEM;
     std::vector<uint64_t*> out_offs(count, nullptr);
     std::vector<uint32_t*> orders(count, nullptr);
-    struct OutGuard {
-        std::vector<uint64_t*>& a;
-        std::vector<uint32_t*>& b;
-        bool keep = false;
-        ~OutGuard() {
-            if (keep) return;
-            for (auto* p : a)
-                if (p) (void)hipFree(p);
-            for (auto* p : b)
-                if (p) (void)hipFree(p);
+    {
+        char* mp = (char*)META.p;
+        for (uint32_t g = 0; g < count; ++g) {
+            out_offs[g] = (uint64_t*)mp;
+            mp += align_up(8 * ((uint64_t)graphs[g].n + 1), 256);
+            orders[g] = (uint32_t*)mp;
+            mp += align_up(4 * std::max<uint64_t>(graphs[g].n, 1), 256);
         }
-    } OG{out_offs, orders};
-    for (uint32_t g = 0; g < count; ++g) {
-        if (hipMalloc((void**)&out_offs[g], 8 * ((uint64_t)graphs[g].n + 1)) != hipSuccess ||
-            hipMalloc((void**)&orders[g], 4 * std::max<uint64_t>(graphs[g].n, 1)) != hipSuccess)
-            return PLL_ENOMEM;
     }
     char* zp = (char*)Z.p;
     char* tp = (char*)TT.p;
@@ -675,8 +697,11 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
         }
     }
     pll_shared_store* store = new (std::nothrow) pll_shared_store{};
-    if (!store) {
+    pll_shared_store* meta = new (std::nothrow) pll_shared_store{};
+    if (!store || !meta) {
         for (auto* p : made) delete p;
+        delete store;
+        delete meta;
         return PLL_ENOMEM;
     }
     int dev = 0;
@@ -685,7 +710,10 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
     store->refs = (int)count;
     store->device = dev;
     OUT.p = nullptr;
-    OG.keep = true;
+    meta->ptr = META.p;
+    meta->refs = (int)count;
+    meta->device = dev;
+    META.p = nullptr;
     for (uint32_t g = 0; g < count; ++g) {
         pll_index* idx = made[g];
         const GraphResult& R = res[g];
@@ -696,6 +724,7 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
         idx->d_ent = (uint32_t*)store->ptr + R.out_base;
         idx->d_order = orders[g];
         idx->store = store;
+        idx->meta = meta;
         idx->query_lanes = query_lanes;
         pll_index_info& I = idx->info;
         I.n = graphs[g].n;

@@ -316,10 +316,10 @@ int pll_run_batches(const BuildArgs& A, uint32_t ib0, uint32_t b, uint32_t flags
     const uint64_t timeout_ticks = (uint64_t)khz * 1000ull * 30ull;  // 30 s of waiting at one barrier
 
     GridCtl* gc = nullptr;
-    if (hipMalloc((void**)&gc, sizeof(GridCtl)) != hipSuccess) return PLL_ENOMEM;
+    if (pll_ws_alloc((void**)&gc, sizeof(GridCtl)) != hipSuccess) return PLL_ENOMEM;
     GridCtl* h = nullptr;
-    if (hipHostMalloc((void**)&h, sizeof(GridCtl), hipHostMallocDefault) != hipSuccess) {
-        (void)hipFree(gc);
+    if (pll_pinned_alloc((void**)&h, sizeof(GridCtl)) != hipSuccess) {
+        pll_ws_free(gc);
         return PLL_ENOMEM;
     }
     int rc = PLL_OK;
@@ -355,7 +355,8 @@ int pll_run_batches(const BuildArgs& A, uint32_t ib0, uint32_t b, uint32_t flags
         *bstamp = h->bstamp;
         *rstamp = h->rstamp;
     }
-    (void)hipHostFree(h);
-    (void)hipFree(gc);
+    (void)hipStreamSynchronize(s);
+    pll_pinned_free(h);
+    pll_ws_free(gc);
     return rc;
 }

@@ -211,6 +211,7 @@ struct pll_server {
             size_t free_b = 0, total_b = 0;
             lk.unlock();
             const bool info_ok = hipMemGetInfo(&free_b, &total_b) == hipSuccess;
+            free_b += pll_ws_cached(device);  // cached build workspace is free for builds
             lk.lock();
             std::vector<Req*> take;
             uint64_t need_sum = opts.mem_reserve;

@@ -109,7 +109,7 @@ class Labels:
         return np.asarray(order, dtype=np.uint32)[self.hub_rank]
 
 
-_COUNTER_NAMES = ["checks", "added", "edge_accesses", "rounds", "batches", "scanned"]
+_COUNTER_NAMES = ["checks", "added", "edge_accesses", "rounds", "batches", "scanned", "cost_pos", "cost_neg"]
 
 
 def _take(c: _CLabels) -> Labels:

@@ -47,7 +47,10 @@ typedef struct {
     uint8_t* dist;       /* total */
     /* counters: [0] distance checks (BFS pops / candidate messages),
      *           [1] entries added, [2] edge accesses, [3] rounds (BVC),
-     *           [4] batches (BVC), [5] entries scanned by checks */
+     *           [4] batches (BVC), [5] entries scanned by checks,
+     *           [6] / [7] cost of the positive / negative checks: the sum of
+     *           |L(v)| at the time of each check that added / pruned
+     *           (Section 4.3, the quantities of Table 3) */
     uint64_t counters[8];
 } oracle_labels;
 
@@ -290,7 +293,7 @@ int oracle_pll(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const u
     if (!L || !T || !visited || !qv || !qd) { rc = ORACLE_ENOMEM; goto done; }
     memset(T, INF8, n);
     for (uint32_t i = 0; i < n; ++i) visited[i] = DIST_INF;
-    uint64_t checks = 0, added = 0, edges = 0, scanned = 0;
+    uint64_t checks = 0, added = 0, edges = 0, scanned = 0, cost_pos = 0, cost_neg = 0;
     for (uint32_t k = 0; k < n && !rc; ++k) {
         uint32_t u = order[k];
         vlist* Lu = &L[u];
@@ -310,6 +313,7 @@ int oracle_pll(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const u
             }
             scanned += Lv->len;
             if (delta < m) {
+                cost_pos += Lv->len;
                 if (delta >= INF8) { rc = ORACLE_EDIST; break; }
                 rc = vlist_push(Lv, k, delta);
                 if (rc) break;
@@ -322,6 +326,8 @@ int oracle_pll(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const u
                         qv[tail] = w; qd[tail] = delta + 1; tail++;
                     }
                 }
+            } else {
+                cost_neg += Lv->len;
             }
         }
         /* L(u) may have grown by (u,0) during this BFS; clear every hub it holds. */
@@ -334,6 +340,8 @@ int oracle_pll(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const u
         out->counters[1] = added;
         out->counters[2] = edges;
         out->counters[5] = scanned;
+        out->counters[6] = cost_pos;
+        out->counters[7] = cost_neg;
     }
 done:
     if (L) vlists_free(L, n);
@@ -391,7 +399,7 @@ int oracle_bvc(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const u
         goto done;
     }
     memset(H, INF8, (size_t)b * n);
-    uint64_t checks = 0, added = 0, edges = 0, rounds = 0, batches = 0, scanned = 0;
+    uint64_t checks = 0, added = 0, edges = 0, rounds = 0, batches = 0, scanned = 0, cost_pos = 0, cost_neg = 0;
     for (uint32_t ib = 0; ib < n && !rc; ib += b) {
         uint32_t bs = (n - ib < b) ? n - ib : b;
         batches++;
@@ -454,7 +462,10 @@ int oracle_bvc(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const u
                     }
                     scanned += len_before;
                     if (j < m) {
+                        cost_pos += len_before;
                         if ((rc = ulist_push(&delta[v], k))) break;
+                    } else {
+                        cost_neg += len_before;
                     }
                 }
                 msgs[v].len = 0;
@@ -497,6 +508,8 @@ int oracle_bvc(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const u
         out->counters[3] = rounds;
         out->counters[4] = batches;
         out->counters[5] = scanned;
+        out->counters[6] = cost_pos;
+        out->counters[7] = cost_neg;
     }
 done:
     if (L) vlists_free(L, n);

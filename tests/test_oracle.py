@@ -274,3 +274,72 @@ def test_pll_matches_def2_sample_rmat16():
         h, d = c.of(i)
         ph, pd = lab.of(int(v))
         assert np.array_equal(h, ph) and np.array_equal(d, pd)
+
+
+# ---- cost-model counters (Section 4.3, Theorem 3, Table 3) -------------------------------------------------------
+
+def _lists_by_rank(lab: oracle.Labels, order):
+    """(hub ranks, dists) of every list, indexed by the owner's rank."""
+    n = len(order)
+    out = [None] * n
+    for vid in range(n):
+        h, d = lab.of(vid)
+        out[vid] = (h.astype(np.int64), d.astype(np.int64))
+    rank = np.empty(n, dtype=np.int64)
+    rank[order.astype(np.int64)] = np.arange(n)
+    return [(rank[v], out[v][0], out[v][1]) for v in range(n)]
+
+
+def pll_positive_cost(lab: oracle.Labels):
+    """PLL adds the entries of L(v) in ascending hub rank, each after a check
+    whose cost is the number of entries already there: 0 + 1 + ... + (l-1)."""
+    sz = lab.sizes()
+    return int((sz * (sz - 1) // 2).sum())
+
+
+def bvc_positive_cost(lab: oracle.Labels, order, b):
+    """BVC-PLL adds the entry (h, d) of L(v), h in batch i, after a check that
+    sees every entry of earlier batches and the entries of batch i at a
+    smaller distance (the groups g_1..g_{k-1} of Theorem 3's proof); the
+    self entry (v, 0) is added without a check."""
+    total = 0
+    for rv, h, d in _lists_by_rank(lab, order):
+        bt = h // b
+        for i in range(len(h)):
+            if h[i] == rv:
+                continue
+            earlier = int((bt < bt[i]).sum())
+            same = int(((bt == bt[i]) & (d < d[i])).sum())
+            total += earlier + same
+    return total
+
+
+@pytest.mark.parametrize("gi", range(len(small_graphs())))
+def test_check_costs_match_closed_forms(gi):
+    g = small_graphs()[gi]
+    order = synth.degree_order(g)
+    p = oracle.pll_labels(g, order)
+    assert p.counters["cost_pos"] == pll_positive_cost(p)
+    assert p.counters["cost_pos"] + p.counters["cost_neg"] == p.counters["scanned"]
+    for b in (1, 2, 3, max(g.n, 1)):
+        bv = oracle.bvc_labels(g, order, b)
+        assert bv.counters["cost_pos"] == bvc_positive_cost(bv, order, b), b
+        assert bv.counters["cost_pos"] + bv.counters["cost_neg"] == bv.counters["scanned"]
+        # Theorem 3: the positive checks of BVC-PLL cost no more than PLL's
+        assert bv.counters["cost_pos"] <= p.counters["cost_pos"]
+
+
+def test_check_costs_ba_and_b1_reduces_to_pll():
+    """With b = 1 every batch is one root: the negative checks and their costs
+    are PLL's, and the positive ones differ only by PLL's n self checks,
+    which see every other entry of L(v) (l_v - 1 each)."""
+    g = synth.ba_graph(600, 3, 9)
+    order = synth.degree_order(g)
+    p = oracle.pll_labels(g, order)
+    b1 = oracle.bvc_labels(g, order, 1)
+    assert b1.counters["cost_neg"] == p.counters["cost_neg"]
+    assert b1.counters["cost_pos"] == p.counters["cost_pos"] - int((p.sizes() - 1).sum())
+    for b in (16, 100, 1024):
+        bv = oracle.bvc_labels(g, order, b)
+        assert bv.counters["cost_pos"] == bvc_positive_cost(bv, order, b)
+        assert bv.counters["cost_pos"] <= p.counters["cost_pos"]

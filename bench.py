@@ -259,6 +259,7 @@ def cpu_baseline(g, order, total_entries, u, v):
     return {"value": lab.total / dt, "unit": "label entries/s", "cores": 1, "kind": "oracle",
             "sample": f"full sequential PLL build of the same graph ({g.n} vertices, {lab.total} entries), "
                       f"1 run, {dt:.2f} s", "seconds": dt,
+            "pll_check_cost": {"pos": lab.counters["cost_pos"], "neg": lab.counters["cost_neg"]},
             "query": {"pairs": int(u.shape[0]), "queries_per_s_1core": u.shape[0] / q1,
                       "queries_per_s_pool": u.shape[0] / qn, "pool_processes": procs,
                       "sample": "the oracle's merge-join over its own labels, the same pairs"}}
@@ -515,8 +516,14 @@ def main():
                            "traffic": tr_query["bytes"] if tr_query else None,
                            "bytes_per_launch": q_bytes, "entries_consumed": cons},
     }
+    # Table 3's quantities: sum of |L(v)| over positive / negative checks
+    res["check_cost"] = {"bvc_pos": info["check_cost_pos"], "bvc_neg": info["check_cost_neg"]}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(g, order, total, u, v)
+        pc = res["cpu_baseline"]["pll_check_cost"]
+        res["check_cost"].update({"pll_pos": pc["pos"], "pll_neg": pc["neg"],
+                                  "pos_ratio_pll_over_bvc": pc["pos"] / max(info["check_cost_pos"], 1),
+                                  "neg_ratio_pll_over_bvc": pc["neg"] / max(info["check_cost_neg"], 1)})
     idx.free()
     print(json.dumps(res), flush=True)
     if args.calibrate:

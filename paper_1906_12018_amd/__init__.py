@@ -76,6 +76,8 @@ class IndexInfo(ctypes.Structure):
         ("build_ms", ctypes.c_double),
         ("check_entries_read", ctypes.c_uint64),
         ("check_table_reads", ctypes.c_uint64),
+        ("check_cost_pos", ctypes.c_uint64),
+        ("check_cost_neg", ctypes.c_uint64),
         ("phase_ms", ctypes.c_double * 7),
         ("phase_launches", ctypes.c_uint64 * 7),
     ]

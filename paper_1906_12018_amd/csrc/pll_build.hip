@@ -241,8 +241,8 @@ __device__ inline pll::Exec grid_exec(const BuildArgs& A) {
 // into the workgroup's shard.  Every thread of the block must call this.
 template <int N>
 __device__ inline void block_add_stats(DevCounters* ctr, const unsigned long long (&v)[N], const int (&which)[N]) {
-    static_assert(N <= 4, "at most 4 statistics per call");
-    __shared__ unsigned long long s_part[kWavesPerBlock][4];
+    static_assert(N <= 6, "at most 6 statistics per call");
+    __shared__ unsigned long long s_part[kWavesPerBlock][6];
     const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -310,9 +310,9 @@ __global__ void __launch_bounds__(kBlock) k_check(BuildArgs A, uint32_t ib, uint
                                                   uint32_t relaxed) {
     PhaseStats st;
     pll::phase_check<WM>(A, grid_exec(A), ib, bs, j, p, relaxed != 0, st);
-    const unsigned long long v[4] = {st.cand, st.acc, st.read, st.table};
-    const int which[4] = {PLL_ST_CAND, PLL_ST_ACC, PLL_ST_READ, PLL_ST_TABLE};
-    block_add_stats<4>(A.ctr, v, which);
+    const unsigned long long v[6] = {st.cand, st.acc, st.read, st.table, st.cost_pos, st.cost_neg};
+    const int which[6] = {PLL_ST_CAND, PLL_ST_ACC, PLL_ST_READ, PLL_ST_TABLE, PLL_ST_COST_POS, PLL_ST_COST_NEG};
+    block_add_stats<6>(A.ctr, v, which);
 }
 
 template <int WM>
@@ -853,6 +853,8 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     I.gang = grid_workgroups ? grid_workgroups : 1;
     I.check_entries_read = sum_stat(h, PLL_ST_READ);
     I.check_table_reads = sum_stat(h, PLL_ST_TABLE);
+    I.check_cost_pos = sum_stat(h, PLL_ST_COST_POS);
+    I.check_cost_neg = sum_stat(h, PLL_ST_COST_NEG);
     for (int ph = 0; ph < PLL_NUM_PHASES; ++ph) {
         I.phase_ms[ph] = P.ms[ph];
         I.phase_launches[ph] = P.launches[ph];

@@ -41,6 +41,8 @@ enum {
     PLL_ST_TABLE = 4,    // 64-byte table segments read by pruning scans
     PLL_ST_GROW = 5,     // label lists moved to a larger block
     PLL_ST_RECHECK = 6,  // entries dropped by the recheck
+    PLL_ST_COST_POS = 7, // sum of |L(v)| over checks that added an entry
+    PLL_ST_COST_NEG = 8, // sum of |L(v)| over checks that pruned
     PLL_NUM_ST = 12
 };
 

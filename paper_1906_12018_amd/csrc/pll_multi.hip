@@ -57,7 +57,7 @@ struct GraphJob {
 struct GraphResult {
     unsigned long long out_base, total;
     uint32_t error, max_dist, max_label, pad;
-    unsigned long long batches, rounds, cand, acc, edges, read, table, removed;
+    unsigned long long batches, rounds, cand, acc, edges, read, table, removed, cost_pos, cost_neg;
 };
 
 struct MultiCtl {
@@ -345,12 +345,13 @@ __global__ void __launch_bounds__(kMultiBlock) k_multi_build(const GraphJob* __r
             }
         }
         md = wave_max32(md);
-        const unsigned long long sums[6] = {wave_sum64(st.cand), wave_sum64(st.acc), wave_sum64(st.edges),
-                                            wave_sum64(st.read), wave_sum64(st.table), wave_sum64(st.removed)};
+        const unsigned long long sums[8] = {wave_sum64(st.cand),  wave_sum64(st.acc),     wave_sum64(st.edges),
+                                            wave_sum64(st.read),  wave_sum64(st.table),   wave_sum64(st.removed),
+                                            wave_sum64(st.cost_pos), wave_sum64(st.cost_neg)};
         if (lane == 0) {
             atomicMax(&s_max[0], md);
             atomicMax(&s_max[1], ml);
-            for (int x = 0; x < 6; ++x)
+            for (int x = 0; x < 8; ++x)
                 if (sums[x]) atomicAdd(&s_tot[x], sums[x]);
         }
         __syncthreads();
@@ -364,6 +365,8 @@ __global__ void __launch_bounds__(kMultiBlock) k_multi_build(const GraphJob* __r
             atomicAdd(&R.read, s_tot[3]);
             atomicAdd(&R.table, s_tot[4]);
             atomicAdd(&R.removed, s_tot[5]);
+            atomicAdd(&R.cost_pos, s_tot[6]);
+            atomicAdd(&R.cost_neg, s_tot[7]);
         }
         __syncthreads();
     }
@@ -741,6 +744,8 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
         I.recheck_removed = R.removed;
         I.check_entries_read = R.read;
         I.check_table_reads = R.table;
+        I.check_cost_pos = R.cost_pos;
+        I.check_cost_neg = R.cost_neg;
         I.arena_entries = region_cap * PLL_SHARDS;
         I.build_attempts = 1;
         I.gang = G[g];

@@ -28,6 +28,9 @@ struct Exec {
 // Per-lane statistics a phase accumulates (summed over lanes by the caller).
 struct PhaseStats {
     unsigned long long cand = 0, acc = 0, edges = 0, read = 0, table = 0, removed = 0;
+    // cost of the positive / negative checks: |L(v)| at each check that
+    // added / pruned a candidate (Section 4.3, Table 3)
+    unsigned long long cost_pos = 0, cost_neg = 0;
 };
 
 // Per byte of x: 1 if byte <= t, where tt = t * 0x01010101 (t <= 254).  Bytes
@@ -341,6 +344,8 @@ __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t i
         const uint32_t pos = wave_excl_scan32(cnt);
         const uint32_t total = readlane32(pos + cnt, 63);
         st.cand += __builtin_popcountll(mine);
+        st.cost_pos += (unsigned long long)len * (uint32_t)__builtin_popcountll(acc);
+        st.cost_neg += (unsigned long long)len * (uint32_t)__builtin_popcountll(mine & ~acc);
         if (lane == 0) A.act_v[q][i] = v;
         if (lane < W) A.act_delta[q][(size_t)i * W + lane] = acc;
         if (total == 0) continue;

@@ -248,10 +248,12 @@ __global__ void __launch_bounds__(kRoundBlock) k_batches(BuildArgs A, GridCtl* g
     }
 
     // statistics of this workgroup, one sharded atomic each
-    const unsigned long long v[6] = {st.cand, st.acc, st.edges, st.read, st.table, st.removed};
-    const int which[6] = {PLL_ST_CAND, PLL_ST_ACC, PLL_ST_EDGES, PLL_ST_READ, PLL_ST_TABLE, PLL_ST_RECHECK};
+    const unsigned long long v[8] = {st.cand, st.acc, st.edges, st.read, st.table, st.removed, st.cost_pos,
+                                     st.cost_neg};
+    const int which[8] = {PLL_ST_CAND,  PLL_ST_ACC,     PLL_ST_EDGES,    PLL_ST_READ,
+                          PLL_ST_TABLE, PLL_ST_RECHECK, PLL_ST_COST_POS, PLL_ST_COST_NEG};
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < 8; ++i) {
         const unsigned long long t = block_sum(v[i], s_part);
         if (tid == 0 && t) atomicAdd(&ctr->sh[my].stat[which[i]], t);
     }

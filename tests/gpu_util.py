@@ -55,5 +55,8 @@ def check_counters(idx, g, order, b, want_pll: oracle.Labels):
     assert info["rounds"] == bvc.counters["rounds"]
     assert info["batches"] == bvc.counters["batches"]
     assert info["edges_scanned"] == bvc.counters["edge_accesses"]
+    # cost of the positive and negative checks (sum of |L(v)| at each check)
+    assert info["check_cost_pos"] == bvc.counters["cost_pos"]
+    assert info["check_cost_neg"] == bvc.counters["cost_neg"]
     assert info["max_dist"] == (int(want_pll.dist.max()) if want_pll.total else 0)
     return info

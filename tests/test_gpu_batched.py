@@ -34,6 +34,8 @@ def test_mixed_graphs_one_launch(b):
         info = idx.info()
         assert info["candidates"] + g.n == want.counters["checks"]
         assert info["accepted"] == want.total - g.n
+        bvc = oracle.bvc_labels(g, o, b)
+        assert (info["check_cost_pos"], info["check_cost_neg"]) == (bvc.counters["cost_pos"], bvc.counters["cost_neg"])
         u, v = synth.query_pairs(g.n, 2000, seed=2)
         assert np.array_equal(gpu_query(idx, u, v), oracle.query(want, u, v))
     # indexes share one output buffer: freeing some keeps the others valid

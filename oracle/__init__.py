@@ -13,6 +13,8 @@ Functions (all host-side, written from the paper, arXiv 1906.12018):
 * :func:`bvc_labels`       -- Algorithm 4 (BVC-PLL) run sequentially with
   batch size b; b = 1 is PLL and b = n is VC-PLL (Algorithm 3).
 * :func:`query`            -- the 2-hop distance formula of Section 2.1.
+* :func:`pll_labels_directed`, :func:`query_directed` -- the directed variant
+  of Section 5.1 (L_in and L_out labels; the query merges L_out(s), L_in(t)).
 * :func:`bfs`              -- textbook BFS distances.
 
 Label sets are returned as :class:`Labels` (CSR by vertex id, hubs as ranks in
@@ -79,6 +81,11 @@ def _load():
         lib.oracle_bfs.restype = None
         lib.oracle_query.argtypes = [P, P, P, ctypes.c_uint64, P, P, P, P]
         lib.oracle_query.restype = None
+        lib.oracle_pll_directed.argtypes = [ctypes.c_uint32, P, P, P, ctypes.POINTER(_CLabels),
+                                            ctypes.POINTER(_CLabels)]
+        lib.oracle_pll_directed.restype = ctypes.c_int
+        lib.oracle_query_directed.argtypes = [P, P, P, P, P, P, ctypes.c_uint64, P, P, P]
+        lib.oracle_query_directed.restype = None
         _lib = lib
     return _lib
 
@@ -193,3 +200,31 @@ def query(labels: Labels, u, v, with_consumed: bool = False):
                          dist.ctypes.data if dist.size else None, u.shape[0], u.ctypes.data, v.ctypes.data,
                          out.ctypes.data, cons.ctypes.data if cons is not None else None)
     return (out, cons) if with_consumed else out
+
+
+def pll_labels_directed(g, order):
+    """Directed PLL (Section 5.1) on the arcs of ``g`` (row v lists the heads
+    of the arcs leaving v).  Returns ``(L_in, L_out)``: L_in(v) holds
+    (u, d(u,v)), L_out(v) holds (u, d(v,u)); lists by vertex id, hubs as
+    ranks.  Counters: L_in's are the forward searches', L_out's the backward
+    searches'."""
+    row_ptr, col, order = _graph_args(g, order)
+    cin, cout = _CLabels(), _CLabels()
+    _check(_load().oracle_pll_directed(g.n, row_ptr.ctypes.data, col.ctypes.data, order.ctypes.data,
+                                       ctypes.byref(cin), ctypes.byref(cout)), "oracle_pll_directed")
+    return _take(cin), _take(cout)
+
+
+def query_directed(lin: Labels, lout: Labels, s, t):
+    """d(s, t) for each pair: min over hubs of L_out(s) and L_in(t) (uint32;
+    DIST_INF when t is unreachable from s)."""
+    s = np.ascontiguousarray(s, dtype=np.uint32)
+    t = np.ascontiguousarray(t, dtype=np.uint32)
+    out = np.empty(s.shape[0], dtype=np.uint32)
+    arrs = []
+    for lab in (lout, lin):
+        arrs += [np.ascontiguousarray(lab.offsets, dtype=np.uint64), np.ascontiguousarray(lab.hub_rank, dtype=np.uint32),
+                 np.ascontiguousarray(lab.dist, dtype=np.uint8)]
+    ptr = [a.ctypes.data if a.size else None for a in arrs]
+    _load().oracle_query_directed(*ptr, s.shape[0], s.ctypes.data, t.ctypes.data, out.ctypes.data)
+    return out

@@ -17,6 +17,10 @@
  *                     arrays of Section 4.1.
  *   oracle_query      the 2-hop distance formula of Section 2.1, by a
  *                     two-pointer merge over hub-sorted lists.
+ *   oracle_pll_directed / oracle_query_directed
+ *                     the directed variant of Section 5.1: L_in and L_out
+ *                     labels from a forward and a backward pruned BFS per
+ *                     root; the query merges L_out(s) with L_in(t).
  *   oracle_bfs        textbook breadth-first search distances.
  *
  * Conventions (readings of points the paper leaves open):
@@ -556,5 +560,172 @@ void oracle_query(const uint64_t* offsets, const uint32_t* hub_rank, const uint8
             }
             consumed[q] = c;
         }
+    }
+}
+
+/* ---- directed graphs (Section 5.1) -----------------------------------------
+ * Each vertex carries two labels: L_in(v) with entries (u, d(u,v)) and
+ * L_out(v) with entries (u, d(v,u)); the distance from s to t is the minimum
+ * of d(s,h) + d(h,t) over hubs h of both L_out(s) and L_in(t).  PLL becomes
+ * two pruned BFSs per root u taken in rank order:
+ *   forward, along out-arcs: a vertex v reached at delta = d(u,v) gets
+ *     (u, delta) in L_in(v) unless some hub h of L_out(u) and L_in(v) has
+ *     d(u,h) + d(h,v) <= delta; only then are its out-neighbours ranked below
+ *     u queued;
+ *   backward, along in-arcs: v reached at delta = d(v,u) gets (u, delta) in
+ *     L_out(v) unless some hub h of L_out(v) and L_in(u) has
+ *     d(v,h) + d(h,u) <= delta.
+ * The result is the directed form of Definition 2: u is in L_in(v) iff u
+ * has the highest rank on every shortest path from u to v (and L_out
+ * likewise for paths from v to u).  The in-arc CSR is the transpose of the
+ * given out-arc CSR, formed here by counting.
+ */
+static int transpose_csr(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, uint64_t** t_row,
+                         uint32_t** t_col) {
+    uint64_t nnz = row_ptr[n];
+    uint64_t* tr = (uint64_t*)calloc((size_t)n + 1, sizeof(uint64_t));
+    uint32_t* tc = (uint32_t*)malloc(sizeof(uint32_t) * (nnz ? nnz : 1));
+    uint64_t* fill = (uint64_t*)malloc(sizeof(uint64_t) * ((size_t)n + 1));
+    if (!tr || !tc || !fill) { free(tr); free(tc); free(fill); return ORACLE_ENOMEM; }
+    for (uint64_t e = 0; e < nnz; ++e) {
+        if (col[e] >= n) { free(tr); free(tc); free(fill); return ORACLE_EINVAL; }
+        tr[col[e] + 1]++;
+    }
+    for (uint32_t i = 0; i < n; ++i) tr[i + 1] += tr[i];
+    memcpy(fill, tr, sizeof(uint64_t) * ((size_t)n + 1));
+    /* sources are visited in ascending id, so every in-row is sorted */
+    for (uint32_t x = 0; x < n; ++x)
+        for (uint64_t e = row_ptr[x]; e < row_ptr[x + 1]; ++e) tc[fill[col[e]]++] = x;
+    free(fill);
+    *t_row = tr;
+    *t_col = tc;
+    return ORACLE_OK;
+}
+
+/* One pruned BFS from the root u = order[k] along the arcs of (row_ptr, col):
+ * T holds the root's other-side label spread by hub rank; a reached vertex v
+ * is checked against its label Lx[v] and, if kept, gets (k, delta) appended. */
+typedef struct {
+    uint64_t checks, added, edges, scanned, cost_pos, cost_neg;
+} dir_counts;
+
+static int pruned_bfs(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* rank, uint32_t k,
+                      uint32_t u, const uint8_t* T, vlist* Lx, uint32_t* visited, uint32_t stamp, uint32_t* qv,
+                      uint32_t* qd, dir_counts* c) {
+    uint32_t head = 0, tail = 0;
+    qv[tail] = u; qd[tail] = 0; tail++;
+    visited[u] = stamp;
+    while (head < tail) {
+        uint32_t v = qv[head], delta = qd[head];
+        head++;
+        c->checks++;
+        vlist* Lv = &Lx[v];
+        uint32_t m = DIST_INF;
+        for (uint32_t i = 0; i < Lv->len; ++i) {
+            uint32_t th = T[Lv->hub[i]];
+            if (th != INF8 && th + Lv->d[i] < m) m = th + Lv->d[i];
+        }
+        c->scanned += Lv->len;
+        if (!(delta < m)) {
+            c->cost_neg += Lv->len;
+            continue;
+        }
+        c->cost_pos += Lv->len;
+        if (delta >= INF8) return ORACLE_EDIST;
+        int rc = vlist_push(Lv, k, delta);
+        if (rc) return rc;
+        c->added++;
+        for (uint64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            uint32_t w = col[e];
+            c->edges++;
+            if (visited[w] != stamp && rank[w] > k) {
+                visited[w] = stamp;
+                qv[tail] = w; qd[tail] = delta + 1; tail++;
+            }
+        }
+    }
+    (void)n;
+    return ORACLE_OK;
+}
+
+int oracle_pll_directed(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* order,
+                        oracle_labels* lin, oracle_labels* lout) {
+    memset(lin, 0, sizeof(*lin));
+    memset(lout, 0, sizeof(*lout));
+    uint32_t* rank = make_rank(n, order);
+    if (!rank) return ORACLE_EINVAL;
+    uint64_t* in_row = NULL;
+    uint32_t* in_col = NULL;
+    int rc = transpose_csr(n, row_ptr, col, &in_row, &in_col);
+    if (rc) { free(rank); return rc; }
+    vlist* Lin = (vlist*)calloc(n ? n : 1, sizeof(vlist));
+    vlist* Lout = (vlist*)calloc(n ? n : 1, sizeof(vlist));
+    uint8_t* T = (uint8_t*)malloc(n ? n : 1);
+    uint32_t* visited = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint32_t* qv = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint32_t* qd = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    dir_counts fw = {0}, bw = {0};
+    if (!Lin || !Lout || !T || !visited || !qv || !qd) { rc = ORACLE_ENOMEM; goto done; }
+    memset(T, INF8, n);
+    for (uint32_t i = 0; i < n; ++i) visited[i] = DIST_INF;
+    for (uint32_t k = 0; k < n && !rc; ++k) {
+        uint32_t u = order[k];
+        /* forward: check through L_out(u), grow L_in */
+        vlist* Lu = &Lout[u];
+        for (uint32_t i = 0; i < Lu->len; ++i) T[Lu->hub[i]] = Lu->d[i];
+        rc = pruned_bfs(n, row_ptr, col, rank, k, u, T, Lin, visited, 2 * k, qv, qd, &fw);
+        for (uint32_t i = 0; i < Lu->len; ++i) T[Lu->hub[i]] = INF8;
+        if (rc) break;
+        /* backward: check through L_in(u), grow L_out */
+        Lu = &Lin[u];
+        for (uint32_t i = 0; i < Lu->len; ++i) T[Lu->hub[i]] = Lu->d[i];
+        rc = pruned_bfs(n, in_row, in_col, rank, k, u, T, Lout, visited, 2 * k + 1, qv, qd, &bw);
+        for (uint32_t i = 0; i < Lu->len; ++i) T[Lu->hub[i]] = INF8;
+    }
+    if (!rc) rc = vlists_to_csr(Lin, n, 0, lin);
+    if (!rc) rc = vlists_to_csr(Lout, n, 0, lout);
+    if (!rc) {
+        const dir_counts* cs[2] = {&fw, &bw};
+        oracle_labels* ls[2] = {lin, lout};
+        for (int s = 0; s < 2; ++s) {
+            ls[s]->counters[0] = cs[s]->checks;
+            ls[s]->counters[1] = cs[s]->added;
+            ls[s]->counters[2] = cs[s]->edges;
+            ls[s]->counters[5] = cs[s]->scanned;
+            ls[s]->counters[6] = cs[s]->cost_pos;
+            ls[s]->counters[7] = cs[s]->cost_neg;
+        }
+    } else {
+        oracle_labels_free(lin);
+        oracle_labels_free(lout);
+    }
+done:
+    if (Lin) vlists_free(Lin, n);
+    if (Lout) vlists_free(Lout, n);
+    free(T); free(visited); free(qv); free(qd); free(rank); free(in_row); free(in_col);
+    return rc;
+}
+
+/* Directed 2-hop query: merge L_out(s) (lists offs/hubs/dists_s) with L_in(t)
+ * (lists offt/hubt/distt) as in oracle_query. */
+void oracle_query_directed(const uint64_t* offs, const uint32_t* hubs, const uint8_t* dists, const uint64_t* offt,
+                           const uint32_t* hubt, const uint8_t* distt, uint64_t count, const uint32_t* qs,
+                           const uint32_t* qt, uint32_t* out) {
+    for (uint64_t q = 0; q < count; ++q) {
+        uint64_t a = offs[qs[q]], ae = offs[qs[q] + 1];
+        uint64_t b = offt[qt[q]], be = offt[qt[q] + 1];
+        uint32_t best = DIST_INF;
+        while (a < ae && b < be) {
+            if (hubs[a] == hubt[b]) {
+                uint32_t s = (uint32_t)dists[a] + distt[b];
+                if (s < best) best = s;
+                a++; b++;
+            } else if (hubs[a] < hubt[b]) {
+                a++;
+            } else {
+                b++;
+            }
+        }
+        out[q] = best;
     }
 }

@@ -211,3 +211,83 @@ def disjoint_union(*graphs: Graph) -> Graph:
         base += g.n
     return csr_from_edges(n, np.concatenate(src) if src else np.zeros(0), np.concatenate(dst) if dst else np.zeros(0),
                           name="union")
+
+
+# --- directed graphs (arcs) ---------------------------------------------------------------------
+
+@dataclass
+class DiGraph:
+    """Directed graph in CSR form: row v lists the heads of the arcs leaving
+    v, sorted by vertex id, with no self-loop and no duplicate arc."""
+    n: int
+    row_ptr: np.ndarray  # uint64[n+1]
+    col: np.ndarray      # uint32[nnz]
+    name: str = ""
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.shape[0])
+
+    def out_degrees(self) -> np.ndarray:
+        return np.diff(self.row_ptr).astype(np.int64)
+
+    def in_degrees(self) -> np.ndarray:
+        return np.bincount(self.col.astype(np.int64), minlength=self.n).astype(np.int64)
+
+
+def digraph_from_arcs(n: int, src: np.ndarray, dst: np.ndarray, name: str = "") -> DiGraph:
+    """Drop self-loops, sort and dedup an arc list into CSR (no symmetrisation)."""
+    src = np.asarray(src, dtype=np.uint64)
+    dst = np.asarray(dst, dtype=np.uint64)
+    keep = src != dst
+    keys = np.unique((src[keep] << np.uint64(32)) | dst[keep])
+    rows = (keys >> np.uint64(32)).astype(np.int64)
+    col = (keys & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    row_ptr = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(np.bincount(rows, minlength=n), out=row_ptr[1:])
+    return DiGraph(n=n, row_ptr=row_ptr, col=col, name=name)
+
+
+def rmat_digraph(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+                 seed: int = 1) -> DiGraph:
+    """R-MAT arcs (same sampler as rmat_graph, sample i is the arc src -> dst),
+    deduplicated, self-loops removed, not symmetrised."""
+    n = 1 << scale
+    ns = edge_factor * n
+    edges = np.empty(2 * ns, dtype=np.uint32)
+    _load().synth_rmat_edges(scale, ns, a, b, c, seed, edges.ctypes.data)
+    return digraph_from_arcs(n, edges[0::2], edges[1::2], name=f"rmat{scale}_ef{edge_factor}_s{seed}_dir")
+
+
+def gnp_digraph(n: int, p: float, seed: int) -> DiGraph:
+    """Each ordered pair (i, j), i != j, is an arc with probability p (row-major order of the n*n grid)."""
+    x = uniform01(splitmix64(seed, 0, n * n)).reshape(n, n)
+    src, dst = np.nonzero(x < p)
+    return digraph_from_arcs(n, src, dst, name=f"dgnp{n}_{p}_s{seed}")
+
+
+def directed_path(n: int) -> DiGraph:
+    s = np.arange(max(n - 1, 0))
+    return digraph_from_arcs(n, s, s + 1, name=f"dpath{n}")
+
+
+def directed_cycle(n: int) -> DiGraph:
+    s = np.arange(n)
+    return digraph_from_arcs(n, s, (s + 1) % n, name=f"dcycle{n}")
+
+
+def as_digraph(g: Graph) -> DiGraph:
+    """The symmetric digraph with both arcs of every edge of g."""
+    return DiGraph(n=g.n, row_ptr=g.row_ptr.copy(), col=g.col.copy(), name=g.name + "_sym")
+
+
+def reverse_digraph(g: DiGraph) -> DiGraph:
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr).astype(np.int64))
+    return digraph_from_arcs(g.n, g.col.astype(np.int64), rows, name=g.name + "_rev")
+
+
+def degree_order_directed(g: DiGraph) -> np.ndarray:
+    """order[k] = vertex of rank k: total degree (in + out) descending, ties by ascending id."""
+    deg = g.out_degrees() + g.in_degrees()
+    ids = np.arange(g.n, dtype=np.int64)
+    return np.lexsort((ids, -deg)).astype(np.uint32)

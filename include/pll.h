@@ -1,9 +1,9 @@
 /*
  * pll.h -- C ABI of the MI355X (gfx950) pruned landmark labeling library.
  *
- * The library builds the canonical 2-hop distance labeling of an undirected,
- * unweighted graph for a given vertex order, and answers exact distance
- * queries from it.  Paper: Jin et al., "Pruned Landmark Labeling Meets Vertex
+ * The library builds the canonical 2-hop distance labeling of an unweighted
+ * graph (undirected, or directed with in- and out-labels) for a given vertex
+ * order, and answers exact distance queries from it.  Paper: Jin et al., "Pruned Landmark Labeling Meets Vertex
  * Centric Computation" (arXiv 1906.12018).
  *
  *   Problem statement (Section 2.1, Definitions 1-2): given G = (V, E) and a
@@ -121,6 +121,10 @@ typedef struct {
     uint64_t check_cost_neg;      /* the same over checks that pruned (Section 4.3, the quantities of Table 3) */
     double phase_ms[PLL_NUM_PHASES];         /* device time per phase (PLL_FLAG_PROFILE, else 0) */
     uint64_t phase_launches[PLL_NUM_PHASES]; /* kernel launches per phase (PLL_FLAG_PROFILE, else 0) */
+    uint32_t directed;        /* 1 for an index of pll_build_labels_directed */
+    uint32_t reserved_info;
+    uint64_t in_entries;      /* directed: sum of |L_in(v)|; undirected: total_entries (one label serves both) */
+    uint64_t out_entries;     /* directed: sum of |L_out(v)|; undirected: total_entries */
 } pll_index_info;
 
 /* One graph of a batched build (all pointers are device pointers). */
@@ -150,6 +154,36 @@ int pll_build_labels(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const 
                      const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out);
 
 /*
+ * Build the labels of a directed graph (Section 5.1): every vertex v gets
+ * L_in(v), the hubs u with (u, d(u,v)) such that u has the highest rank on
+ * every shortest path from u to v, and L_out(v), the hubs u with (u, d(v,u))
+ * such that u has the highest rank on every shortest path from v to u.  The
+ * batches run a forward search (out-arcs, growing L_in) and a backward search
+ * (in-arcs, growing L_out) in lockstep rounds; a forward check of root u at v
+ * compares L_in(v) with L_out(u), a backward check L_out(v) with L_in(u).
+ *   n, nnz      vertices and arcs
+ *   d_row_ptr   uint64[n+1], d_row_ptr[0] = 0, d_row_ptr[n] = nnz
+ *   d_col       uint32[nnz]; row v lists the heads w of the arcs v -> w, in
+ *               ascending id, with no self-loop and no duplicate arc (the
+ *               graph need not be symmetric; a symmetric one gives
+ *               L_in = L_out = the undirected labels)
+ *   d_order     uint32[n], a permutation; d_order[k] = vertex of rank k
+ *   opts        NULL for defaults; PLL_FLAG_RELAXED and PLL_FLAG_PERSISTENT
+ *               are rejected (PLL_EINVAL), the other fields act as for
+ *               pll_build_labels
+ *   out         receives the new index
+ * The in-arc CSR is formed on the device.  pll_query on the index returns
+ * d(u, v), the length of a shortest path from u to v (PLL_DIST_INF when there
+ * is none), by merging L_out(u) with L_in(v).  pll_index_info reports both
+ * labels summed (total_entries) and apart (in_entries, out_entries).  Checks
+ * and errors as for pll_build_labels, except that PLL_FLAG_VALIDATE does not
+ * ask for symmetry.
+ */
+int pll_build_labels_directed(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
+                              const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream,
+                              pll_index** out);
+
+/*
  * Exact distances for `count` pairs (Section 2.1, the 2-hop query).
  *   d_u, d_v    uint32[count] vertex ids; an id >= n has no label, so its
  *               pairs answer PLL_DIST_INF
@@ -174,6 +208,18 @@ int pll_index_info_get(const pll_index* idx, pll_index_info* out);
  */
 int pll_export_labels(const pll_index* idx, uint64_t* d_offsets, uint32_t* d_hubs, uint8_t* d_dists,
                       hipStream_t stream);
+
+/*
+ * Copy one side of the labels out, as pll_export_labels does: `side` is
+ * PLL_LABELS_IN (L_in, what pll_export_labels copies) or PLL_LABELS_OUT
+ * (L_out); d_hubs and d_dists hold in_entries or out_entries entries.  For an
+ * undirected index both sides are its one label.  Another side value is
+ * PLL_EINVAL.
+ */
+#define PLL_LABELS_IN 0u
+#define PLL_LABELS_OUT 1u
+int pll_export_labels_side(const pll_index* idx, uint32_t side, uint64_t* d_offsets, uint32_t* d_hubs,
+                           uint8_t* d_dists, hipStream_t stream);
 
 /*
  * Build `count` independent graphs in one persistent-kernel launch, captured

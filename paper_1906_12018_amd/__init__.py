@@ -8,7 +8,8 @@ the library is not built, or no GPU is present, calls raise :class:`PllError`.
 Paper: Jin et al., "Pruned Landmark Labeling Meets Vertex Centric
 Computation" (arXiv 1906.12018): BVC-PLL (Section 4.2, Algorithm 4) builds the
 canonical 2-hop labeling (Definition 2) for a vertex order; the 2-hop query
-(Section 2.1) merges two hub-sorted lists.
+(Section 2.1) merges two hub-sorted lists.  Directed graphs (Section 5.1) get
+L_in and L_out labels, and the query merges L_out(u) with L_in(v).
 """
 from __future__ import annotations
 
@@ -26,9 +27,11 @@ DIST_INF = 0xFFFFFFFF
 FLAG_VALIDATE, FLAG_RECHECK, FLAG_RELAXED, FLAG_PROFILE, FLAG_PERSISTENT = 0x1, 0x2, 0x4, 0x8, 0x10
 PHASES = ("prep", "init", "push", "check", "end", "final", "loop")
 DEFAULT_BATCH = 1024
+LABELS_IN, LABELS_OUT = 0, 1
 
 EXPORTED_SYMBOLS = (
-    "pll_build_labels", "pll_query", "pll_index_info_get", "pll_export_labels",
+    "pll_build_labels", "pll_build_labels_directed", "pll_query", "pll_index_info_get", "pll_export_labels",
+    "pll_export_labels_side",
     "pll_build_labels_batched", "pll_index_free", "pll_status_string",
     "pll_server_create", "pll_server_add_index", "pll_server_index", "pll_server_submit", "pll_server_poll",
     "pll_server_replay", "pll_server_destroy",
@@ -80,6 +83,10 @@ class IndexInfo(ctypes.Structure):
         ("check_cost_neg", ctypes.c_uint64),
         ("phase_ms", ctypes.c_double * 7),
         ("phase_launches", ctypes.c_uint64 * 7),
+        ("directed", ctypes.c_uint32),
+        ("reserved_info", ctypes.c_uint32),
+        ("in_entries", ctypes.c_uint64),
+        ("out_entries", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:
@@ -168,6 +175,11 @@ def load_library(path: str = LIB_PATH):
     lib.pll_index_info_get.argtypes = [P, ctypes.POINTER(IndexInfo)]
     lib.pll_index_info_get.restype = ctypes.c_int
     lib.pll_export_labels.argtypes = [P, P, P, P, P]
+    lib.pll_export_labels.restype = ctypes.c_int
+    lib.pll_export_labels_side.argtypes = [P, U32, P, P, P, P]
+    lib.pll_export_labels_side.restype = ctypes.c_int
+    lib.pll_build_labels_directed.argtypes = [U32, U64, P, P, P, ctypes.POINTER(BuildOpts), P, ctypes.POINTER(P)]
+    lib.pll_build_labels_directed.restype = ctypes.c_int
     lib.pll_export_labels.restype = ctypes.c_int
     lib.pll_build_labels_batched.argtypes = [U32, ctypes.POINTER(GraphDesc), ctypes.POINTER(BuildOpts), P,
                                              ctypes.POINTER(P)]
@@ -271,16 +283,19 @@ class Index:
             raise PllError(rc, "pll_query")
         return out
 
-    def export(self, stream=None) -> ExportedLabels:
+    def export(self, side: int = 0, stream=None) -> ExportedLabels:
+        """Labels in CSR form; ``side`` is LABELS_IN (L_in, the one label of an
+        undirected index) or LABELS_OUT (L_out of a directed index)."""
         inf = self.info()
-        n, total = inf["n"], inf["total_entries"]
+        n = inf["n"]
+        total = inf["out_entries"] if side == LABELS_OUT else inf["in_entries"]
         off = torch.empty(n + 1, dtype=torch.int64, device=self.device)
         hubs = torch.empty(max(total, 1), dtype=torch.int32, device=self.device)
         dists = torch.empty(max(total, 1), dtype=torch.uint8, device=self.device)
-        rc = load_library().pll_export_labels(self.handle, off.data_ptr(), hubs.data_ptr(), dists.data_ptr(),
-                                              _stream_handle(stream))
+        rc = load_library().pll_export_labels_side(self.handle, side, off.data_ptr(), hubs.data_ptr(),
+                                                   dists.data_ptr(), _stream_handle(stream))
         if rc:
-            raise PllError(rc, "pll_export_labels")
+            raise PllError(rc, "pll_export_labels_side")
         return ExportedLabels(off, hubs[:total], dists[:total])
 
     def free(self):
@@ -312,6 +327,27 @@ def build_labels(row_ptr: torch.Tensor, col: torch.Tensor, order: torch.Tensor, 
                                          ctypes.byref(o), _stream_handle(stream), ctypes.byref(h))
     if rc:
         raise PllError(rc, "pll_build_labels")
+    return Index(h.value, order.device)
+
+
+def build_labels_directed(row_ptr: torch.Tensor, col: torch.Tensor, order: torch.Tensor,
+                          batch_size: int = DEFAULT_BATCH, flags: int = FLAG_VALIDATE, arena_entries: int = 0,
+                          query_lanes: int = 0, stream=None) -> Index:
+    """L_in / L_out labels of the directed CSR graph (row v lists the heads of
+    the arcs leaving v); the index's query gives the distance from u to v."""
+    row_ptr = _dev(row_ptr, torch.int64, "row_ptr")
+    col = _dev(col, torch.int32, "col")
+    order = _dev(order, torch.int32, "order")
+    n = order.numel()
+    if row_ptr.numel() != n + 1:
+        raise PllError(PLL_EINVAL, "row_ptr must have n+1 entries")
+    h = ctypes.c_void_p()
+    o = _opts(batch_size, flags, arena_entries, query_lanes)
+    rc = load_library().pll_build_labels_directed(n, col.numel(), row_ptr.data_ptr(), col.data_ptr(),
+                                                  order.data_ptr(), ctypes.byref(o), _stream_handle(stream),
+                                                  ctypes.byref(h))
+    if rc:
+        raise PllError(rc, "pll_build_labels_directed")
     return Index(h.value, order.device)
 
 

@@ -31,6 +31,10 @@ void free_index(pll_index* idx) {
         (void)hipFree(idx->d_off);
         (void)hipFree(idx->d_order);
     }
+    if (idx->directed) {
+        (void)hipFree(idx->d_off_out);
+        (void)hipFree(idx->d_ent_out);
+    }
     if (idx->store) {
         if (idx->store->refs.fetch_sub(1) == 1) {
             (void)hipFree(idx->store->ptr);
@@ -70,20 +74,40 @@ int pll_index_info_get(const pll_index* idx, pll_index_info* out) {
     return PLL_OK;
 }
 
-int pll_export_labels(const pll_index* idx, uint64_t* d_offsets, uint32_t* d_hubs, uint8_t* d_dists,
-                      hipStream_t stream) {
-    if (!idx || !d_offsets) return PLL_EINVAL;
-    if (idx->total && (!d_hubs || !d_dists)) return PLL_EINVAL;
-    if (hipMemcpyAsync(d_offsets, idx->d_off, sizeof(uint64_t) * ((size_t)idx->n + 1), hipMemcpyDeviceToDevice,
-                       stream) != hipSuccess)
+int pll_export_labels_side(const pll_index* idx, uint32_t side, uint64_t* d_offsets, uint32_t* d_hubs,
+                           uint8_t* d_dists, hipStream_t stream) {
+    if (!idx || !d_offsets || side > PLL_LABELS_OUT) return PLL_EINVAL;
+    const bool out_side = idx->directed && side == PLL_LABELS_OUT;
+    const uint64_t total = out_side ? idx->total_out : idx->total;
+    const uint64_t* off = out_side ? idx->d_off_out : idx->d_off;
+    const uint32_t* ent = out_side ? idx->d_ent_out : idx->d_ent;
+    if (total && (!d_hubs || !d_dists)) return PLL_EINVAL;
+    if (hipMemcpyAsync(d_offsets, off, sizeof(uint64_t) * ((size_t)idx->n + 1), hipMemcpyDeviceToDevice, stream) !=
+        hipSuccess)
         return PLL_EDEVICE;
-    if (idx->total) {
-        uint64_t blocks = (idx->total + kBlock - 1) / kBlock;
+    if (total) {
+        uint64_t blocks = (total + kBlock - 1) / kBlock;
         if (blocks > 65536) blocks = 65536;
-        k_export<<<(uint32_t)blocks, kBlock, 0, stream>>>(idx->total, idx->d_ent, idx->d_order, d_hubs, d_dists);
+        k_export<<<(uint32_t)blocks, kBlock, 0, stream>>>(total, ent, idx->d_order, d_hubs, d_dists);
         if (hipGetLastError() != hipSuccess) return PLL_EDEVICE;
     }
     return PLL_OK;
+}
+
+int pll_export_labels(const pll_index* idx, uint64_t* d_offsets, uint32_t* d_hubs, uint8_t* d_dists,
+                      hipStream_t stream) {
+    return pll_export_labels_side(idx, PLL_LABELS_IN, d_offsets, d_hubs, d_dists, stream);
+}
+
+int pll_build_labels_directed(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
+                              const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream,
+                              pll_index** out) {
+    try {
+        return pll_build_directed(n, nnz, d_row_ptr, d_col, d_order, opts, stream, out);
+    } catch (...) {
+        if (out) *out = nullptr;
+        return PLL_ENOMEM;
+    }
 }
 
 int pll_build_labels_batched(uint32_t count, const pll_graph_desc* graphs, const pll_build_opts* opts,

@@ -168,10 +168,11 @@ __global__ void k_check_order_counts(uint32_t n, const uint32_t* cnt, DevCounter
 }
 
 // Full CSR check (flag PLL_FLAG_VALIDATE): each row strictly ascending, no
-// self-loop, and every edge present in both directions.  Runs only after the
-// row pointers and column ids passed the bounds checks.
+// self-loop, and (`symmetric`, undirected graphs) every edge present in both
+// directions.  Runs only after the row pointers and column ids passed the
+// bounds checks.
 __global__ void __launch_bounds__(kBlock) k_check_csr(uint32_t n, const uint64_t* row_ptr, const uint32_t* col,
-                                                      DevCounters* ctr) {
+                                                      uint32_t symmetric, DevCounters* ctr) {
     const uint32_t lane = lane_id();
     for (uint32_t v = global_wave(); v < n; v += num_waves()) {
         const uint64_t beg = row_ptr[v], end = row_ptr[v + 1];
@@ -180,6 +181,7 @@ __global__ void __launch_bounds__(kBlock) k_check_csr(uint32_t n, const uint64_t
             uint32_t c = col[e];
             if (c == v) bad = true;
             if (e > beg && col[e - 1] >= c) bad = true;
+            if (!symmetric) continue;
             uint64_t lo = row_ptr[c], hi = row_ptr[c + 1];
             while (lo < hi) {
                 uint64_t mid = (lo + hi) >> 1;
@@ -213,6 +215,27 @@ __global__ void __launch_bounds__(kBlock) k_relabel_cols(uint32_t n, const uint3
         const uint64_t src = row_ptr[v], dst = rrow[k];
         const uint32_t deg = (uint32_t)(row_ptr[v + 1] - src);
         for (uint32_t i = lane; i < deg; i += 64) rcol[dst + i] = rank[col[src + i]];
+    }
+}
+
+// In-arcs of a directed graph in rank space: heads count their in-arcs,
+// the counts are scanned into row pointers, then every arc r -> c claims a
+// slot of row c.  Rows come out in no particular order, which the rounds do
+// not need.
+__global__ void k_count_heads(uint64_t nnz, const uint32_t* rcol, uint32_t* cnt) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < nnz; e += (uint64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[rcol[e]], 1u);
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_transpose(uint32_t n, const uint64_t* rrow, const uint32_t* rcol,
+                                                           const uint64_t* irow, uint32_t* cursor, uint32_t* icol) {
+    const uint32_t lane = lane_id();
+    for (uint32_t r = global_wave(); r < n; r += num_waves()) {
+        const uint64_t beg = rrow[r], end = rrow[r + 1];
+        for (uint64_t e = beg + lane; e < end; e += 64) {
+            const uint32_t c = rcol[e];
+            icol[irow[c] + atomicAdd(&cursor[c], 1u)] = r;
+        }
     }
 }
 
@@ -609,32 +632,27 @@ int relayout_arena(DevAllocs& M, BuildArgs& A, uint64_t*& spare_off, uint32_t* c
     return PLL_OK;
 }
 
-// One complete build attempt with a given initial arena size.
-int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* order,
-                  uint32_t b, uint32_t flags, uint64_t arena_hint, bool arena_fixed, uint32_t max_workgroups,
-                  hipStream_t s, pll_index* idx, uint64_t* used_arena) {
-    DevAllocs M;
-    M.s = s;
-    HostCounters HC;
-    PhaseProfiler P;
-    P.on = (flags & PLL_FLAG_PROFILE) != 0;
-    P.s = s;
-    TRY_HIP(pll_pinned_alloc((void**)&HC.p, sizeof(DevCounters)));
-    DevCounters* h = HC.p;
-    const uint32_t W = (b + 63) / 64;
-    const uint32_t bstride = 64 * W;
+// Input checks (bounds always; the full CSR structure under
+// PLL_FLAG_VALIDATE, symmetry only for undirected graphs) and the rank-space
+// CSR of the given rows.
+struct RankCsr {
+    uint32_t* rank = nullptr;
+    uint32_t* tmp32 = nullptr;  // n+1 scratch counts
+    uint64_t* scan_scratch = nullptr;
+    uint64_t* rrow = nullptr;
+    uint32_t* rcol = nullptr;
+};
 
-    DevCounters* ctr = M.get<DevCounters>(1);
-    uint32_t* rank = M.get<uint32_t>(n);
-    uint32_t* tmp32 = M.get<uint32_t>((size_t)n + 1);
-    uint64_t* scan_scratch = M.get<uint64_t>((n + 1) / kScanTile + 2);
-    uint64_t* rrow = M.get<uint64_t>((size_t)n + 1);
-    uint32_t* rcol = M.get<uint32_t>(nnz ? nnz : 1);
+int prepare_rank_csr(DevAllocs& M, DevCounters* ctr, DevCounters* h, uint32_t n, uint64_t nnz,
+                     const uint64_t* row_ptr, const uint32_t* col, const uint32_t* order, uint32_t flags,
+                     bool symmetric, hipStream_t s, RankCsr* R) {
+    R->rank = M.get<uint32_t>(n);
+    R->tmp32 = M.get<uint32_t>((size_t)n + 1);
+    R->scan_scratch = M.get<uint64_t>((n + 1) / kScanTile + 2);
+    R->rrow = M.get<uint64_t>((size_t)n + 1);
+    R->rcol = M.get<uint32_t>(nnz ? nnz : 1);
     if (M.err != hipSuccess) return status_of(M.err);
-    TRY_HIP(hipMemsetAsync(ctr, 0, sizeof(DevCounters), s));
-    hipEvent_t e_prep = P.mark();
-
-    // --- input checks (bounds always; full CSR structure on request)
+    uint32_t* tmp32 = R->tmp32;
     k_check_rowptr<<<blocks_for_threads((uint64_t)n + 1), kBlock, 0, s>>>(n, nnz, row_ptr, ctr);
     TRY_HIP(hipMemsetAsync(tmp32, 0, sizeof(uint32_t) * n, s));
     k_count_order<<<blocks_for_threads(n), kBlock, 0, s>>>(n, order, tmp32, ctr);
@@ -648,34 +666,41 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     if (rc) return rc;
     if (h->error) return PLL_EINVAL;
     if (flags & PLL_FLAG_VALIDATE) {
-        k_check_csr<<<blocks_for_waves(n), kBlock, 0, s>>>(n, row_ptr, col, ctr);
+        k_check_csr<<<blocks_for_waves(n), kBlock, 0, s>>>(n, row_ptr, col, symmetric ? 1u : 0u, ctr);
         rc = read_counters(ctr, h, s);
         if (rc) return rc;
         if (h->error) return PLL_EINVAL;
     }
-
-    // --- rank space (a0)
-    k_make_rank<<<blocks_for_threads(n), kBlock, 0, s>>>(n, order, rank);
+    // rank space (a0)
+    k_make_rank<<<blocks_for_threads(n), kBlock, 0, s>>>(n, order, R->rank);
     k_rank_degrees<<<blocks_for_threads(n), kBlock, 0, s>>>(n, order, row_ptr, tmp32);
-    TRY_HIP(scan_u32_to_u64(tmp32, n, rrow, scan_scratch, s));
-    k_relabel_cols<<<blocks_for_waves(n), kBlock, 0, s>>>(n, order, row_ptr, col, rank, rrow, rcol);
+    TRY_HIP(scan_u32_to_u64(tmp32, n, R->rrow, R->scan_scratch, s));
+    k_relabel_cols<<<blocks_for_waves(n), kBlock, 0, s>>>(n, order, row_ptr, col, R->rank, R->rrow, R->rcol);
     TRY_HIP(hipGetLastError());
+    return PLL_OK;
+}
 
-    // --- build state
-    BuildArgs A{};
+// Working buffers of the batch phases over the rank-space CSR (rrow, rcol);
+// the pruning checks read the build's own table until the caller says
+// otherwise.  Returns the spare offsets array of the arena relayout.
+int init_state(DevAllocs& M, BuildArgs& A, uint32_t n, uint64_t nnz, uint32_t W, const uint64_t* rrow,
+               const uint32_t* rcol, DevCounters* ctr, hipStream_t s, uint64_t** spare_off) {
+    A = BuildArgs{};
     A.n = n;
     A.W = W;
-    A.bstride = bstride;
+    A.bstride = 64 * W;
     A.rrow = rrow;
     A.rcol = rcol;
     A.loff = M.get<uint64_t>((size_t)n + 1);
-    uint64_t* spare_off = M.get<uint64_t>((size_t)n + 1);
+    *spare_off = M.get<uint64_t>((size_t)n + 1);
     A.llen = M.get<uint32_t>(n);
     A.lcap = M.get<uint32_t>(n);
     A.C = M.get<uint64_t>((size_t)n * W);
     A.msgs = M.get<uint64_t>((size_t)n * W);
-    A.T = M.get<uint8_t>((size_t)n * bstride);
+    A.T = M.get<uint8_t>((size_t)n * A.bstride);
     A.rowmask = M.get<uint32_t>(n);
+    A.Tchk = A.T;
+    A.rmchk = A.rowmask;
     A.hq_seg = 2 * (nnz / kHeavy) + 64;
     for (int q = 0; q < 2; ++q) {
         A.act_v[q] = M.get<uint32_t>(n);
@@ -692,10 +717,64 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     TRY_HIP(hipMemsetAsync(A.llen, 0, sizeof(uint32_t) * n, s));
     TRY_HIP(hipMemsetAsync(A.C, 0, sizeof(uint64_t) * n * W, s));
     TRY_HIP(hipMemsetAsync(A.msgs, 0, sizeof(uint64_t) * n * W, s));
-    TRY_HIP(hipMemsetAsync(A.T, 0xFF, (size_t)n * bstride, s));
+    TRY_HIP(hipMemsetAsync(A.T, 0xFF, (size_t)n * A.bstride, s));
     TRY_HIP(hipMemsetAsync(A.rowmask, 0, sizeof(uint32_t) * n, s));
     TRY_HIP(hipMemsetAsync(A.recv_stamp, 0, sizeof(uint32_t) * n, s));
     TRY_HIP(hipMemsetAsync(A.touch_stamp, 0, sizeof(uint32_t) * n, s));
+    return PLL_OK;
+}
+
+// Final label CSR of one build, by vertex id with hubs as ranks (a8):
+// lengths, their scan, then the copy out of the arena.  The entry array is
+// padded to whole 4-entry chunks: the query kernel reads labels in aligned
+// 16-byte loads.
+int finalize_labels(DevAllocs& M, const BuildArgs& A, const uint32_t* rank, uint32_t* tmp32,
+                    uint64_t* scan_scratch, hipStream_t s, uint64_t** d_off, uint32_t** d_ent, uint64_t* total) {
+    const uint32_t n = A.n;
+    k_final_lens<<<blocks_for_threads(n), kBlock, 0, s>>>(n, rank, A.llen, tmp32, A.ctr);
+    *d_off = M.get_out<uint64_t>((size_t)n + 1);
+    if (M.err != hipSuccess) return status_of(M.err);
+    TRY_HIP(scan_u32_to_u64(tmp32, n, *d_off, scan_scratch, s));
+    TRY_HIP(hipMemcpyAsync(total, *d_off + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    TRY_HIP(hipStreamSynchronize(s));
+    *d_ent = M.get_out<uint32_t>(std::max<uint64_t>((*total + 3) & ~3ull, 4));
+    if (M.err != hipSuccess) return status_of(M.err);
+    k_final_copy<<<std::min<uint32_t>(blocks_for_waves(n), 1024), kBlock, 0, s>>>(n, rank, A.loff, A.llen, A.arena,
+                                                                                   *d_off, *d_ent, A.ctr);
+    TRY_HIP(hipGetLastError());
+    return PLL_OK;
+}
+
+// One complete build attempt with a given initial arena size.
+int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* order,
+                  uint32_t b, uint32_t flags, uint64_t arena_hint, bool arena_fixed, uint32_t max_workgroups,
+                  hipStream_t s, pll_index* idx, uint64_t* used_arena) {
+    DevAllocs M;
+    M.s = s;
+    HostCounters HC;
+    PhaseProfiler P;
+    P.on = (flags & PLL_FLAG_PROFILE) != 0;
+    P.s = s;
+    TRY_HIP(pll_pinned_alloc((void**)&HC.p, sizeof(DevCounters)));
+    DevCounters* h = HC.p;
+    const uint32_t W = (b + 63) / 64;
+
+    DevCounters* ctr = M.get<DevCounters>(1);
+    if (M.err != hipSuccess) return status_of(M.err);
+    TRY_HIP(hipMemsetAsync(ctr, 0, sizeof(DevCounters), s));
+    hipEvent_t e_prep = P.mark();
+    RankCsr RC;
+    int rc = prepare_rank_csr(M, ctr, h, n, nnz, row_ptr, col, order, flags, true, s, &RC);
+    if (rc) return rc;
+    uint32_t* rank = RC.rank;
+    uint32_t* tmp32 = RC.tmp32;
+    uint64_t* scan_scratch = RC.scan_scratch;
+
+    // --- build state
+    BuildArgs A{};
+    uint64_t* spare_off = nullptr;
+    rc = init_state(M, A, n, nnz, W, RC.rrow, RC.rcol, ctr, s, &spare_off);
+    if (rc) return rc;
     // initial label layout: capacities 16/32, then the bump regions
     uint64_t region_cap = std::max<uint64_t>(4096, arena_hint / PLL_SHARDS);
     rc = relayout_arena(M, A, spare_off, tmp32, scan_scratch, true, region_cap, arena_fixed ? arena_hint : 0, s);
@@ -809,19 +888,13 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     if (h->error) return device_error_status(h->error);
     P.resolve();
     hipEvent_t e_fin = P.mark();
-    k_final_lens<<<blocks_for_threads(n), kBlock, 0, s>>>(n, rank, A.llen, tmp32, ctr);
-    uint64_t* d_off = M.get_out<uint64_t>((size_t)n + 1);
-    if (M.err != hipSuccess) return status_of(M.err);
-    TRY_HIP(scan_u32_to_u64(tmp32, n, d_off, scan_scratch, s));
+    uint64_t* d_off = nullptr;
+    uint32_t* d_ent = nullptr;
     uint64_t total = 0;
-    TRY_HIP(hipMemcpyAsync(&total, d_off + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    TRY_HIP(hipStreamSynchronize(s));
-    // whole 4-entry chunks: the query kernel reads labels in aligned 16-byte loads
-    uint32_t* d_ent = M.get_out<uint32_t>(std::max<uint64_t>((total + 3) & ~3ull, 4));
+    rc = finalize_labels(M, A, rank, tmp32, scan_scratch, s, &d_off, &d_ent, &total);
+    if (rc) return rc;
     uint32_t* d_order = M.get_out<uint32_t>(n);
     if (M.err != hipSuccess) return status_of(M.err);
-    k_final_copy<<<std::min<uint32_t>(blocks_for_waves(n), 1024), kBlock, 0, s>>>(n, rank, A.loff, A.llen, A.arena,
-                                                                                   d_off, d_ent, ctr);
     TRY_HIP(hipMemcpyAsync(d_order, order, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
     TRY_HIP(hipGetLastError());
     P.span(PLL_PHASE_FINAL, e_fin, P.mark(), 5);
@@ -841,6 +914,8 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     I.n = n;
     I.batch_size = b;
     I.total_entries = total;
+    I.in_entries = total;
+    I.out_entries = total;
     I.label_bytes = total * sizeof(uint32_t) + ((uint64_t)n + 1) * sizeof(uint64_t);
     I.max_dist = h->max_dist;
     I.max_label = h->max_label;
@@ -863,10 +938,216 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     return PLL_OK;
 }
 
+// Directed graphs (Section 5.1).  Two coupled builds run in lockstep:
+// the forward side grows L_in along out-arcs and the backward side grows
+// L_out along in-arcs, each with its own candidate bit-vectors, queues and
+// distance table.  A side's table holds its own label of the batch roots
+// (forward: L_in(u_k), filled at batch init and when a root accepts an
+// entry); a side's pruning checks read the other side's table, so a forward
+// check of u_k at v scans L_in(v) against L_out(u_k) and a backward check
+// scans L_out(v) against L_in(u_k).  Round j of both sides runs after round
+// j-1 of both: an entry that must prune a round-j candidate has distance
+// below j on both of its sides, and an entry accepted in round j on either
+// side cannot prune a round-j candidate of the other (its hub would have to
+// be the candidate vertex itself, which the rank mask keeps out).
+int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint32_t* col,
+                           const uint32_t* order, uint32_t b, uint32_t flags, uint64_t arena_hint, bool arena_fixed,
+                           hipStream_t s, pll_index* idx, uint64_t* used_arena) {
+    DevAllocs M;
+    M.s = s;
+    HostCounters HC[2];
+    PhaseProfiler P;
+    P.on = (flags & PLL_FLAG_PROFILE) != 0;
+    P.s = s;
+    for (auto& hc : HC) TRY_HIP(pll_pinned_alloc((void**)&hc.p, sizeof(DevCounters)));
+    DevCounters* h[2] = {HC[0].p, HC[1].p};
+    const uint32_t W = (b + 63) / 64;
+
+    DevCounters* ctr = M.get<DevCounters>(2);
+    if (M.err != hipSuccess) return status_of(M.err);
+    TRY_HIP(hipMemsetAsync(ctr, 0, 2 * sizeof(DevCounters), s));
+    hipEvent_t e_prep = P.mark();
+    RankCsr RC;
+    int rc = prepare_rank_csr(M, ctr, h[0], n, nnz, row_ptr, col, order, flags, false, s, &RC);
+    if (rc) return rc;
+    uint32_t* tmp32 = RC.tmp32;
+    uint64_t* scan_scratch = RC.scan_scratch;
+
+    // in-arcs in rank space
+    uint64_t* irow = M.get<uint64_t>((size_t)n + 1);
+    uint32_t* icol = M.get<uint32_t>(nnz ? nnz : 1);
+    if (M.err != hipSuccess) return status_of(M.err);
+    TRY_HIP(hipMemsetAsync(tmp32, 0, sizeof(uint32_t) * ((size_t)n + 1), s));
+    if (nnz) k_count_heads<<<blocks_for_threads(nnz), kBlock, 0, s>>>(nnz, RC.rcol, tmp32);
+    TRY_HIP(scan_u32_to_u64(tmp32, n, irow, scan_scratch, s));
+    TRY_HIP(hipMemsetAsync(tmp32, 0, sizeof(uint32_t) * ((size_t)n + 1), s));
+    k_fill_transpose<<<blocks_for_waves(n), kBlock, 0, s>>>(n, RC.rrow, RC.rcol, irow, tmp32, icol);
+    TRY_HIP(hipGetLastError());
+
+    // side 0: forward (L_in, out-arcs); side 1: backward (L_out, in-arcs)
+    BuildArgs A[2];
+    uint64_t* spare_off[2] = {nullptr, nullptr};
+    rc = init_state(M, A[0], n, nnz, W, RC.rrow, RC.rcol, ctr, s, &spare_off[0]);
+    if (rc) return rc;
+    rc = init_state(M, A[1], n, nnz, W, irow, icol, ctr + 1, s, &spare_off[1]);
+    if (rc) return rc;
+    for (int d = 0; d < 2; ++d) {
+        A[d].Tchk = A[d ^ 1].T;
+        A[d].rmchk = A[d ^ 1].rowmask;
+    }
+    const uint64_t region_cap = std::max<uint64_t>(4096, arena_hint / (2 * PLL_SHARDS));
+    for (int d = 0; d < 2; ++d) {
+        rc = relayout_arena(M, A[d], spare_off[d], tmp32, scan_scratch, true, region_cap,
+                            arena_fixed ? arena_hint / 2 : 0, s);
+        if (rc) return rc;
+    }
+    P.span(PLL_PHASE_PREP, e_prep, P.mark(), (flags & PLL_FLAG_VALIDATE) ? 20 : 19);
+
+    auto read_both = [&]() -> int {
+        TRY_HIP(hipMemcpyAsync(h[0], ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+        TRY_HIP(hipMemcpyAsync(h[1], ctr + 1, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+        TRY_HIP(hipStreamSynchronize(s));
+        return PLL_OK;
+    };
+    const uint32_t recheck = (flags & PLL_FLAG_RECHECK) ? 1u : 0u;
+    uint32_t rstamp = 0, bstamp = 0;
+    uint64_t rounds = 0, batches = 0;
+    unsigned long long accepted_seen[2] = {0, 0};
+    for (uint32_t ib = 0; ib < n; ib += b) {
+        const uint32_t bs = std::min(b, n - ib);
+        ++bstamp;
+        ++batches;
+        hipEvent_t e0 = P.mark();
+        for (int d = 0; d < 2; ++d) {
+            k_batch_prep<<<1, 64, 0, s>>>(A[d].ctr);
+            k_batch_init<<<blocks_for_waves(bs), kBlock, 0, s>>>(A[d], ib, bs, bstamp);
+        }
+        P.span(PLL_PHASE_INIT, e0, P.mark(), 4);
+        uint32_t p[2] = {0, 0}, nact[2] = {bs, bs};
+        uint64_t heavy_waves[2] = {1024, 1024};
+        bool live[2] = {true, true};
+        for (uint32_t j = 1; live[0] || live[1]; ++j) {
+            ++rstamp;
+            ++rounds;
+            for (int d = 0; d < 2; ++d) {
+                if (!live[d]) continue;
+                hipEvent_t r0 = P.mark();
+                k_push<<<blocks_for_waves(nact[d] + heavy_waves[d]), kBlock, 0, s>>>(A[d], ib, p[d], nact[d], rstamp,
+                                                                                    bstamp);
+                hipEvent_t r1 = P.mark();
+                const uint32_t check_blocks = blocks_for_waves(std::min<uint64_t>(n, 16ull * nact[d] + 2048));
+                dispatch_check(check_blocks, s, A[d], ib, bs, j, p[d], 0);
+                hipEvent_t r2 = P.mark();
+                P.span(PLL_PHASE_PUSH, r0, r1, 1);
+                P.span(PLL_PHASE_CHECK, r1, r2, 1);
+            }
+            TRY_HIP(hipGetLastError());
+            rc = read_both();
+            if (rc) return rc;
+            P.resolve();
+            for (int d = 0; d < 2; ++d) {
+                if (h[d]->error) return device_error_status(h[d]->error);
+                if (!live[d]) continue;
+                const unsigned long long acc_now = sum_stat(h[d], PLL_ST_ACC);
+                if (acc_now == accepted_seen[d]) {  // this side accepted nothing: its search is done
+                    live[d] = false;
+                    continue;
+                }
+                accepted_seen[d] = acc_now;
+                nact[d] = sum_recv(h[d], p[d]);
+                p[d] ^= 1u;
+                heavy_waves[d] = sum_hq(h[d], p[d]);
+            }
+        }
+        // both sides' batch ends read the other side's table, so the tables
+        // are cleared only after both
+        hipEvent_t e1 = P.mark();
+        for (int d = 0; d < 2; ++d) dispatch_batch_end(blocks_for_waves(sum_touched(h[d])), s, A[d], ib, bs, recheck);
+        for (int d = 0; d < 2; ++d) k_clear_table<<<blocks_for_waves(bs), kBlock, 0, s>>>(A[d], ib, bs);
+        P.span(PLL_PHASE_END, e1, P.mark(), 4);
+        TRY_HIP(hipGetLastError());
+        for (int d = 0; d < 2; ++d) {
+            if (!arena_fixed && ib + b < n && max_top(h[d]) * 2 > A[d].region_cap) {
+                rc = relayout_arena(M, A[d], spare_off[d], tmp32, scan_scratch, false, A[d].region_cap * 2, 0, s);
+                if (rc) return rc;
+            }
+        }
+    }
+
+    // --- finalize: L_in and L_out by vertex id
+    rc = read_both();
+    if (rc) return rc;
+    for (int d = 0; d < 2; ++d)
+        if (h[d]->error) return device_error_status(h[d]->error);
+    P.resolve();
+    hipEvent_t e_fin = P.mark();
+    uint64_t* d_off[2] = {nullptr, nullptr};
+    uint32_t* d_ent[2] = {nullptr, nullptr};
+    uint64_t total[2] = {0, 0};
+    for (int d = 0; d < 2; ++d) {
+        rc = finalize_labels(M, A[d], RC.rank, tmp32, scan_scratch, s, &d_off[d], &d_ent[d], &total[d]);
+        if (rc) return rc;
+    }
+    uint32_t* d_order = M.get_out<uint32_t>(n);
+    if (M.err != hipSuccess) return status_of(M.err);
+    TRY_HIP(hipMemcpyAsync(d_order, order, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+    TRY_HIP(hipGetLastError());
+    P.span(PLL_PHASE_FINAL, e_fin, P.mark(), 9);
+    rc = read_both();
+    if (rc) return rc;
+    P.resolve();
+
+    idx->n = n;
+    idx->directed = true;
+    idx->total = total[0];
+    idx->d_off = d_off[0];
+    idx->d_ent = d_ent[0];
+    idx->total_out = total[1];
+    idx->d_off_out = d_off[1];
+    idx->d_ent_out = d_ent[1];
+    idx->d_order = d_order;
+    for (int d = 0; d < 2; ++d) {
+        M.forget(d_off[d]);
+        M.forget(d_ent[d]);
+    }
+    M.forget(d_order);
+    pll_index_info& I = idx->info;
+    I.n = n;
+    I.batch_size = b;
+    I.directed = 1;
+    I.in_entries = total[0];
+    I.out_entries = total[1];
+    I.total_entries = total[0] + total[1];
+    I.label_bytes = (total[0] + total[1]) * sizeof(uint32_t) + 2 * ((uint64_t)n + 1) * sizeof(uint64_t);
+    I.max_dist = std::max(h[0]->max_dist, h[1]->max_dist);
+    I.max_label = std::max(h[0]->max_label, h[1]->max_label);
+    I.batches = batches;
+    I.rounds = rounds;
+    auto both = [&](int k) { return sum_stat(h[0], k) + sum_stat(h[1], k); };
+    I.candidates = both(PLL_ST_CAND);
+    I.accepted = both(PLL_ST_ACC);
+    I.edges_scanned = both(PLL_ST_EDGES);
+    I.recheck_removed = both(PLL_ST_RECHECK);
+    I.gang = 1;
+    I.check_entries_read = both(PLL_ST_READ);
+    I.check_table_reads = both(PLL_ST_TABLE);
+    I.check_cost_pos = both(PLL_ST_COST_POS);
+    I.check_cost_neg = both(PLL_ST_COST_NEG);
+    for (int ph = 0; ph < PLL_NUM_PHASES; ++ph) {
+        I.phase_ms[ph] = P.ms[ph];
+        I.phase_launches[ph] = P.launches[ph];
+    }
+    *used_arena = 0;
+    for (int d = 0; d < 2; ++d) *used_arena += A[d].region_base + PLL_SHARDS * A[d].region_cap;
+    return PLL_OK;
+}
+
 }  // namespace
 
-int pll_build_one(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
-                  const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out) {
+namespace {
+
+int build_index(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col, const uint32_t* d_order,
+                const pll_build_opts* opts, bool directed, hipStream_t stream, pll_index** out) {
     if (!out) return PLL_EINVAL;
     *out = nullptr;
     pll_build_opts o{};
@@ -878,6 +1159,7 @@ int pll_build_one(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uin
     if ((o.flags & PLL_FLAG_RELAXED) && !(o.flags & PLL_FLAG_RECHECK)) return PLL_EINVAL;
     if (o.flags & ~(PLL_FLAG_VALIDATE | PLL_FLAG_RECHECK | PLL_FLAG_RELAXED | PLL_FLAG_PROFILE | PLL_FLAG_PERSISTENT))
         return PLL_EINVAL;
+    if (directed && (o.flags & (PLL_FLAG_RELAXED | PLL_FLAG_PERSISTENT))) return PLL_EINVAL;
     const uint32_t ql = o.query_lanes;
     if (!(ql == 0 || ql == 1 || ql == 4 || ql == 8 || ql == 16 || ql == 32 || ql == 64)) return PLL_EINVAL;
     if (n > 0 && (!d_row_ptr || !d_order || (nnz && !d_col))) return PLL_EINVAL;
@@ -898,15 +1180,24 @@ int pll_build_one(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uin
         idx->d_off = M.get_out<uint64_t>(1);
         idx->d_ent = M.get_out<uint32_t>(4);
         idx->d_order = M.get_out<uint32_t>(1);
+        if (directed) {
+            idx->directed = true;
+            idx->info.directed = 1;
+            idx->d_off_out = M.get_out<uint64_t>(1);
+            idx->d_ent_out = M.get_out<uint32_t>(4);
+        }
         if (M.err != hipSuccess) {
             rc = status_of(M.err);
         } else if (hipMemsetAsync(idx->d_off, 0, sizeof(uint64_t), stream) != hipSuccess ||
+                   (directed && hipMemsetAsync(idx->d_off_out, 0, sizeof(uint64_t), stream) != hipSuccess) ||
                    hipStreamSynchronize(stream) != hipSuccess) {
             rc = PLL_EDEVICE;
         } else {
             M.forget(idx->d_off);
             M.forget(idx->d_ent);
             M.forget(idx->d_order);
+            M.forget(idx->d_off_out);
+            M.forget(idx->d_ent_out);
             idx->info.batch_size = b;
             idx->info.label_bytes = sizeof(uint64_t);
             idx->info.build_attempts = 1;
@@ -916,8 +1207,10 @@ int pll_build_one(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uin
         uint64_t cap = fixed ? o.arena_entries : std::max<uint64_t>(1ull << 20, 4 * nnz + 16ull * n);
         for (uint32_t attempt = 1;; ++attempt) {
             uint64_t used = 0;
-            rc = build_attempt(n, nnz, d_row_ptr, d_col, d_order, b, o.flags, cap, fixed, o.max_workgroups, stream,
-                               idx, &used);
+            rc = directed ? build_attempt_directed(n, nnz, d_row_ptr, d_col, d_order, b, o.flags, cap, fixed, stream,
+                                                   idx, &used)
+                          : build_attempt(n, nnz, d_row_ptr, d_col, d_order, b, o.flags, cap, fixed,
+                                          o.max_workgroups, stream, idx, &used);
             idx->info.build_attempts = attempt;
             idx->info.arena_entries = used;
             if (rc == PLL_ENOSPC && !fixed && attempt < 8) {
@@ -935,4 +1228,16 @@ int pll_build_one(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uin
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = idx;
     return PLL_OK;
+}
+
+}  // namespace
+
+int pll_build_one(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
+                  const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out) {
+    return build_index(n, nnz, d_row_ptr, d_col, d_order, opts, false, stream, out);
+}
+
+int pll_build_directed(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
+                       const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out) {
+    return build_index(n, nnz, d_row_ptr, d_col, d_order, opts, true, stream, out);
 }

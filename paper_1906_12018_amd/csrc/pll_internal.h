@@ -87,6 +87,11 @@ struct BuildArgs {
     // per-batch distance table: T[h * bstride + k] = d(u_k, h) for (h, d) in L(u_k)
     uint8_t* T;
     uint32_t* rowmask;  // bit w set when row h of T has an entry in word w
+    // table the pruning checks read: T itself for an undirected graph; for a
+    // directed one, the other side's table (a forward check of candidate u_k
+    // at v scans L_in(v) against the table of L_out(u_k), and vice versa)
+    const uint8_t* Tchk;
+    const uint32_t* rmchk;
     // frontier queues (shard s owns [s * seg, (s + 1) * seg) of each)
     uint32_t* act_v[2];      // active list by parity (compact)
     uint64_t* act_delta[2];  // W words per active slot: delta L of that vertex
@@ -207,6 +212,9 @@ int pll_build_one(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uin
 int pll_query_launch(const pll_index* idx, uint64_t count, const uint32_t* d_u, const uint32_t* d_v,
                      uint32_t* d_out, hipStream_t stream);
 
+int pll_build_directed(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
+                       const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out);
+
 int pll_build_multi(uint32_t count, const pll_graph_desc* graphs, const pll_build_opts* opts, hipStream_t stream,
                     pll_index** outs);
 
@@ -218,13 +226,19 @@ struct pll_shared_store {
     int device;
 };
 
-// Final label store (what pll_index owns).
+// Final label store (what pll_index owns).  An undirected index has one
+// label per vertex (d_off / d_ent); a directed one keeps L_in there and L_out
+// in d_off_out / d_ent_out.
 struct pll_index {
     int device;
     uint32_t n;
     uint64_t total;
     uint64_t* d_off;    // [n+1], by vertex id
     uint32_t* d_ent;    // [total], packed (hub rank << 8) | dist, ascending within each list
+    bool directed;
+    uint64_t total_out;
+    uint64_t* d_off_out;  // directed only: L_out, laid out as d_off / d_ent
+    uint32_t* d_ent_out;
     uint32_t* d_order;  // [n], rank -> vertex id
     uint32_t query_lanes;
     pll_shared_store* store;  // non-null when d_ent points into a shared allocation

@@ -605,6 +605,8 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
         A.recv_stamp = (uint32_t*)(zp + o.recv_stamp);
         A.touch_stamp = (uint32_t*)(zp + o.touch_stamp);
         A.T = (uint8_t*)(tp + o.T);
+        A.Tchk = A.T;
+        A.rmchk = A.rowmask;
         J.rank = (uint32_t*)(op + o.rank);
         A.rrow = (uint64_t*)(op + o.rrow);
         A.rcol = (uint32_t*)(op + o.rcol);
@@ -733,6 +735,8 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
         I.n = graphs[g].n;
         I.batch_size = b;
         I.total_entries = R.total;
+        I.in_entries = R.total;
+        I.out_entries = R.total;
         I.label_bytes = R.total * 4 + 8 * ((uint64_t)graphs[g].n + 1);
         I.max_dist = R.max_dist;
         I.max_label = R.max_label;

@@ -89,9 +89,9 @@ __device__ inline uint64_t prune_scan(const BuildArgs& A, uint64_t off, uint32_t
         const uint32_t h = ent >> 8, d = ent & 255u;
         ok = ok && d < j;
         if (relaxed) ok = ok && h < ib;
-        const uint32_t rm = ok ? A.rowmask[h] : 0u;
+        const uint32_t rm = ok ? A.rmchk[h] : 0u;
         const uint32_t tt = ok ? (j - d) * 0x01010101u : 0u;
-        const uint8_t* row = A.T + (size_t)h * A.bstride;
+        const uint8_t* row = A.Tchk + (size_t)h * A.bstride;
         const uint64_t live_lane = cw & ~pw;
 #pragma unroll
         for (int w = 0; w < WM; ++w) {

@@ -16,6 +16,8 @@
 //    and once the window holding a list's end moves on the pair is done, so
 //    neither list is read past the point where the sequential merge stops.
 //    The pair's minimum is reduced across the group at the end.
+// For a directed index (Section 5.1) the distance from u to v merges
+// L_out(u) with L_in(v); the kernels take the two lists' arrays apart.
 #include <atomic>
 
 #include "pll_internal.h"
@@ -25,8 +27,10 @@ namespace {
 constexpr int kBlock = 256;
 constexpr uint32_t kAfter = 0xFFFFFFFFu;  // sorts after every key
 
-__global__ void __launch_bounds__(kBlock) k_query_lane(const uint64_t* __restrict__ off,
-                                                       const uint32_t* __restrict__ ent, uint32_t n, uint64_t count,
+__global__ void __launch_bounds__(kBlock) k_query_lane(const uint64_t* __restrict__ offu,
+                                                       const uint32_t* __restrict__ entu,
+                                                       const uint64_t* __restrict__ offv,
+                                                       const uint32_t* __restrict__ entv, uint32_t n, uint64_t count,
                                                        const uint32_t* __restrict__ qu,
                                                        const uint32_t* __restrict__ qv, uint32_t* __restrict__ out) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
@@ -35,26 +39,26 @@ __global__ void __launch_bounds__(kBlock) k_query_lane(const uint64_t* __restric
         uint32_t best = PLL_DIST_INF;
         uint64_t a = 0, ae = 0, b = 0, be = 0;
         if (u < n && v < n) {  // an id out of range has no label: no common hub
-            a = off[u];
-            ae = off[u + 1];
-            b = off[v];
-            be = off[v + 1];
+            a = offu[u];
+            ae = offu[u + 1];
+            b = offv[v];
+            be = offv[v + 1];
         }
         if (a < ae && b < be) {
-            uint32_t ea = ent[a], eb = ent[b];
+            uint32_t ea = entu[a], eb = entv[b];
             for (;;) {
                 const uint32_t ha = ea >> 8, hb = eb >> 8;
                 if (ha == hb) {
                     best = min(best, (ea & 255u) + (eb & 255u));
                     if (++a == ae || ++b == be) break;
-                    ea = ent[a];
-                    eb = ent[b];
+                    ea = entu[a];
+                    eb = entv[b];
                 } else if (ha < hb) {
                     if (++a == ae) break;
-                    ea = ent[a];
+                    ea = entu[a];
                 } else {
                     if (++b == be) break;
-                    eb = ent[b];
+                    eb = entv[b];
                 }
             }
         }
@@ -130,8 +134,10 @@ constexpr int kEntriesU = 2;
 constexpr int kEntriesV = 4;
 
 template <int G>
-__global__ void __launch_bounds__(kBlock) k_query_group(const uint64_t* __restrict__ off,
-                                                        const uint32_t* __restrict__ ent, uint32_t n, uint64_t count,
+__global__ void __launch_bounds__(kBlock) k_query_group(const uint64_t* __restrict__ offu,
+                                                        const uint32_t* __restrict__ entu,
+                                                        const uint64_t* __restrict__ offv,
+                                                        const uint32_t* __restrict__ entv, uint32_t n, uint64_t count,
                                                         const uint32_t* __restrict__ qu,
                                                         const uint32_t* __restrict__ qv, uint32_t* __restrict__ out) {
     static_assert(G >= 4 && G <= 64 && (G & (G - 1)) == 0, "group size");
@@ -147,17 +153,17 @@ __global__ void __launch_bounds__(kBlock) k_query_group(const uint64_t* __restri
         const uint32_t u = qu[p], v = qv[p];
         uint64_t a = 0, ae = 0, b = 0, be = 0;
         if (u < n && v < n) {  // an id out of range has no label: no common hub
-            a = off[u];
-            ae = off[u + 1];
-            b = off[v];
-            be = off[v + 1];
+            a = offu[u];
+            ae = offu[u + 1];
+            b = offv[v];
+            be = offv[v + 1];
         }
         uint32_t best = PLL_DIST_INF;
         // windows: base pointers aligned to the entries per lane; list bounds
         // relative to the window start (lists are shorter than 2^31 entries)
         constexpr uint64_t kAlignU = kEntriesU - 1, kAlignV = kEntriesV - 1;
-        const uint32_t* wa = ent + (a & ~kAlignU);
-        const uint32_t* wb = ent + (b & ~kAlignV);
+        const uint32_t* wa = entu + (a & ~kAlignU);
+        const uint32_t* wb = entv + (b & ~kAlignV);
         int32_t a_lo = (int32_t)(a & kAlignU), a_hi = (int32_t)(ae - (a & ~kAlignU));
         int32_t b_lo = (int32_t)(b & kAlignV), b_hi = (int32_t)(be - (b & ~kAlignV));
         if (!(a < ae && b < be)) a_hi = 0;  // an empty list: no common hub
@@ -249,13 +255,18 @@ void launch_group(const pll_index* idx, uint64_t count, const uint32_t* d_u, con
         if (dev >= 0 && dev < 64) cap_cache[dev].store(cap, std::memory_order_relaxed);
     }
     if (blocks > cap) blocks = cap;
-    k_query_group<G><<<(uint32_t)blocks, kBlock, 0, stream>>>(idx->d_off, idx->d_ent, idx->n, count, d_u, d_v, d_out);
+    // the source's list comes from L_out and the target's from L_in (one
+    // label serves both for an undirected index)
+    const uint64_t* offu = idx->directed ? idx->d_off_out : idx->d_off;
+    const uint32_t* entu = idx->directed ? idx->d_ent_out : idx->d_ent;
+    k_query_group<G><<<(uint32_t)blocks, kBlock, 0, stream>>>(offu, entu, idx->d_off, idx->d_ent, idx->n, count, d_u,
+                                                               d_v, d_out);
 }
 
 // Lanes per pair when the index leaves it open: the window (4 entries per
 // lane) should hold about one average label.
 uint32_t query_lanes_auto(const pll_index* idx) {
-    const uint64_t mean = idx->n ? idx->total / idx->n : 0;
+    const uint64_t mean = idx->n ? (idx->total + (idx->directed ? idx->total_out : idx->total)) / (2ull * idx->n) : 0;
     uint32_t g = 4;
     while (g < 64 && 4ull * g < mean) g *= 2;
     return g;
@@ -271,7 +282,9 @@ int pll_query_launch(const pll_index* idx, uint64_t count, const uint32_t* d_u, 
         case 1: {
             uint64_t blocks = (count + kBlock - 1) / kBlock;
             if (blocks > 65536) blocks = 65536;
-            k_query_lane<<<(uint32_t)blocks, kBlock, 0, stream>>>(idx->d_off, idx->d_ent, idx->n, count, d_u, d_v, d_out);
+            k_query_lane<<<(uint32_t)blocks, kBlock, 0, stream>>>(
+                idx->directed ? idx->d_off_out : idx->d_off, idx->directed ? idx->d_ent_out : idx->d_ent, idx->d_off,
+                idx->d_ent, idx->n, count, d_u, d_v, d_out);
             break;
         }
         case 4: launch_group<4>(idx, count, d_u, d_v, d_out, stream); break;

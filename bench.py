@@ -9,7 +9,8 @@ device-resident CSR, followed by one batched query of 10^6 uniform pairs
 events; --steps profiled builds follow, and their HIP events give the
 kernel times of the roofline entry.  Other modes: --mode query (queries
 alone), --mode batched (the 256-graph one-launch build), --mode serve (the
-serving loop), each printing its own JSON line.
+serving loop), --mode directed (directed R-MAT build and query), each
+printing its own JSON line.
 """
 from __future__ import annotations
 
@@ -265,6 +266,89 @@ def cpu_baseline(g, order, total_entries, u, v):
                       "sample": "the oracle's merge-join over its own labels, the same pairs"}}
 
 
+def directed_mode(args):
+    """Directed graphs (Section 5.1): R-MAT arcs of scale --directed-scale
+    (edge factor 16, a,b,c = .57,.19,.19, seed 1, not symmetrised), total
+    degree order, b = --batch-size.  A step is one directed build (L_in and
+    L_out) followed by one batched query of 10^6 uniform pairs (seed 2) over
+    L_out(u) and L_in(v).  The CPU baseline is the directed oracle on the
+    same graph and pairs."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1906_12018_amd as pll
+    dev = torch.device("cuda:0")
+    g = synth.rmat_digraph(args.directed_scale, 16, seed=1)
+    order = synth.degree_order_directed(g)
+    rp = torch.from_numpy(g.row_ptr.view(np.int64)).to(dev)
+    cl = torch.from_numpy(g.col.view(np.int32)).to(dev)
+    od = torch.from_numpy(order.view(np.int32)).to(dev)
+    pairs = 1_000_000
+    u, v = synth.query_pairs(g.n, pairs, seed=2)
+    du = torch.from_numpy(u.view(np.int32)).to(dev)
+    dv = torch.from_numpy(v.view(np.int32)).to(dev)
+    out = torch.empty_like(du)
+    torch.cuda.synchronize()
+    build_ms, query_ms, ref = [], [], None
+    for it in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        idx = pll.build_labels_directed(rp, cl, od, batch_size=args.batch_size, flags=0)
+        t1 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        idx.query(du, dv, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        info = idx.info()
+        if ref is None:
+            ref = (info["total_entries"], out.clone())
+        else:
+            assert info["total_entries"] == ref[0] and torch.equal(out, ref[1]), "steps disagree"
+        if it >= args.warmup:
+            build_ms.append((t1 - t0) * 1e3)
+            query_ms.append(e0.elapsed_time(e1))
+        idx.free()
+    prof = []
+    for _ in range(args.steps):
+        pidx = pll.build_labels_directed(rp, cl, od, batch_size=args.batch_size, flags=pll.FLAG_PROFILE)
+        prof.append(pidx.info())
+        pidx.free()
+    info = prof[-1]
+    total = info["total_entries"]
+    check_ms = float(np.mean([i["phase_ms"]["check"] for i in prof]))
+    check_bytes = 4 * info["check_entries_read"] + 64 * info["check_table_reads"] + 4 * info["accepted"]
+    check_gbs = check_bytes / (check_ms / 1e3) / 1e9
+    res = {"mode": "directed", "workload": f"directed rmat{args.directed_scale} (arcs not symmetrised) build + "
+                                           f"{pairs} query pairs",
+           "n": g.n, "arcs": g.nnz, "batch_size": args.batch_size, "steps": args.steps,
+           "build_ms_p50": float(np.median(build_ms)),
+           "entries_per_s": total * len(build_ms) / (sum(build_ms) / 1e3),
+           "label_entries": total, "in_entries": info["in_entries"], "out_entries": info["out_entries"],
+           "queries_per_s": pairs / (float(np.median(query_ms)) / 1e3),
+           "query_batch_ms_p50": float(np.median(query_ms)),
+           "rounds": info["rounds"], "batches": info["batches"], "candidates": info["candidates"],
+           "build_phase_ms": {k: round(x, 3) for k, x in info["phase_ms"].items()},
+           "roofline": {"kernel": "k_check", "bound": "hbm", "achieved": check_gbs, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": check_gbs / HBM_PEAK_GBS, "traffic": None,
+                        "launches_per_step": info["phase_launches"]["check"], "bytes_per_step": check_bytes}}
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        lin, lout = oracle.pll_labels_directed(g, order)
+        dt = time.perf_counter() - t0
+        assert lin.total + lout.total == total, "oracle and GPU label counts differ"
+        t0 = time.perf_counter()
+        want = oracle.query_directed(lin, lout, u, v)
+        q1 = time.perf_counter() - t0
+        assert np.array_equal(want, out.cpu().numpy().view(np.uint32)), "oracle and GPU distances differ"
+        res["cpu_baseline"] = {"value": total / dt, "unit": "label entries/s", "cores": 1, "kind": "oracle",
+                               "sample": f"full sequential directed PLL build of the same graph, 1 run, {dt:.2f} s; "
+                                         f"queries: the oracle's merge-join over the same {pairs} pairs",
+                               "seconds": dt, "queries_per_s_1core": pairs / q1}
+    print(json.dumps(res), flush=True)
+
+
 def serve_mode(args):
     """Serving workload: R-MAT scale-20 index resident; open-loop Poisson
     arrivals (stream 4) of query requests with sizes log-uniform in [1, 65536]
@@ -378,7 +462,8 @@ def main():
     ap.add_argument("--workload", default="rmat16", choices=sorted(WORKLOADS))
     ap.add_argument("--batch-size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="build", choices=["build", "query", "batched", "serve"])
+    ap.add_argument("--mode", default="build", choices=["build", "query", "batched", "serve", "directed"])
+    ap.add_argument("--directed-scale", type=int, default=16)
     ap.add_argument("--tune-cache", default="", help="batched mode: autotuner cache file")
     ap.add_argument("--calibrate", action="store_true",
                     help="finish with a 256 MiB read + 256 MiB write elementwise kernel (counter scale)")
@@ -398,6 +483,9 @@ def main():
         return
     if args.mode == "batched":
         batched_mode(args)
+        return
+    if args.mode == "directed":
+        directed_mode(args)
         return
     if args.mode == "query":
         query_mode(args)

@@ -15,6 +15,9 @@ Functions (all host-side, written from the paper, arXiv 1906.12018):
 * :func:`query`            -- the 2-hop distance formula of Section 2.1.
 * :func:`pll_labels_directed`, :func:`query_directed` -- the directed variant
   of Section 5.1 (L_in and L_out labels; the query merges L_out(s), L_in(t)).
+* :func:`pll_labels_weighted` -- PLL with Dijkstra for positive integer edge
+  weights (Section 5.1; the weighted baseline of Section 6).  The query is
+  :func:`query` unchanged.
 * :func:`bfs`              -- textbook BFS distances.
 
 Label sets are returned as :class:`Labels` (CSR by vertex id, hubs as ranks in
@@ -86,6 +89,8 @@ def _load():
         lib.oracle_pll_directed.restype = ctypes.c_int
         lib.oracle_query_directed.argtypes = [P, P, P, P, P, P, ctypes.c_uint64, P, P, P]
         lib.oracle_query_directed.restype = None
+        lib.oracle_pll_weighted.argtypes = [ctypes.c_uint32, P, P, P, P, ctypes.POINTER(_CLabels)]
+        lib.oracle_pll_weighted.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -228,3 +233,17 @@ def query_directed(lin: Labels, lout: Labels, s, t):
     ptr = [a.ctypes.data if a.size else None for a in arrs]
     _load().oracle_query_directed(*ptr, s.shape[0], s.ctypes.data, t.ctypes.data, out.ctypes.data)
     return out
+
+
+def pll_labels_weighted(g, order) -> Labels:
+    """PLL with Dijkstra on the weighted graph ``g`` (``g.w``: uint8 weight of
+    each CSR entry, >= 1, equal on both arcs of an edge); lists by vertex id,
+    hubs as ranks, distances uint8 (a kept distance of 255 or more raises)."""
+    row_ptr, col, order = _graph_args(g, order)
+    w = np.ascontiguousarray(g.w, dtype=np.uint8)
+    if w.shape[0] != col.shape[0]:
+        raise OracleError("one weight per CSR entry")
+    c = _CLabels()
+    _check(_load().oracle_pll_weighted(g.n, row_ptr.ctypes.data, col.ctypes.data, w.ctypes.data,
+                                       order.ctypes.data, ctypes.byref(c)), "oracle_pll_weighted")
+    return _take(c)

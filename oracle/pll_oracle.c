@@ -21,6 +21,10 @@
  *                     the directed variant of Section 5.1: L_in and L_out
  *                     labels from a forward and a backward pruned BFS per
  *                     root; the query merges L_out(s) with L_in(t).
+ *   oracle_pll_weighted
+ *                     PLL with Dijkstra for positive integer edge weights
+ *                     (Section 5.1's weighted graphs); labels follow
+ *                     Definition 2 with weighted distances.
  *   oracle_bfs        textbook breadth-first search distances.
  *
  * Conventions (readings of points the paper leaves open):
@@ -728,4 +732,127 @@ void oracle_query_directed(const uint64_t* offs, const uint32_t* hubs, const uin
         }
         out[q] = best;
     }
+}
+
+/* ---- weighted graphs: PLL with Dijkstra (Section 5.1; the weighted
+ * baseline of Section 6) -----------------------------------------------------
+ * Edge e carries a positive integer weight w[e] (the CSR is symmetric and
+ * both arcs of an edge carry the same weight).  Roots are taken in rank
+ * order; from root u = order[k] a Dijkstra search settles vertices in
+ * increasing tentative distance.  A settled v at delta gets (u, delta) in
+ * L(v) unless some hub h of L(u) and L(v) has d(u,h) + d(h,v) <= delta; only
+ * a kept v relaxes its edges, and only towards vertices ranked below u.  The
+ * result is Definition 2 with weighted distances.  Distances are stored in
+ * uint8 as in the unweighted oracle: a kept distance of 255 or more is
+ * ORACLE_EDIST.  The priority queue is a binary heap of (distance, vertex)
+ * with lazy deletion (stale items are skipped when popped).
+ */
+typedef struct { uint64_t* a; uint32_t len, cap; } heap64;
+
+static int heap_push(heap64* H, uint64_t x) {
+    if (H->len == H->cap) {
+        uint32_t nc = H->cap ? 2 * H->cap : 64;
+        uint64_t* na = (uint64_t*)realloc(H->a, sizeof(uint64_t) * nc);
+        if (!na) return ORACLE_ENOMEM;
+        H->a = na;
+        H->cap = nc;
+    }
+    uint32_t i = H->len++;
+    while (i > 0) {
+        uint32_t p = (i - 1) / 2;
+        if (H->a[p] <= x) break;
+        H->a[i] = H->a[p];
+        i = p;
+    }
+    H->a[i] = x;
+    return ORACLE_OK;
+}
+
+static uint64_t heap_pop(heap64* H) {
+    uint64_t top = H->a[0], x = H->a[--H->len];
+    uint32_t i = 0;
+    for (;;) {
+        uint32_t c = 2 * i + 1;
+        if (c >= H->len) break;
+        if (c + 1 < H->len && H->a[c + 1] < H->a[c]) c++;
+        if (H->a[c] >= x) break;
+        H->a[i] = H->a[c];
+        i = c;
+    }
+    if (H->len) H->a[i] = x;
+    return top;
+}
+
+int oracle_pll_weighted(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint8_t* w,
+                        const uint32_t* order, oracle_labels* out) {
+    memset(out, 0, sizeof(*out));
+    uint32_t* rank = make_rank(n, order);
+    if (!rank) return ORACLE_EINVAL;
+    for (uint64_t e = 0; e < row_ptr[n]; ++e)
+        if (w[e] == 0) { free(rank); return ORACLE_EINVAL; }
+    vlist* L = (vlist*)calloc(n ? n : 1, sizeof(vlist));
+    uint8_t* T = (uint8_t*)malloc(n ? n : 1);
+    uint32_t* tent = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint32_t* stamp = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint8_t* settled = (uint8_t*)malloc(n ? n : 1);
+    heap64 H = {0};
+    int rc = ORACLE_OK;
+    uint64_t checks = 0, added = 0, edges = 0, scanned = 0, cost_pos = 0, cost_neg = 0;
+    if (!L || !T || !tent || !stamp || !settled) { rc = ORACLE_ENOMEM; goto done; }
+    memset(T, INF8, n);
+    for (uint32_t i = 0; i < n; ++i) stamp[i] = DIST_INF;
+    for (uint32_t k = 0; k < n && !rc; ++k) {
+        uint32_t u = order[k];
+        vlist* Lu = &L[u];
+        for (uint32_t i = 0; i < Lu->len; ++i) T[Lu->hub[i]] = Lu->d[i];
+        /* stamp[v] == k: tent[v] and settled[v] belong to this search */
+        stamp[u] = k; tent[u] = 0; settled[u] = 0;
+        H.len = 0;
+        rc = heap_push(&H, (uint64_t)u);
+        while (!rc && H.len) {
+            uint64_t top = heap_pop(&H);
+            uint32_t v = (uint32_t)(top & 0xFFFFFFFFu), delta = (uint32_t)(top >> 32);
+            if (settled[v] || delta != tent[v]) continue;  /* stale item */
+            settled[v] = 1;
+            checks++;
+            vlist* Lv = &L[v];
+            uint32_t m = DIST_INF;
+            for (uint32_t i = 0; i < Lv->len; ++i) {
+                uint32_t th = T[Lv->hub[i]];
+                if (th != INF8 && th + Lv->d[i] < m) m = th + Lv->d[i];
+            }
+            scanned += Lv->len;
+            if (!(delta < m)) { cost_neg += Lv->len; continue; }
+            cost_pos += Lv->len;
+            if (delta >= INF8) { rc = ORACLE_EDIST; break; }
+            rc = vlist_push(Lv, k, delta);
+            if (rc) break;
+            added++;
+            for (uint64_t e = row_ptr[v]; e < row_ptr[v + 1] && !rc; ++e) {
+                uint32_t x = col[e];
+                edges++;
+                if (rank[x] <= k) continue;
+                uint32_t nd = delta + w[e];
+                if (stamp[x] != k) { stamp[x] = k; tent[x] = DIST_INF; settled[x] = 0; }
+                if (!settled[x] && nd < tent[x]) {
+                    tent[x] = nd;
+                    rc = heap_push(&H, ((uint64_t)nd << 32) | x);
+                }
+            }
+        }
+        for (uint32_t i = 0; i < Lu->len; ++i) T[Lu->hub[i]] = INF8;
+    }
+    if (!rc) {
+        rc = vlists_to_csr(L, n, 0, out);
+        out->counters[0] = checks;
+        out->counters[1] = added;
+        out->counters[2] = edges;
+        out->counters[5] = scanned;
+        out->counters[6] = cost_pos;
+        out->counters[7] = cost_neg;
+    }
+done:
+    if (L) vlists_free(L, n);
+    free(T); free(tent); free(stamp); free(settled); free(rank); free(H.a);
+    return rc;
 }

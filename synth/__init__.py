@@ -291,3 +291,58 @@ def degree_order_directed(g: DiGraph) -> np.ndarray:
     deg = g.out_degrees() + g.in_degrees()
     ids = np.arange(g.n, dtype=np.int64)
     return np.lexsort((ids, -deg)).astype(np.uint32)
+
+
+# --- weighted graphs ----------------------------------------------------------------------------
+
+@dataclass
+class WGraph:
+    """Undirected graph with positive integer edge weights: the CSR of Graph
+    plus w[e], the weight of CSR entry e (both arcs of an edge carry the same
+    weight)."""
+    n: int
+    row_ptr: np.ndarray  # uint64[n+1]
+    col: np.ndarray      # uint32[nnz]
+    w: np.ndarray        # uint8[nnz]
+    name: str = ""
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.shape[0])
+
+    @property
+    def num_edges(self) -> int:
+        return self.nnz // 2
+
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.row_ptr).astype(np.int64)
+
+
+def _mix64(z: np.ndarray) -> np.ndarray:
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def splitmix64_at(seed: int, k: np.ndarray) -> np.ndarray:
+    """Draw k of stream `seed` for any array of draw indices (graphgen.c's definition)."""
+    k = np.asarray(k, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        return _mix64(np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + (k + np.uint64(1)) * np.uint64(GOLDEN))
+
+
+def with_weights(g: Graph, lo: int = 1, hi: int = 7, seed: int = 5) -> WGraph:
+    """Weights uniform in [lo, hi] (the paper's recipe for its weighted runs
+    is 1..7, Section 6): edge {a, b}, a < b, takes draw a * n + b of stream
+    `seed`, so both arcs agree."""
+    rows = np.repeat(np.arange(g.n, dtype=np.uint64), np.diff(g.row_ptr).astype(np.int64))
+    cols = g.col.astype(np.uint64)
+    a, b = np.minimum(rows, cols), np.maximum(rows, cols)
+    x = splitmix64_at(seed, a * np.uint64(g.n) + b)
+    w = (lo + bounded(x, hi - lo + 1)).astype(np.uint8)
+    return WGraph(n=g.n, row_ptr=g.row_ptr, col=g.col, w=w, name=f"{g.name}_w{lo}-{hi}_s{seed}")
+
+
+def constant_weights(g: Graph, c: int) -> WGraph:
+    return WGraph(n=g.n, row_ptr=g.row_ptr, col=g.col, w=np.full(g.nnz, c, dtype=np.uint8), name=f"{g.name}_c{c}")

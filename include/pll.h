@@ -1,9 +1,10 @@
 /*
  * pll.h -- C ABI of the MI355X (gfx950) pruned landmark labeling library.
  *
- * The library builds the canonical 2-hop distance labeling of an unweighted
- * graph (undirected, or directed with in- and out-labels) for a given vertex
- * order, and answers exact distance queries from it.  Paper: Jin et al., "Pruned Landmark Labeling Meets Vertex
+ * The library builds the canonical 2-hop distance labeling of a graph
+ * (undirected; directed with in- and out-labels; or undirected with positive
+ * integer edge weights) for a given vertex order, and answers exact distance
+ * queries from it.  Paper: Jin et al., "Pruned Landmark Labeling Meets Vertex
  * Centric Computation" (arXiv 1906.12018).
  *
  *   Problem statement (Section 2.1, Definitions 1-2): given G = (V, E) and a
@@ -122,7 +123,7 @@ typedef struct {
     double phase_ms[PLL_NUM_PHASES];         /* device time per phase (PLL_FLAG_PROFILE, else 0) */
     uint64_t phase_launches[PLL_NUM_PHASES]; /* kernel launches per phase (PLL_FLAG_PROFILE, else 0) */
     uint32_t directed;        /* 1 for an index of pll_build_labels_directed */
-    uint32_t reserved_info;
+    uint32_t weighted;        /* 1 for an index of pll_build_labels_weighted */
     uint64_t in_entries;      /* directed: sum of |L_in(v)|; undirected: total_entries (one label serves both) */
     uint64_t out_entries;     /* directed: sum of |L_out(v)|; undirected: total_entries */
 } pll_index_info;
@@ -182,6 +183,31 @@ int pll_build_labels(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const 
 int pll_build_labels_directed(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
                               const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream,
                               pll_index** out);
+
+/*
+ * Build the labels of an undirected graph with positive integer edge weights
+ * (Section 5.1, weighted graphs): Definition 2 with weighted distances, the
+ * labels PLL with Dijkstra computes.  The batch rounds become Bellman-Ford
+ * iterations: a candidate travels with its own distance d + w_e, passes only
+ * if it is shorter than every earlier arrival of its root at that vertex in
+ * the batch, and is checked at that distance.  Such rounds can accept
+ * non-canonical entries, so every batch ends with the recheck (the one
+ * PLL_FLAG_RECHECK asks for in unweighted builds), which here is always on
+ * and removes them; recheck_removed counts them.
+ *   d_w         uint8[nnz], the weight of each CSR entry, 1..254; both arcs
+ *               of an edge carry the same weight (checked under
+ *               PLL_FLAG_VALIDATE; a zero weight is always PLL_EINVAL)
+ *   other arguments as for pll_build_labels; PLL_FLAG_RELAXED and
+ *   PLL_FLAG_PERSISTENT are PLL_EINVAL
+ * Distances stay uint8: PLL_EDIST when a candidate path of 255 or more
+ * reaches a vertex that no shorter candidate of the same root has reached
+ * yet (so a graph whose shortest distances all fit can still fail when a
+ * long detour arrives first).  The index answers pll_query with weighted
+ * distances.
+ */
+int pll_build_labels_weighted(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
+                              const uint8_t* d_w, const uint32_t* d_order, const pll_build_opts* opts,
+                              hipStream_t stream, pll_index** out);
 
 /*
  * Exact distances for `count` pairs (Section 2.1, the 2-hop query).

@@ -9,7 +9,9 @@ Paper: Jin et al., "Pruned Landmark Labeling Meets Vertex Centric
 Computation" (arXiv 1906.12018): BVC-PLL (Section 4.2, Algorithm 4) builds the
 canonical 2-hop labeling (Definition 2) for a vertex order; the 2-hop query
 (Section 2.1) merges two hub-sorted lists.  Directed graphs (Section 5.1) get
-L_in and L_out labels, and the query merges L_out(u) with L_in(v).
+L_in and L_out labels, and the query merges L_out(u) with L_in(v); weighted
+graphs (Section 5.1) run the rounds as Bellman-Ford iterations with a
+batch-end recheck.
 """
 from __future__ import annotations
 
@@ -30,7 +32,7 @@ DEFAULT_BATCH = 1024
 LABELS_IN, LABELS_OUT = 0, 1
 
 EXPORTED_SYMBOLS = (
-    "pll_build_labels", "pll_build_labels_directed", "pll_query", "pll_index_info_get", "pll_export_labels",
+    "pll_build_labels", "pll_build_labels_directed", "pll_build_labels_weighted", "pll_query", "pll_index_info_get", "pll_export_labels",
     "pll_export_labels_side",
     "pll_build_labels_batched", "pll_index_free", "pll_status_string",
     "pll_server_create", "pll_server_add_index", "pll_server_index", "pll_server_submit", "pll_server_poll",
@@ -84,7 +86,7 @@ class IndexInfo(ctypes.Structure):
         ("phase_ms", ctypes.c_double * 7),
         ("phase_launches", ctypes.c_uint64 * 7),
         ("directed", ctypes.c_uint32),
-        ("reserved_info", ctypes.c_uint32),
+        ("weighted", ctypes.c_uint32),
         ("in_entries", ctypes.c_uint64),
         ("out_entries", ctypes.c_uint64),
     ]
@@ -180,6 +182,8 @@ def load_library(path: str = LIB_PATH):
     lib.pll_export_labels_side.restype = ctypes.c_int
     lib.pll_build_labels_directed.argtypes = [U32, U64, P, P, P, ctypes.POINTER(BuildOpts), P, ctypes.POINTER(P)]
     lib.pll_build_labels_directed.restype = ctypes.c_int
+    lib.pll_build_labels_weighted.argtypes = [U32, U64, P, P, P, P, ctypes.POINTER(BuildOpts), P, ctypes.POINTER(P)]
+    lib.pll_build_labels_weighted.restype = ctypes.c_int
     lib.pll_export_labels.restype = ctypes.c_int
     lib.pll_build_labels_batched.argtypes = [U32, ctypes.POINTER(GraphDesc), ctypes.POINTER(BuildOpts), P,
                                              ctypes.POINTER(P)]
@@ -348,6 +352,31 @@ def build_labels_directed(row_ptr: torch.Tensor, col: torch.Tensor, order: torch
                                                   ctypes.byref(h))
     if rc:
         raise PllError(rc, "pll_build_labels_directed")
+    return Index(h.value, order.device)
+
+
+def build_labels_weighted(row_ptr: torch.Tensor, col: torch.Tensor, weights: torch.Tensor, order: torch.Tensor,
+                          batch_size: int = DEFAULT_BATCH, flags: int = FLAG_VALIDATE, arena_entries: int = 0,
+                          query_lanes: int = 0, stream=None) -> Index:
+    """Labels of the undirected graph with positive integer edge weights
+    (weights uint8 [nnz], one per CSR entry, equal on both arcs of an edge);
+    the index's query gives weighted distances."""
+    row_ptr = _dev(row_ptr, torch.int64, "row_ptr")
+    col = _dev(col, torch.int32, "col")
+    weights = _dev(weights, torch.uint8, "weights")
+    order = _dev(order, torch.int32, "order")
+    n = order.numel()
+    if row_ptr.numel() != n + 1:
+        raise PllError(PLL_EINVAL, "row_ptr must have n+1 entries")
+    if weights.numel() != col.numel():
+        raise PllError(PLL_EINVAL, "one weight per CSR entry")
+    h = ctypes.c_void_p()
+    o = _opts(batch_size, flags, arena_entries, query_lanes)
+    rc = load_library().pll_build_labels_weighted(n, col.numel(), row_ptr.data_ptr(), col.data_ptr(),
+                                                  weights.data_ptr(), order.data_ptr(), ctypes.byref(o),
+                                                  _stream_handle(stream), ctypes.byref(h))
+    if rc:
+        raise PllError(rc, "pll_build_labels_weighted")
     return Index(h.value, order.device)
 
 

@@ -99,6 +99,17 @@ int pll_export_labels(const pll_index* idx, uint64_t* d_offsets, uint32_t* d_hub
     return pll_export_labels_side(idx, PLL_LABELS_IN, d_offsets, d_hubs, d_dists, stream);
 }
 
+int pll_build_labels_weighted(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
+                              const uint8_t* d_w, const uint32_t* d_order, const pll_build_opts* opts,
+                              hipStream_t stream, pll_index** out) {
+    try {
+        return pll_build_weighted(n, nnz, d_row_ptr, d_col, d_w, d_order, opts, stream, out);
+    } catch (...) {
+        if (out) *out = nullptr;
+        return PLL_ENOMEM;
+    }
+}
+
 int pll_build_labels_directed(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
                               const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream,
                               pll_index** out) {

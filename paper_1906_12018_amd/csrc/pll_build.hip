@@ -172,7 +172,7 @@ __global__ void k_check_order_counts(uint32_t n, const uint32_t* cnt, DevCounter
 // directions.  Runs only after the row pointers and column ids passed the
 // bounds checks.
 __global__ void __launch_bounds__(kBlock) k_check_csr(uint32_t n, const uint64_t* row_ptr, const uint32_t* col,
-                                                      uint32_t symmetric, DevCounters* ctr) {
+                                                      uint32_t symmetric, const uint8_t* w, DevCounters* ctr) {
     const uint32_t lane = lane_id();
     for (uint32_t v = global_wave(); v < n; v += num_waves()) {
         const uint64_t beg = row_ptr[v], end = row_ptr[v + 1];
@@ -188,6 +188,7 @@ __global__ void __launch_bounds__(kBlock) k_check_csr(uint32_t n, const uint64_t
                 if (col[mid] < v) lo = mid + 1; else hi = mid;
             }
             if (lo >= row_ptr[c + 1] || col[lo] != v) bad = true;
+            else if (w && w[lo] != w[e]) bad = true;  // both arcs of an edge carry one weight
         }
         if (ballot64(bad) && lane == 0) atomicOr(&ctr->error, PLL_ERR_CSR);
     }
@@ -344,10 +345,61 @@ __global__ void __launch_bounds__(kBlock) k_batch_end(BuildArgs A, uint32_t ib, 
     __shared__ uint8_t s_dist[kWavesPerBlock][PLL_BMAX];
     const uint32_t wv = threadIdx.x >> 6;
     PhaseStats st;
-    pll::phase_batch_end<WM>(A, grid_exec(A), ib, bs, recheck != 0, s_pres[wv], s_dist[wv], st);
+    pll::phase_batch_end<WM>(A, grid_exec(A), ib, bs, recheck != 0, s_pres[wv], s_dist[wv], nullptr, st);
     const unsigned long long v[3] = {st.removed, st.read, st.table};
     const int which[3] = {PLL_ST_RECHECK, PLL_ST_READ, PLL_ST_TABLE};
     block_add_stats<3>(A.ctr, v, which);
+}
+
+// ---- weighted batch kernels (Section 5.1) ----
+
+__global__ void __launch_bounds__(kBlock) k_push_w(BuildArgs A, uint32_t ib, uint32_t p, uint32_t nact,
+                                                   uint32_t rstamp, uint32_t bstamp) {
+    PhaseStats st;
+    pll::phase_push_w(A, grid_exec(A), ib, p, nact, rstamp, bstamp, st);
+    const unsigned long long v[1] = {st.edges};
+    const int which[1] = {PLL_ST_EDGES};
+    block_add_stats<1>(A.ctr, v, which);
+}
+
+template <int WM>
+__global__ void __launch_bounds__(kBlock) k_check_w(BuildArgs A, uint32_t ib, uint32_t bs, uint32_t p) {
+    __shared__ uint4 s_thr[kWavesPerBlock][4 * PLL_WMAX];
+    PhaseStats st;
+    pll::phase_check_w<WM>(A, grid_exec(A), ib, bs, p, s_thr[threadIdx.x >> 6], st);
+    const unsigned long long v[6] = {st.cand, st.acc, st.read, st.table, st.cost_pos, st.cost_neg};
+    const int which[6] = {PLL_ST_CAND, PLL_ST_ACC, PLL_ST_READ, PLL_ST_TABLE, PLL_ST_COST_POS, PLL_ST_COST_NEG};
+    block_add_stats<6>(A.ctr, v, which);
+}
+
+template <int WM>
+__global__ void __launch_bounds__(kBlock) k_batch_end_w(BuildArgs A, uint32_t ib, uint32_t bs) {
+    __shared__ uint64_t s_pres[kWavesPerBlock][PLL_WMAX];
+    __shared__ uint8_t s_dist[kWavesPerBlock][PLL_BMAX];
+    __shared__ uint32_t s_pos[kWavesPerBlock][PLL_BMAX];
+    const uint32_t wv = threadIdx.x >> 6;
+    PhaseStats st;
+    pll::phase_batch_end<WM, true>(A, grid_exec(A), ib, bs, true, s_pres[wv], s_dist[wv], s_pos[wv], st);
+    const unsigned long long v[3] = {st.removed, st.read, st.table};
+    const int which[3] = {PLL_ST_RECHECK, PLL_ST_READ, PLL_ST_TABLE};
+    block_add_stats<3>(A.ctr, v, which);
+}
+
+// Weights follow their CSR entries into rank space.
+__global__ void __launch_bounds__(kBlock) k_relabel_weights(uint32_t n, const uint32_t* order, const uint64_t* row_ptr,
+                                                            const uint8_t* w, const uint64_t* rrow, uint8_t* rw) {
+    const uint32_t lane = lane_id();
+    for (uint32_t k = global_wave(); k < n; k += num_waves()) {
+        const uint32_t v = order[k];
+        const uint64_t src = row_ptr[v], dst = rrow[k];
+        const uint32_t deg = (uint32_t)(row_ptr[v + 1] - src);
+        for (uint32_t i = lane; i < deg; i += 64) rw[dst + i] = w[src + i];
+    }
+}
+
+__global__ void k_check_weights(uint64_t nnz, const uint8_t* w, DevCounters* ctr) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < nnz; e += (uint64_t)gridDim.x * blockDim.x)
+        if (w[e] == 0) atomicOr(&ctr->error, PLL_ERR_BOUNDS);
 }
 
 __global__ void __launch_bounds__(kBlock) k_clear_table(BuildArgs A, uint32_t ib, uint32_t bs) {
@@ -566,6 +618,26 @@ void dispatch_batch_end(uint32_t blocks, hipStream_t s, const BuildArgs& A, uint
     }
 }
 
+void dispatch_check_w(uint32_t blocks, hipStream_t s, const BuildArgs& A, uint32_t ib, uint32_t bs, uint32_t p) {
+    switch (words_class(A.W)) {
+        case 1: k_check_w<1><<<blocks, kBlock, 0, s>>>(A, ib, bs, p); break;
+        case 2: k_check_w<2><<<blocks, kBlock, 0, s>>>(A, ib, bs, p); break;
+        case 4: k_check_w<4><<<blocks, kBlock, 0, s>>>(A, ib, bs, p); break;
+        case 8: k_check_w<8><<<blocks, kBlock, 0, s>>>(A, ib, bs, p); break;
+        default: k_check_w<16><<<blocks, kBlock, 0, s>>>(A, ib, bs, p); break;
+    }
+}
+
+void dispatch_batch_end_w(uint32_t blocks, hipStream_t s, const BuildArgs& A, uint32_t ib, uint32_t bs) {
+    switch (words_class(A.W)) {
+        case 1: k_batch_end_w<1><<<blocks, kBlock, 0, s>>>(A, ib, bs); break;
+        case 2: k_batch_end_w<2><<<blocks, kBlock, 0, s>>>(A, ib, bs); break;
+        case 4: k_batch_end_w<4><<<blocks, kBlock, 0, s>>>(A, ib, bs); break;
+        case 8: k_batch_end_w<8><<<blocks, kBlock, 0, s>>>(A, ib, bs); break;
+        default: k_batch_end_w<16><<<blocks, kBlock, 0, s>>>(A, ib, bs); break;
+    }
+}
+
 __global__ void k_reset_tops(DevCounters* ctr) {
     if (threadIdx.x < PLL_SHARDS) ctr->sh[threadIdx.x].arena_top = 0;
 }
@@ -641,11 +713,12 @@ struct RankCsr {
     uint64_t* scan_scratch = nullptr;
     uint64_t* rrow = nullptr;
     uint32_t* rcol = nullptr;
+    uint8_t* rw = nullptr;  // weighted graphs only
 };
 
 int prepare_rank_csr(DevAllocs& M, DevCounters* ctr, DevCounters* h, uint32_t n, uint64_t nnz,
                      const uint64_t* row_ptr, const uint32_t* col, const uint32_t* order, uint32_t flags,
-                     bool symmetric, hipStream_t s, RankCsr* R) {
+                     bool symmetric, hipStream_t s, RankCsr* R, const uint8_t* w = nullptr) {
     R->rank = M.get<uint32_t>(n);
     R->tmp32 = M.get<uint32_t>((size_t)n + 1);
     R->scan_scratch = M.get<uint64_t>((n + 1) / kScanTile + 2);
@@ -662,11 +735,12 @@ int prepare_rank_csr(DevAllocs& M, DevCounters* ctr, DevCounters* h, uint32_t n,
     if (rc) return rc;
     if (h->error) return PLL_EINVAL;
     if (nnz) k_check_cols<<<blocks_for_threads(nnz), kBlock, 0, s>>>(n, nnz, col, ctr);
+    if (nnz && w) k_check_weights<<<blocks_for_threads(nnz), kBlock, 0, s>>>(nnz, w, ctr);
     rc = read_counters(ctr, h, s);
     if (rc) return rc;
     if (h->error) return PLL_EINVAL;
     if (flags & PLL_FLAG_VALIDATE) {
-        k_check_csr<<<blocks_for_waves(n), kBlock, 0, s>>>(n, row_ptr, col, symmetric ? 1u : 0u, ctr);
+        k_check_csr<<<blocks_for_waves(n), kBlock, 0, s>>>(n, row_ptr, col, symmetric ? 1u : 0u, w, ctr);
         rc = read_counters(ctr, h, s);
         if (rc) return rc;
         if (h->error) return PLL_EINVAL;
@@ -676,6 +750,11 @@ int prepare_rank_csr(DevAllocs& M, DevCounters* ctr, DevCounters* h, uint32_t n,
     k_rank_degrees<<<blocks_for_threads(n), kBlock, 0, s>>>(n, order, row_ptr, tmp32);
     TRY_HIP(scan_u32_to_u64(tmp32, n, R->rrow, R->scan_scratch, s));
     k_relabel_cols<<<blocks_for_waves(n), kBlock, 0, s>>>(n, order, row_ptr, col, R->rank, R->rrow, R->rcol);
+    if (w) {
+        R->rw = M.get<uint8_t>(nnz ? nnz : 1);
+        if (M.err != hipSuccess) return status_of(M.err);
+        k_relabel_weights<<<blocks_for_waves(n), kBlock, 0, s>>>(n, order, row_ptr, w, R->rrow, R->rw);
+    }
     TRY_HIP(hipGetLastError());
     return PLL_OK;
 }
@@ -938,6 +1017,154 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     return PLL_OK;
 }
 
+// Weighted graphs (Section 5.1).  The rounds of a batch become
+// Bellman-Ford iterations restricted to vertices ranked below the roots:
+// a vertex that accepted entries in round j-1 pushes each of them along its
+// edges with distance d + w_e; a candidate passes the D filter only if it
+// lowers the best distance that reached the vertex in this batch, and the
+// pruning check compares each candidate with its own distance.  A batch
+// ends when a round accepts nothing.  Entries accepted on the way can be
+// non-canonical (a shorter path through a higher-ranked hub may arrive in a
+// later round); the batch end keeps each hub's last (shortest) entry and
+// rechecks every entry of the batch against the batch's tables, which
+// leaves exactly the canonical labels.  Distances stay uint8: a candidate
+// path of 255 or more fails the build with PLL_EDIST.
+int build_attempt_weighted(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint32_t* col, const uint8_t* w,
+                           const uint32_t* order, uint32_t b, uint32_t flags, uint64_t arena_hint, bool arena_fixed,
+                           hipStream_t s, pll_index* idx, uint64_t* used_arena) {
+    DevAllocs M;
+    M.s = s;
+    HostCounters HC;
+    PhaseProfiler P;
+    P.on = (flags & PLL_FLAG_PROFILE) != 0;
+    P.s = s;
+    TRY_HIP(pll_pinned_alloc((void**)&HC.p, sizeof(DevCounters)));
+    DevCounters* h = HC.p;
+    const uint32_t W = (b + 63) / 64;
+
+    DevCounters* ctr = M.get<DevCounters>(1);
+    if (M.err != hipSuccess) return status_of(M.err);
+    TRY_HIP(hipMemsetAsync(ctr, 0, sizeof(DevCounters), s));
+    hipEvent_t e_prep = P.mark();
+    RankCsr RC;
+    int rc = prepare_rank_csr(M, ctr, h, n, nnz, row_ptr, col, order, flags, true, s, &RC, w);
+    if (rc) return rc;
+    BuildArgs A{};
+    uint64_t* spare_off = nullptr;
+    rc = init_state(M, A, n, nnz, W, RC.rrow, RC.rcol, ctr, s, &spare_off);
+    if (rc) return rc;
+    A.rw = RC.rw;
+    A.D = M.get<uint8_t>((size_t)n * A.bstride);
+    for (int q = 0; q < 2; ++q) A.act_rng[q] = M.get<uint2>(n);
+    if (M.err != hipSuccess) return status_of(M.err);
+    TRY_HIP(hipMemsetAsync(A.D, 0xFF, (size_t)n * A.bstride, s));
+    const uint64_t region_cap = std::max<uint64_t>(4096, arena_hint / PLL_SHARDS);
+    rc = relayout_arena(M, A, spare_off, RC.tmp32, RC.scan_scratch, true, region_cap, arena_fixed ? arena_hint : 0, s);
+    if (rc) return rc;
+    P.span(PLL_PHASE_PREP, e_prep, P.mark(), (flags & PLL_FLAG_VALIDATE) ? 16 : 15);
+
+    uint32_t rstamp = 0, bstamp = 0;
+    uint64_t rounds = 0, batches = 0;
+    unsigned long long accepted_seen = 0;
+    for (uint32_t ib = 0; ib < n; ib += b) {
+        const uint32_t bs = std::min(b, n - ib);
+        ++bstamp;
+        ++batches;
+        hipEvent_t e0 = P.mark();
+        k_batch_prep<<<1, 64, 0, s>>>(ctr);
+        k_batch_init<<<blocks_for_waves(bs), kBlock, 0, s>>>(A, ib, bs, bstamp);
+        P.span(PLL_PHASE_INIT, e0, P.mark(), 2);
+        uint32_t p = 0, nact = bs;
+        uint64_t heavy_waves = 1024;
+        for (;;) {
+            ++rstamp;
+            ++rounds;
+            hipEvent_t r0 = P.mark();
+            k_push_w<<<blocks_for_waves(nact + heavy_waves), kBlock, 0, s>>>(A, ib, p, nact, rstamp, bstamp);
+            hipEvent_t r1 = P.mark();
+            dispatch_check_w(blocks_for_waves(std::min<uint64_t>(n, 16ull * nact + 2048)), s, A, ib, bs, p);
+            hipEvent_t r2 = P.mark();
+            P.span(PLL_PHASE_PUSH, r0, r1, 1);
+            P.span(PLL_PHASE_CHECK, r1, r2, 1);
+            TRY_HIP(hipGetLastError());
+            rc = read_counters(ctr, h, s);
+            if (rc) return rc;
+            P.resolve();
+            if (h->error) return device_error_status(h->error);
+            const unsigned long long acc_now = sum_stat(h, PLL_ST_ACC);
+            if (acc_now == accepted_seen) break;
+            accepted_seen = acc_now;
+            nact = sum_recv(h, p);
+            p ^= 1u;
+            heavy_waves = sum_hq(h, p);
+        }
+        hipEvent_t e1 = P.mark();
+        dispatch_batch_end_w(blocks_for_waves(sum_touched(h)), s, A, ib, bs);
+        k_clear_table<<<blocks_for_waves(bs), kBlock, 0, s>>>(A, ib, bs);
+        P.span(PLL_PHASE_END, e1, P.mark(), 2);
+        TRY_HIP(hipGetLastError());
+        if (!arena_fixed && ib + b < n && max_top(h) * 2 > A.region_cap) {
+            rc = relayout_arena(M, A, spare_off, RC.tmp32, RC.scan_scratch, false, A.region_cap * 2, 0, s);
+            if (rc) return rc;
+        }
+    }
+
+    rc = read_counters(ctr, h, s);
+    if (rc) return rc;
+    if (h->error) return device_error_status(h->error);
+    P.resolve();
+    hipEvent_t e_fin = P.mark();
+    uint64_t* d_off = nullptr;
+    uint32_t* d_ent = nullptr;
+    uint64_t total = 0;
+    rc = finalize_labels(M, A, RC.rank, RC.tmp32, RC.scan_scratch, s, &d_off, &d_ent, &total);
+    if (rc) return rc;
+    uint32_t* d_order = M.get_out<uint32_t>(n);
+    if (M.err != hipSuccess) return status_of(M.err);
+    TRY_HIP(hipMemcpyAsync(d_order, order, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+    TRY_HIP(hipGetLastError());
+    P.span(PLL_PHASE_FINAL, e_fin, P.mark(), 5);
+    rc = read_counters(ctr, h, s);
+    if (rc) return rc;
+    P.resolve();
+
+    idx->n = n;
+    idx->total = total;
+    idx->d_off = d_off;
+    idx->d_ent = d_ent;
+    idx->d_order = d_order;
+    M.forget(d_off);
+    M.forget(d_ent);
+    M.forget(d_order);
+    pll_index_info& I = idx->info;
+    I.n = n;
+    I.batch_size = b;
+    I.weighted = 1;
+    I.total_entries = total;
+    I.in_entries = total;
+    I.out_entries = total;
+    I.label_bytes = total * sizeof(uint32_t) + ((uint64_t)n + 1) * sizeof(uint64_t);
+    I.max_dist = h->max_dist;
+    I.max_label = h->max_label;
+    I.batches = batches;
+    I.rounds = rounds;
+    I.candidates = sum_stat(h, PLL_ST_CAND);
+    I.accepted = sum_stat(h, PLL_ST_ACC);
+    I.edges_scanned = sum_stat(h, PLL_ST_EDGES);
+    I.recheck_removed = sum_stat(h, PLL_ST_RECHECK);
+    I.gang = 1;
+    I.check_entries_read = sum_stat(h, PLL_ST_READ);
+    I.check_table_reads = sum_stat(h, PLL_ST_TABLE);
+    I.check_cost_pos = sum_stat(h, PLL_ST_COST_POS);
+    I.check_cost_neg = sum_stat(h, PLL_ST_COST_NEG);
+    for (int ph = 0; ph < PLL_NUM_PHASES; ++ph) {
+        I.phase_ms[ph] = P.ms[ph];
+        I.phase_launches[ph] = P.launches[ph];
+    }
+    *used_arena = A.region_base + PLL_SHARDS * A.region_cap;
+    return PLL_OK;
+}
+
 // Directed graphs (Section 5.1).  Two coupled builds run in lockstep:
 // the forward side grows L_in along out-arcs and the backward side grows
 // L_out along in-arcs, each with its own candidate bit-vectors, queues and
@@ -1146,8 +1373,9 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
 
 namespace {
 
-int build_index(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col, const uint32_t* d_order,
-                const pll_build_opts* opts, bool directed, hipStream_t stream, pll_index** out) {
+int build_index(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col, const uint8_t* d_w,
+                bool weighted, const uint32_t* d_order, const pll_build_opts* opts, bool directed, hipStream_t stream,
+                pll_index** out) {
     if (!out) return PLL_EINVAL;
     *out = nullptr;
     pll_build_opts o{};
@@ -1159,10 +1387,11 @@ int build_index(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint3
     if ((o.flags & PLL_FLAG_RELAXED) && !(o.flags & PLL_FLAG_RECHECK)) return PLL_EINVAL;
     if (o.flags & ~(PLL_FLAG_VALIDATE | PLL_FLAG_RECHECK | PLL_FLAG_RELAXED | PLL_FLAG_PROFILE | PLL_FLAG_PERSISTENT))
         return PLL_EINVAL;
-    if (directed && (o.flags & (PLL_FLAG_RELAXED | PLL_FLAG_PERSISTENT))) return PLL_EINVAL;
+    if ((directed || weighted) && (o.flags & (PLL_FLAG_RELAXED | PLL_FLAG_PERSISTENT))) return PLL_EINVAL;
     const uint32_t ql = o.query_lanes;
     if (!(ql == 0 || ql == 1 || ql == 4 || ql == 8 || ql == 16 || ql == 32 || ql == 64)) return PLL_EINVAL;
     if (n > 0 && (!d_row_ptr || !d_order || (nnz && !d_col))) return PLL_EINVAL;
+    if (weighted && (directed || (nnz && !d_w))) return PLL_EINVAL;
     if (nnz > 0xFFFFFFFFull * 2) return PLL_EINVAL;
 
     auto t0 = std::chrono::steady_clock::now();
@@ -1198,6 +1427,7 @@ int build_index(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint3
             M.forget(idx->d_order);
             M.forget(idx->d_off_out);
             M.forget(idx->d_ent_out);
+            idx->info.weighted = weighted ? 1u : 0u;
             idx->info.batch_size = b;
             idx->info.label_bytes = sizeof(uint64_t);
             idx->info.build_attempts = 1;
@@ -1207,10 +1437,15 @@ int build_index(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint3
         uint64_t cap = fixed ? o.arena_entries : std::max<uint64_t>(1ull << 20, 4 * nnz + 16ull * n);
         for (uint32_t attempt = 1;; ++attempt) {
             uint64_t used = 0;
-            rc = directed ? build_attempt_directed(n, nnz, d_row_ptr, d_col, d_order, b, o.flags, cap, fixed, stream,
-                                                   idx, &used)
-                          : build_attempt(n, nnz, d_row_ptr, d_col, d_order, b, o.flags, cap, fixed,
-                                          o.max_workgroups, stream, idx, &used);
+            if (directed)
+                rc = build_attempt_directed(n, nnz, d_row_ptr, d_col, d_order, b, o.flags, cap, fixed, stream, idx,
+                                            &used);
+            else if (weighted)
+                rc = build_attempt_weighted(n, nnz, d_row_ptr, d_col, d_w, d_order, b, o.flags, cap, fixed, stream,
+                                            idx, &used);
+            else
+                rc = build_attempt(n, nnz, d_row_ptr, d_col, d_order, b, o.flags, cap, fixed, o.max_workgroups,
+                                   stream, idx, &used);
             idx->info.build_attempts = attempt;
             idx->info.arena_entries = used;
             if (rc == PLL_ENOSPC && !fixed && attempt < 8) {
@@ -1234,10 +1469,15 @@ int build_index(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint3
 
 int pll_build_one(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
                   const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out) {
-    return build_index(n, nnz, d_row_ptr, d_col, d_order, opts, false, stream, out);
+    return build_index(n, nnz, d_row_ptr, d_col, nullptr, false, d_order, opts, false, stream, out);
 }
 
 int pll_build_directed(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
                        const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out) {
-    return build_index(n, nnz, d_row_ptr, d_col, d_order, opts, true, stream, out);
+    return build_index(n, nnz, d_row_ptr, d_col, nullptr, false, d_order, opts, true, stream, out);
+}
+
+int pll_build_weighted(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col, const uint8_t* d_w,
+                       const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out) {
+    return build_index(n, nnz, d_row_ptr, d_col, d_w, true, d_order, opts, false, stream, out);
 }

@@ -74,6 +74,7 @@ struct BuildArgs {
     uint32_t pad0;
     const uint64_t* rrow;   // rank-space CSR row pointers [n+1]
     const uint32_t* rcol;   // rank-space CSR columns [nnz]
+    const uint8_t* rw;      // weighted graphs: weight of each rank-space CSR entry (null otherwise)
     // growing labels: list of rank r is arena[loff[r] .. loff[r] + llen[r])
     uint64_t* loff;
     uint32_t* llen;
@@ -92,9 +93,14 @@ struct BuildArgs {
     // at v scans L_in(v) against the table of L_out(u_k), and vice versa)
     const uint8_t* Tchk;
     const uint32_t* rmchk;
+    // weighted graphs: D[v * bstride + k] = the smallest candidate distance
+    // of u_k that reached v in this batch (255: none); it plays the part of
+    // C(v), since a candidate may come back shorter in a later round
+    uint8_t* D;
     // frontier queues (shard s owns [s * seg, (s + 1) * seg) of each)
     uint32_t* act_v[2];      // active list by parity (compact)
     uint64_t* act_delta[2];  // W words per active slot: delta L of that vertex
+    uint2* act_rng[2];       // weighted graphs: (first, count) of the label entries the slot's vertex accepted
     uint2* hq[2];            // (active slot, chunk) items for rows longer than the heavy threshold
     uint64_t hq_seg;
     uint32_t* recv;          // receivers of the current round, segment per shard (seg = n)
@@ -213,6 +219,9 @@ int pll_query_launch(const pll_index* idx, uint64_t count, const uint32_t* d_u, 
                      uint32_t* d_out, hipStream_t stream);
 
 int pll_build_directed(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
+                       const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out);
+
+int pll_build_weighted(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col, const uint8_t* d_w,
                        const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out);
 
 int pll_build_multi(uint32_t count, const pll_graph_desc* graphs, const pll_build_opts* opts, hipStream_t stream,

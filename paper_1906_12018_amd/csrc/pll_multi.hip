@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(kMultiBlock) k_multi_build(const GraphJob* __r
                 p ^= 1u;
             }
             if (failed) break;
-            pll::phase_batch_end<WM>(A, X, ib, bs, recheck, s_pres[wv], s_dist[wv], st);
+            pll::phase_batch_end<WM>(A, X, ib, bs, recheck, s_pres[wv], s_dist[wv], nullptr, st);
             if (gang_sync(gc, G, k, ctr, spin_limit, &s_flag)) { failed = true; break; }
             pll::phase_clear_table(A, X, ib, bs);
             if (gang_sync(gc, G, k, ctr, spin_limit, &s_flag)) { failed = true; break; }

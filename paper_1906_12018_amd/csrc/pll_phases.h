@@ -226,6 +226,7 @@ __device__ inline void phase_batch_init(const BuildArgs& A, const Exec& X, uint3
             atomicOr(&A.rowmask[h], kw);
         }
         if (lane == 0) A.act_v[0][k] = u;
+        if (lane == 0 && A.act_rng[0]) A.act_rng[0][k] = make_uint2(len, 1u);  // the self entry
         if (lane < A.W) A.act_delta[0][(size_t)k * A.W + lane] = (lane == (k >> 6)) ? (1ull << (k & 63)) : 0ull;
         enqueue_heavy(A, X, 0, k, A.rrow[u + 1] - A.rrow[u]);
     }
@@ -384,11 +385,18 @@ __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t i
 // another hub at distance <= d (Section 5.1's recheck with the batch's
 // tables still in memory).  s_pres (W words) and s_dist (b bytes) are this
 // wave's LDS scratch.
-template <int WM>
+//
+// Weighted graphs (WEIGHTED): the recheck always runs (it is what makes the
+// labels canonical there), D(v) is reset instead of C(v), and a hub may
+// appear several times in the batch segment, each later entry shorter than
+// the one before; only the last one is kept (s_pos, b words of LDS, holds
+// the position of each hub's last entry).
+template <int WM, bool WEIGHTED = false>
 __device__ inline void phase_batch_end(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t bs, bool recheck,
-                                       uint64_t* s_pres, uint8_t* s_dist, PhaseStats& st) {
+                                       uint64_t* s_pres, uint8_t* s_dist, uint32_t* s_pos, PhaseStats& st) {
     const uint32_t lane = lane_id();
     const uint32_t W = A.W;
+    if (WEIGHTED) recheck = true;
     uint32_t pre;
     const uint32_t ntouched = shard_prefix(lane < X.nq ? X.qs[lane].touched : 0u, pre);
     for (uint32_t i = X.w; i < ntouched; i += X.nw) {
@@ -398,14 +406,25 @@ __device__ inline void phase_batch_end(const BuildArgs& A, const Exec& X, uint32
         const uint32_t ts = A.tstart[at];
         const uint32_t len = A.llen[v];
         const uint64_t off = A.loff[v];
-        if (lane < W) A.C[(size_t)v * W + lane] = 0;
+        if (WEIGHTED) {
+            uint4* drow = reinterpret_cast<uint4*>(A.D + (size_t)v * A.bstride);
+            for (uint32_t c = lane; c < 4 * W; c += 64) drow[c] = make_uint4(~0u, ~0u, ~0u, ~0u);
+        } else if (lane < W) {
+            A.C[(size_t)v * W + lane] = 0;
+        }
         const uint32_t tail = len - ts;
         if (tail < 2 && !(recheck && tail >= 1)) continue;
         if (lane < W) s_pres[lane] = 0;
+        if (WEIGHTED) {
+            for (uint32_t k = lane; k < bs; k += 64) s_pos[k] = 0;
+            wave_lds_sync();
+            for (uint32_t x = ts + lane; x < len; x += 64) atomicMax(&s_pos[(A.arena[off + x] >> 8) - ib], x - ts + 1);
+        }
         wave_lds_sync();
         for (uint32_t x = ts + lane; x < len; x += 64) {
             const uint32_t e = A.arena[off + x];
             const uint32_t k = (e >> 8) - ib;
+            if (WEIGHTED && s_pos[k] != x - ts + 1) continue;
             s_dist[k] = (uint8_t)(e & 255u);
             atomicOr((unsigned long long*)&s_pres[k >> 6], 1ull << (k & 63));
         }
@@ -462,6 +481,259 @@ __device__ inline void phase_batch_end(const BuildArgs& A, const Exec& X, uint32
             }
         }
         if (lane == 0 && total != tail) A.llen[v] = ts + total;
+        wave_lds_sync();
+    }
+}
+
+// ---- weighted graphs (Section 5.1) ----------------------------------------------------------------
+//
+// A candidate now carries its own distance d + w_e, and a round no longer
+// equals a distance: a candidate can come back shorter in a later round.
+// D(v) replaces C(v) as the filter (a candidate passes only if it lowers
+// D(v)[k]); the pruning check compares each candidate with its own
+// distance; a vertex that accepts pushes the entries it accepted (its
+// delta L) rather than a bit-vector.  Entries accepted on the way may be
+// non-canonical; the batch-end recheck removes them.
+
+// Per byte: min(x + d, 255) with dd = d * 0x01010101.  The low 7 bits of
+// each byte are added without carries leaving the byte; the carry out of
+// bit 7 marks the bytes that saturate.
+__device__ inline uint32_t add_sat4(uint32_t x, uint32_t dd) {
+    const uint32_t H = 0x80808080u;
+    const uint32_t low = (x & ~H) + (dd & ~H);
+    const uint32_t sum = low ^ ((x ^ dd) & H);
+    const uint32_t ovf = ((x & dd) | ((x | dd) & ~sum)) & H;
+    return sum | ((ovf >> 7) * 0xFFu);
+}
+
+// Bit i: min(p[i] + d, 255) <= thr[i], for 64 consecutive table bytes p and
+// thresholds thr (le4 compares bytes against any per-byte threshold).
+__device__ inline uint64_t sum_le_mask64(const uint8_t* p, uint32_t dd, const uint4* thr) {
+    const uint4* q = reinterpret_cast<const uint4*>(p);
+    uint64_t m = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint4 v = q[i];
+        const uint4 t = thr[i];
+        const uint32_t b = le4(add_sat4(v.x, dd), t.x) | (le4(add_sat4(v.y, dd), t.y) << 4) |
+                           (le4(add_sat4(v.z, dd), t.z) << 8) | (le4(add_sat4(v.w, dd), t.w) << 12);
+        m |= (uint64_t)b << (16 * i);
+    }
+    return m;
+}
+
+// prune_scan with a distance per candidate: s_thr (LDS, 64 * W bytes) holds
+// D(v); candidate u_k is pruned when some entry (h, d) of the list has
+// T[h][k] + d <= D(v)[k].  Lanes beyond the live candidates are masked off,
+// so bytes of 255 (no candidate) never count.
+template <int WM>
+__device__ inline uint64_t prune_scan_w(const BuildArgs& A, uint64_t off, uint32_t len, uint64_t cw,
+                                        const uint4* s_thr, PhaseStats& st) {
+    const uint32_t lane = lane_id();
+    uint64_t pw = 0;
+    uint64_t accm[WM];
+#pragma unroll
+    for (int w = 0; w < WM; ++w) accm[w] = 0;
+    uint32_t chunk = 0;
+    for (uint32_t base = 0; base < len; base += 64, ++chunk) {
+        const uint32_t idx = base + lane;
+        const bool ok = idx < len;
+        st.read += ok;
+        const uint32_t ent = ok ? A.arena[off + idx] : 0u;
+        const uint32_t h = ent >> 8;
+        const uint32_t rm = ok ? A.rmchk[h] : 0u;
+        const uint32_t dd = (ent & 255u) * 0x01010101u;
+        const uint8_t* row = A.Tchk + (size_t)h * A.bstride;
+        const uint64_t live_lane = cw & ~pw;
+#pragma unroll
+        for (int w = 0; w < WM; ++w) {
+            const uint64_t live = readlane64(live_lane, w);
+            if (live != 0 && ((rm >> w) & 1u)) {
+                accm[w] |= sum_le_mask64(row + 64u * w, dd, s_thr + 4 * w) & live;
+                ++st.table;
+            }
+        }
+        if ((chunk & 3u) == 3u || base + 64 >= len) {
+#pragma unroll
+            for (int w = 0; w < WM; ++w) {
+                if (readlane64(live_lane, w)) {
+                    const uint64_t red = wave_or64_u(accm[w]);
+                    if (lane == (uint32_t)w) pw |= red;
+                    accm[w] = 0;
+                }
+            }
+            if (!ballot64((cw & ~pw) != 0)) break;
+        }
+    }
+    return pw;
+}
+
+// D[p] = min(D[p], nd) on one byte (a compare-and-swap on its aligned word);
+// true when this call lowered it.
+__device__ inline bool byte_atomic_min(uint8_t* p, uint32_t nd) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    uint32_t* wp = reinterpret_cast<uint32_t*>(a & ~uintptr_t(3));
+    const uint32_t sh = (uint32_t)(a & 3u) * 8u;
+    uint32_t old = __hip_atomic_load(wp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        if (nd >= ((old >> sh) & 255u)) return false;
+        const uint32_t nw = (old & ~(255u << sh)) | (nd << sh);
+        const uint32_t prev = atomicCAS(wp, old, nw);
+        if (prev == old) return true;
+        old = prev;
+    }
+}
+
+// Push the cnt entries at arena[eoff ..] (what the active vertex accepted
+// last round) along its weighted CSR entries [beg, end).
+__device__ inline void push_edges_w(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t p, uint32_t rstamp,
+                                    uint32_t bstamp, uint64_t eoff, uint32_t cnt, uint64_t beg, uint64_t end) {
+    const uint32_t lane = lane_id();
+    for (uint64_t e0 = beg; e0 < end; e0 += 64) {
+        const uint64_t e = e0 + lane;
+        const bool in = e < end;
+        const uint32_t r = in ? A.rcol[e] : 0u;
+        const uint32_t wt = in ? A.rw[e] : 0u;
+        const bool cand = in && r > ib;
+        bool any = false, over = false;
+        if (ballot64(cand)) {
+            for (uint32_t t = 0; t < cnt; ++t) {
+                const uint32_t ent = A.arena[eoff + t];
+                const uint32_t k = (ent >> 8) - ib;
+                const uint32_t nd = (ent & 255u) + wt;
+                if (cand && r - ib > k) {  // only to vertices ranked below u_k
+                    uint8_t* pd = A.D + (size_t)r * A.bstride + k;
+                    if (nd >= PLL_INF8) {
+                        // too long for the labels; harmless when a shorter
+                        // candidate already reached r, else the build fails
+                        over = over || *pd == PLL_INF8;
+                    } else {
+                        if (nd < *pd && byte_atomic_min(pd, nd)) {
+                            atomicOr((unsigned long long*)&A.msgs[(size_t)r * A.W + (k >> 6)],
+                                     (unsigned long long)(1ull << (k & 63)));
+                            any = true;
+                        }
+                    }
+                }
+            }
+        }
+        if (ballot64(over) && lane == 0) atomicOr(&A.ctr->error, PLL_ERR_DIST);
+        bool enq = false;
+        if (any && A.recv_stamp[r] != rstamp) enq = atomicExch(&A.recv_stamp[r], rstamp) != rstamp;
+        bool first = false;
+        if (enq && A.touch_stamp[r] != bstamp) {
+            A.touch_stamp[r] = bstamp;
+            first = true;
+        }
+        if (ballot64(enq)) {
+            const uint32_t rp = shard_append(&X.qs[X.my].recv[p], enq, (uint64_t)X.my * X.seg);
+            if (enq) A.recv[rp] = r;
+            const uint32_t tp = shard_append(&X.qs[X.my].touched, first, (uint64_t)X.my * X.seg);
+            if (first) {
+                A.touched[tp] = r;
+                A.tstart[tp] = A.llen[r];
+            }
+        }
+    }
+}
+
+// Scatter phase for weighted graphs over active list p.
+__device__ inline void phase_push_w(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t p, uint32_t nact,
+                                    uint32_t rstamp, uint32_t bstamp, PhaseStats& st) {
+    const uint32_t lane = lane_id();
+    if (X.zero_i < X.nq) X.qs[X.zero_i].hq[p ^ 1u] = 0;
+    for (uint32_t i = X.w; i < nact; i += X.nw) {
+        const uint2 rg = A.act_rng[p][i];
+        if (rg.y == 0) continue;
+        const uint32_t a = A.act_v[p][i];
+        const uint64_t beg = A.rrow[a], end = A.rrow[a + 1];
+        if (end - beg > kHeavy) continue;
+        if (lane == 0) st.edges += end - beg;
+        push_edges_w(A, X, ib, p, rstamp, bstamp, A.loff[a] + rg.x, rg.y, beg, end);
+    }
+    uint32_t pre;
+    const uint32_t nh = shard_prefix(lane < X.nq ? X.qs[lane].hq[p] : 0u, pre);
+    for (uint32_t t = X.w; t < nh; t += X.nw) {
+        const uint32_t s = shard_of(X.nq, pre, t);
+        const uint2 item = A.hq[p][s * A.hq_seg + (t - readlane32(pre, s))];
+        const uint2 rg = A.act_rng[p][item.x];
+        const uint32_t a = A.act_v[p][item.x];
+        const uint64_t beg = A.rrow[a] + (uint64_t)item.y * kHeavy;
+        const uint64_t end = min(A.rrow[a + 1], beg + kHeavy);
+        if (lane == 0) st.edges += end - beg;
+        push_edges_w(A, X, ib, p, rstamp, bstamp, A.loff[a] + rg.x, rg.y, beg, end);
+    }
+}
+
+// Gather phase for weighted graphs: the candidates of receiver v are the
+// bits of msgs(v); candidate u_k has distance D(v)[k], staged in this
+// wave's LDS s_thr (64 * W bytes).  Survivors are appended with that
+// distance (a hub may already hold a longer entry from an earlier round;
+// the batch end keeps the last one); the slot records where they start.
+template <int WM>
+__device__ inline void phase_check_w(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t bs, uint32_t p,
+                                     uint4* s_thr, PhaseStats& st) {
+    const uint32_t lane = lane_id();
+    const uint32_t W = A.W;
+    const uint32_t q = p ^ 1u;
+    uint32_t pre;
+    const uint32_t nrecv = shard_prefix(lane < X.nq ? X.qs[lane].recv[p] : 0u, pre);
+    if (X.zero_i < X.nq) X.qs[X.zero_i].recv[q] = 0;
+    const uint8_t* thr_bytes = reinterpret_cast<const uint8_t*>(s_thr);
+    for (uint32_t i = X.w; i < nrecv; i += X.nw) {
+        const uint32_t s = shard_of(X.nq, pre, i);
+        const uint32_t v = A.recv[(size_t)s * X.seg + (i - readlane32(pre, s))];
+        uint64_t mine = 0;
+        if (lane < W) {
+            const size_t at = (size_t)v * W + lane;
+            mine = A.msgs[at];
+            A.msgs[at] = 0;
+        }
+        const uint4* drow = reinterpret_cast<const uint4*>(A.D + (size_t)v * A.bstride);
+        for (uint32_t c = lane; c < 4 * W; c += 64) s_thr[c] = drow[c];
+        wave_lds_sync();
+        const uint32_t len = A.llen[v];
+        uint64_t off = A.loff[v];
+        const uint64_t pw = prune_scan_w<WM>(A, off, len, mine, s_thr, st);
+        const uint64_t acc = lane < W ? (mine & ~pw) : 0ull;
+        const uint32_t cnt = (uint32_t)__builtin_popcountll(acc);
+        const uint32_t pos = wave_excl_scan32(cnt);
+        const uint32_t total = readlane32(pos + cnt, 63);
+        st.cand += __builtin_popcountll(mine);
+        st.cost_pos += (unsigned long long)len * (uint32_t)__builtin_popcountll(acc);
+        st.cost_neg += (unsigned long long)len * (uint32_t)__builtin_popcountll(mine & ~acc);
+        if (lane == 0) {
+            A.act_v[q][i] = v;
+            A.act_rng[q][i] = make_uint2(len, total);
+        }
+        if (total != 0) {
+            off = wave_reserve(A, X, v, off, len, total);
+            if (off != ~0ull) {
+                if (lane == 0) st.acc += total;
+                const bool in_batch = v - ib < bs;
+                const uint64_t lt = lanemask_lt();
+                uint64_t todo = ballot64(acc != 0);
+                while (todo) {
+                    const uint32_t w = (uint32_t)__builtin_ctzll(todo);
+                    todo &= todo - 1;
+                    const uint64_t aw = readlane64(acc, w);
+                    const uint32_t pwos = readlane32(pos, w);
+                    if ((aw >> lane) & 1ull) {
+                        const uint32_t k = w * 64u + lane;
+                        const uint32_t dk = thr_bytes[k];
+                        A.arena[off + len + pwos + __builtin_popcountll(aw & lt)] = pll_pack(ib + k, dk);
+                        if (in_batch) {
+                            A.T[(size_t)(ib + k) * A.bstride + (v - ib)] = (uint8_t)dk;
+                            atomicOr(&A.rowmask[ib + k], 1u << ((v - ib) >> 6));
+                        }
+                    }
+                }
+                if (lane == 0) A.llen[v] = len + total;
+                enqueue_heavy(A, X, q, i, A.rrow[v + 1] - A.rrow[v]);
+            } else if (lane == 0) {
+                A.act_rng[q][i] = make_uint2(len, 0u);
+            }
+        }
         wave_lds_sync();
     }
 }

@@ -229,7 +229,7 @@ __global__ void __launch_bounds__(kRoundBlock) k_batches(BuildArgs A, GridCtl* g
             p ^= 1u;
         }
         if (failed) break;
-        pll::phase_batch_end<WM>(A, X, ib, bs, recheck, s_pres[wv], s_dist[wv], st);
+        pll::phase_batch_end<WM>(A, X, ib, bs, recheck, s_pres[wv], s_dist[wv], nullptr, st);
         if (grid_sync(gc, k, ctr, timeout_ticks, 0u, &s_flag)) break;
         pll::phase_clear_table(A, X, ib, bs);
         // hand back to the host for compaction once a bump region is half used

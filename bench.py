@@ -9,8 +9,9 @@ device-resident CSR, followed by one batched query of 10^6 uniform pairs
 events; --steps profiled builds follow, and their HIP events give the
 kernel times of the roofline entry.  Other modes: --mode query (queries
 alone), --mode batched (the 256-graph one-launch build), --mode serve (the
-serving loop), --mode directed (directed R-MAT build and query), each
-printing its own JSON line.
+serving loop), --mode directed (directed R-MAT build and query), --mode
+weighted (R-MAT with 1..7 weights, build and query), each printing its own
+JSON line.
 """
 from __future__ import annotations
 
@@ -349,6 +350,85 @@ def directed_mode(args):
     print(json.dumps(res), flush=True)
 
 
+def weighted_mode(args):
+    """Weighted graphs (Section 5.1): the R-MAT graph of scale --weighted-scale
+    (edge factor 16, seed 1) with weights uniform in 1..7 (stream 5, the
+    paper's weighted recipe), degree order, b = --batch-size.  A step is one
+    weighted build followed by one batched query of 10^6 uniform pairs (seed
+    2).  The CPU baseline is the weighted oracle (PLL with Dijkstra)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1906_12018_amd as pll
+    dev = torch.device("cuda:0")
+    g = synth.with_weights(synth.rmat_graph(args.weighted_scale, 16, seed=1))
+    order = synth.degree_order(g)
+    rp, cl = pll.graph_to_device(g, dev)
+    wt = torch.from_numpy(g.w).to(dev)
+    od = torch.from_numpy(order.view(np.int32)).to(dev)
+    pairs = 1_000_000
+    u, v = synth.query_pairs(g.n, pairs, seed=2)
+    du = torch.from_numpy(u.view(np.int32)).to(dev)
+    dv = torch.from_numpy(v.view(np.int32)).to(dev)
+    out = torch.empty_like(du)
+    torch.cuda.synchronize()
+    build_ms, query_ms, ref = [], [], None
+    for it in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        idx = pll.build_labels_weighted(rp, cl, wt, od, batch_size=args.batch_size, flags=0)
+        t1 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        idx.query(du, dv, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        info = idx.info()
+        if ref is None:
+            ref = (info["total_entries"], out.clone())
+        else:
+            assert info["total_entries"] == ref[0] and torch.equal(out, ref[1]), "steps disagree"
+        if it >= args.warmup:
+            build_ms.append((t1 - t0) * 1e3)
+            query_ms.append(e0.elapsed_time(e1))
+        idx.free()
+    pidx = pll.build_labels_weighted(rp, cl, wt, od, batch_size=args.batch_size, flags=pll.FLAG_PROFILE)
+    info = pidx.info()
+    pidx.free()
+    total = info["total_entries"]
+    check_ms = info["phase_ms"]["check"]
+    check_bytes = 4 * info["check_entries_read"] + 64 * info["check_table_reads"] + 4 * info["accepted"]
+    res = {"mode": "weighted", "workload": f"rmat{args.weighted_scale} with weights uniform 1..7 build + "
+                                          f"{pairs} query pairs",
+           "n": g.n, "undirected_edges": g.num_edges, "batch_size": args.batch_size, "steps": args.steps,
+           "build_ms_p50": float(np.median(build_ms)),
+           "entries_per_s": total * len(build_ms) / (sum(build_ms) / 1e3), "label_entries": total,
+           "max_dist": info["max_dist"], "queries_per_s": pairs / (float(np.median(query_ms)) / 1e3),
+           "query_batch_ms_p50": float(np.median(query_ms)), "rounds": info["rounds"], "batches": info["batches"],
+           "candidates": info["candidates"], "accepted": info["accepted"],
+           "recheck_removed": info["recheck_removed"],
+           "build_phase_ms": {k: round(x, 3) for k, x in info["phase_ms"].items()},
+           "roofline": {"kernel": "k_check_w", "bound": "hbm",
+                        "achieved": check_bytes / (check_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": check_bytes / (check_ms / 1e3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "launches_per_step": info["phase_launches"]["check"], "bytes_per_step": check_bytes}}
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        lab = oracle.pll_labels_weighted(g, order)
+        dt = time.perf_counter() - t0
+        assert lab.total == total, "oracle and GPU label counts differ"
+        t0 = time.perf_counter()
+        want = oracle.query(lab, u, v)
+        q1 = time.perf_counter() - t0
+        assert np.array_equal(want, out.cpu().numpy().view(np.uint32)), "oracle and GPU distances differ"
+        res["cpu_baseline"] = {"value": total / dt, "unit": "label entries/s", "cores": 1, "kind": "oracle",
+                               "sample": f"full sequential PLL-with-Dijkstra build of the same graph, 1 run, "
+                                         f"{dt:.2f} s; queries: the oracle's merge-join over the same pairs",
+                               "seconds": dt, "queries_per_s_1core": pairs / q1}
+    print(json.dumps(res), flush=True)
+
+
 def serve_mode(args):
     """Serving workload: R-MAT scale-20 index resident; open-loop Poisson
     arrivals (stream 4) of query requests with sizes log-uniform in [1, 65536]
@@ -462,8 +542,9 @@ def main():
     ap.add_argument("--workload", default="rmat16", choices=sorted(WORKLOADS))
     ap.add_argument("--batch-size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="build", choices=["build", "query", "batched", "serve", "directed"])
+    ap.add_argument("--mode", default="build", choices=["build", "query", "batched", "serve", "directed", "weighted"])
     ap.add_argument("--directed-scale", type=int, default=16)
+    ap.add_argument("--weighted-scale", type=int, default=16)
     ap.add_argument("--tune-cache", default="", help="batched mode: autotuner cache file")
     ap.add_argument("--calibrate", action="store_true",
                     help="finish with a 256 MiB read + 256 MiB write elementwise kernel (counter scale)")
@@ -486,6 +567,9 @@ def main():
         return
     if args.mode == "directed":
         directed_mode(args)
+        return
+    if args.mode == "weighted":
+        weighted_mode(args)
         return
     if args.mode == "query":
         query_mode(args)

@@ -18,6 +18,8 @@ Functions (all host-side, written from the paper, arXiv 1906.12018):
 * :func:`pll_labels_weighted` -- PLL with Dijkstra for positive integer edge
   weights (Section 5.1; the weighted baseline of Section 6).  The query is
   :func:`query` unchanged.
+* :func:`pll_labels_bp`, :func:`query_bp` -- bit-parallel labels (Section 5.2,
+  adopted from the original PLL) followed by PLL over the remaining vertices.
 * :func:`bfs`              -- textbook BFS distances.
 
 Label sets are returned as :class:`Labels` (CSR by vertex id, hubs as ranks in
@@ -64,6 +66,17 @@ class _CLabels(ctypes.Structure):
     ]
 
 
+class _CBp(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_uint32),
+        ("root", ctypes.POINTER(ctypes.c_uint32)),
+        ("nbr", ctypes.POINTER(ctypes.c_uint32)),
+        ("dist", ctypes.POINTER(ctypes.c_uint8)),
+        ("sm1", ctypes.POINTER(ctypes.c_uint64)),
+        ("s0", ctypes.POINTER(ctypes.c_uint64)),
+    ]
+
+
 def _load():
     global _lib
     if _lib is None:
@@ -91,6 +104,13 @@ def _load():
         lib.oracle_query_directed.restype = None
         lib.oracle_pll_weighted.argtypes = [ctypes.c_uint32, P, P, P, P, ctypes.POINTER(_CLabels)]
         lib.oracle_pll_weighted.restype = ctypes.c_int
+        lib.oracle_pll_bp.argtypes = [ctypes.c_uint32, P, P, P, ctypes.c_uint32, ctypes.POINTER(_CLabels),
+                                      ctypes.POINTER(_CBp)]
+        lib.oracle_pll_bp.restype = ctypes.c_int
+        lib.oracle_bp_free.argtypes = [ctypes.POINTER(_CBp)]
+        lib.oracle_bp_free.restype = None
+        lib.oracle_query_bp.argtypes = [P, P, P, ctypes.POINTER(_CBp), ctypes.c_uint64, P, P, P]
+        lib.oracle_query_bp.restype = None
         _lib = lib
     return _lib
 
@@ -247,3 +267,63 @@ def pll_labels_weighted(g, order) -> Labels:
     _check(_load().oracle_pll_weighted(g.n, row_ptr.ctypes.data, col.ctypes.data, w.ctypes.data,
                                        order.ctypes.data, ctypes.byref(c)), "oracle_pll_weighted")
     return _take(c)
+
+
+@dataclass
+class BPLabels:
+    """Bit-parallel labels: BP root i is vertex ``root[i]`` with neighbour set
+    ``nbr[i]`` (vertex ids, bit j = nbr[i][j]; DIST_INF past the set);
+    ``dist[v, i]`` = d(root_i, v) (255: unreachable), ``sm1[v, i]`` and
+    ``s0[v, i]`` the S^-1 and S^0 bit sets."""
+    root: np.ndarray  # uint32[t]
+    nbr: np.ndarray   # uint32[t, 64]
+    dist: np.ndarray  # uint8[n, t]
+    sm1: np.ndarray   # uint64[n, t]
+    s0: np.ndarray    # uint64[n, t]
+
+    @property
+    def t(self) -> int:
+        return int(self.root.shape[0])
+
+
+def pll_labels_bp(g, order, t: int):
+    """Up to t BP roots (each with up to 64 neighbours), then PLL over the
+    vertices they did not use, pruning by the BP bound first.  Returns
+    (Labels, BPLabels); the labels' counter "bp_pruned" counts the checks the
+    BP bound decided."""
+    row_ptr, col, order = _graph_args(g, order)
+    c, b = _CLabels(), _CBp()
+    lib = _load()
+    _check(lib.oracle_pll_bp(g.n, row_ptr.ctypes.data, col.ctypes.data, order.ctypes.data, t, ctypes.byref(c),
+                             ctypes.byref(b)), "oracle_pll_bp")
+    tt, n = b.t, g.n
+    bp = BPLabels(
+        root=np.ctypeslib.as_array(b.root, shape=(max(tt, 1),))[:tt].copy(),
+        nbr=np.ctypeslib.as_array(b.nbr, shape=(max(tt, 1) * 64,))[:tt * 64].copy().reshape(tt, 64),
+        dist=np.ctypeslib.as_array(b.dist, shape=(n * tt + 1,))[:n * tt].copy().reshape(n, tt),
+        sm1=np.ctypeslib.as_array(b.sm1, shape=(n * tt + 1,))[:n * tt].copy().reshape(n, tt),
+        s0=np.ctypeslib.as_array(b.s0, shape=(n * tt + 1,))[:n * tt].copy().reshape(n, tt))
+    lib.oracle_bp_free(ctypes.byref(b))
+    lab = _take(c)
+    lab.counters["bp_pruned"] = lab.counters.pop("cost_pos")
+    lab.counters.pop("cost_neg", None)
+    return lab, bp
+
+
+def query_bp(labels: Labels, bp: BPLabels, u, v):
+    """min(BP bound, 2-hop merge) for each pair (uint32; DIST_INF when none)."""
+    u = np.ascontiguousarray(u, dtype=np.uint32)
+    v = np.ascontiguousarray(v, dtype=np.uint32)
+    out = np.empty(u.shape[0], dtype=np.uint32)
+    off = np.ascontiguousarray(labels.offsets, dtype=np.uint64)
+    hub = np.ascontiguousarray(labels.hub_rank, dtype=np.uint32)
+    dist = np.ascontiguousarray(labels.dist, dtype=np.uint8)
+    keep = [np.ascontiguousarray(bp.root, dtype=np.uint32), np.ascontiguousarray(bp.nbr, dtype=np.uint32),
+            np.ascontiguousarray(bp.dist, dtype=np.uint8), np.ascontiguousarray(bp.sm1, dtype=np.uint64),
+            np.ascontiguousarray(bp.s0, dtype=np.uint64)]
+    cb = _CBp(bp.t, *(a.ctypes.data_as(ctypes.POINTER(ct)) for a, ct in
+                      zip(keep, (ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint8, ctypes.c_uint64, ctypes.c_uint64))))
+    _load().oracle_query_bp(off.ctypes.data, hub.ctypes.data if hub.size else None,
+                            dist.ctypes.data if dist.size else None, ctypes.byref(cb), u.shape[0], u.ctypes.data,
+                            v.ctypes.data, out.ctypes.data)
+    return out

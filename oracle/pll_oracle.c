@@ -21,6 +21,11 @@
  *                     the directed variant of Section 5.1: L_in and L_out
  *                     labels from a forward and a backward pruned BFS per
  *                     root; the query merges L_out(s) with L_in(t).
+ *   oracle_pll_bp / oracle_query_bp
+ *                     bit-parallel labels (Section 5.2) for the first BP
+ *                     roots, then PLL over the other vertices pruning by
+ *                     the BP bound first; the query takes the smaller of
+ *                     the BP bound and the 2-hop merge.
  *   oracle_pll_weighted
  *                     PLL with Dijkstra for positive integer edge weights
  *                     (Section 5.1's weighted graphs); labels follow
@@ -855,4 +860,193 @@ done:
     if (L) vlists_free(L, n);
     free(T); free(tent); free(stamp); free(settled); free(rank); free(H.a);
     return rc;
+}
+
+/* ---- bit-parallel labels (Section 5.2, adopted from the original PLL) ----
+ * Before the pruned searches, t bit-parallel (BP) roots are chosen and every
+ * vertex v gets, per BP root r with neighbour set S_r (|S_r| <= 64):
+ *   d_r(v)      = d(r, v)                      (255: unreachable)
+ *   S^-1_r(v)   = { s in S_r : d(s, v) = d(r, v) - 1 }   (bit j: s_j)
+ *   S^0_r(v)    = { s in S_r : d(s, v) = d(r, v) }
+ * Selection: the BP root is the highest-ranked vertex not used yet; its S_r
+ * is its first (up to) 64 unused neighbours in ascending rank; all of them
+ * become used.  Here the three quantities are computed from their
+ * definitions, with one BFS from r and one from every s in S_r.
+ * The BP bound of a pair is min over BP roots of d_r(u) + d_r(v) minus 2 if
+ * S^-1_r(u) and S^-1_r(v) meet, else minus 1 if S^-1 of one meets S^0 of
+ * the other: the length of the best path through r or some s in S_r.
+ * PLL then runs over the unused vertices in rank order; a reached (v, delta)
+ * is pruned when the BP bound is <= delta or the labels cover it.  The pair
+ * query is the smaller of the BP bound and the 2-hop merge.
+ */
+typedef struct {
+    uint32_t t;          /* BP roots chosen (<= requested) */
+    uint32_t* root;      /* t, vertex ids */
+    uint32_t* nbr;       /* t * 64 vertex ids of S_r in bit order, DIST_INF past |S_r| */
+    uint8_t* dist;       /* n * t: dist[v * t + i] = d_{r_i}(v) */
+    uint64_t* sm1;       /* n * t: S^-1 */
+    uint64_t* s0;        /* n * t: S^0 */
+} oracle_bp;
+
+void oracle_bp_free(oracle_bp* B) {
+    if (!B) return;
+    free(B->root); free(B->nbr); free(B->dist); free(B->sm1); free(B->s0);
+    memset(B, 0, sizeof(*B));
+}
+
+static uint32_t bp_bound(const oracle_bp* B, uint32_t u, uint32_t v) {
+    uint32_t best = DIST_INF;
+    for (uint32_t i = 0; i < B->t; ++i) {
+        uint32_t du = B->dist[(size_t)u * B->t + i], dv = B->dist[(size_t)v * B->t + i];
+        if (du == INF8 || dv == INF8) continue;
+        uint32_t td = du + dv;
+        uint64_t mu = B->sm1[(size_t)u * B->t + i], mv = B->sm1[(size_t)v * B->t + i];
+        uint64_t zu = B->s0[(size_t)u * B->t + i], zv = B->s0[(size_t)v * B->t + i];
+        if (mu & mv) td -= 2;
+        else if ((mu & zv) | (zu & mv)) td -= 1;
+        if (td < best) best = td;
+    }
+    return best;
+}
+
+static int cmp_u32(const void* a, const void* b) {
+    uint32_t x = *(const uint32_t*)a, y = *(const uint32_t*)b;
+    return x < y ? -1 : (x > y);
+}
+
+int oracle_pll_bp(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* order, uint32_t t_req,
+                  oracle_labels* out, oracle_bp* B) {
+    memset(out, 0, sizeof(*out));
+    memset(B, 0, sizeof(*B));
+    if (t_req > 64) return ORACLE_EINVAL;
+    uint32_t* rank = make_rank(n, order);
+    if (!rank) return ORACLE_EINVAL;
+    int rc = ORACLE_OK;
+    uint8_t* used = (uint8_t*)calloc(n ? n : 1, 1);
+    uint32_t* dr = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint32_t* ds = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint32_t* nb = NULL;
+    B->root = (uint32_t*)malloc(sizeof(uint32_t) * (t_req ? t_req : 1));
+    B->nbr = (uint32_t*)malloc(sizeof(uint32_t) * 64 * (t_req ? t_req : 1));
+    B->dist = (uint8_t*)malloc((size_t)n * (t_req ? t_req : 1) + 1);
+    B->sm1 = (uint64_t*)calloc((size_t)n * (t_req ? t_req : 1) + 1, sizeof(uint64_t));
+    B->s0 = (uint64_t*)calloc((size_t)n * (t_req ? t_req : 1) + 1, sizeof(uint64_t));
+    vlist* L = NULL;
+    uint8_t* T = NULL;
+    uint32_t *visited = NULL, *qv = NULL, *qd = NULL;
+    if (!used || !dr || !ds || !B->root || !B->nbr || !B->dist || !B->sm1 || !B->s0) { rc = ORACLE_ENOMEM; goto done; }
+
+    /* selection, then the BP quantities of each root from their definitions */
+    uint32_t next = 0, t = 0;
+    for (; t < t_req; ++t) {
+        while (next < n && used[order[next]]) next++;
+        if (next == n) break;
+        uint32_t r = order[next];
+        used[r] = 1;
+        uint32_t deg = (uint32_t)(row_ptr[r + 1] - row_ptr[r]);
+        free(nb);
+        nb = (uint32_t*)malloc(sizeof(uint32_t) * (deg ? deg : 1));
+        if (!nb) { rc = ORACLE_ENOMEM; goto done; }
+        uint32_t m = 0;
+        for (uint64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e)
+            if (!used[col[e]]) nb[m++] = rank[col[e]];
+        qsort(nb, m, sizeof(uint32_t), cmp_u32);
+        if (m > 64) m = 64;
+        B->root[t] = r;
+        for (uint32_t j = 0; j < 64; ++j) B->nbr[t * 64 + j] = j < m ? order[nb[j]] : DIST_INF;
+        for (uint32_t j = 0; j < m; ++j) used[order[nb[j]]] = 1;
+        oracle_bfs(n, row_ptr, col, r, dr);
+        for (uint32_t v = 0; v < n; ++v) {
+            if (dr[v] != DIST_INF && dr[v] >= INF8) { rc = ORACLE_EDIST; goto done; }
+            B->dist[(size_t)v * t_req + t] = dr[v] == DIST_INF ? (uint8_t)INF8 : (uint8_t)dr[v];
+        }
+        for (uint32_t j = 0; j < m; ++j) {
+            oracle_bfs(n, row_ptr, col, order[nb[j]], ds);
+            for (uint32_t v = 0; v < n; ++v) {
+                if (dr[v] == DIST_INF) continue;
+                if (ds[v] + 1 == dr[v]) B->sm1[(size_t)v * t_req + t] |= 1ull << j;
+                else if (ds[v] == dr[v]) B->s0[(size_t)v * t_req + t] |= 1ull << j;
+            }
+        }
+    }
+    /* compact the per-vertex stride from t_req to t */
+    if (t < t_req) {
+        for (uint32_t v = 0; v < n; ++v)
+            for (uint32_t i = 0; i < t; ++i) {
+                B->dist[(size_t)v * t + i] = B->dist[(size_t)v * t_req + i];
+                B->sm1[(size_t)v * t + i] = B->sm1[(size_t)v * t_req + i];
+                B->s0[(size_t)v * t + i] = B->s0[(size_t)v * t_req + i];
+            }
+    }
+    B->t = t;
+
+    /* PLL over the unused vertices, pruning by the BP bound first */
+    L = (vlist*)calloc(n ? n : 1, sizeof(vlist));
+    T = (uint8_t*)malloc(n ? n : 1);
+    visited = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    qv = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    qd = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    if (!L || !T || !visited || !qv || !qd) { rc = ORACLE_ENOMEM; goto done; }
+    memset(T, INF8, n);
+    for (uint32_t i = 0; i < n; ++i) visited[i] = DIST_INF;
+    uint64_t checks = 0, added = 0, edges = 0, scanned = 0, bp_pruned = 0;
+    for (uint32_t k = 0; k < n && !rc; ++k) {
+        uint32_t u = order[k];
+        if (used[u]) continue;
+        vlist* Lu = &L[u];
+        for (uint32_t i = 0; i < Lu->len; ++i) T[Lu->hub[i]] = Lu->d[i];
+        uint32_t head = 0, tail = 0;
+        qv[tail] = u; qd[tail] = 0; tail++;
+        visited[u] = k;
+        while (head < tail) {
+            uint32_t v = qv[head], delta = qd[head];
+            head++;
+            checks++;
+            if (bp_bound(B, u, v) <= delta) { bp_pruned++; continue; }
+            vlist* Lv = &L[v];
+            uint32_t mm = DIST_INF;
+            for (uint32_t i = 0; i < Lv->len; ++i) {
+                uint32_t th = T[Lv->hub[i]];
+                if (th != INF8 && th + Lv->d[i] < mm) mm = th + Lv->d[i];
+            }
+            scanned += Lv->len;
+            if (!(delta < mm)) continue;
+            if (delta >= INF8) { rc = ORACLE_EDIST; break; }
+            rc = vlist_push(Lv, k, delta);
+            if (rc) break;
+            added++;
+            for (uint64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                uint32_t w = col[e];
+                edges++;
+                if (visited[w] != k && rank[w] > k) {
+                    visited[w] = k;
+                    qv[tail] = w; qd[tail] = delta + 1; tail++;
+                }
+            }
+        }
+        for (uint32_t i = 0; i < Lu->len; ++i) T[Lu->hub[i]] = INF8;
+    }
+    if (!rc) {
+        rc = vlists_to_csr(L, n, 0, out);
+        out->counters[0] = checks;
+        out->counters[1] = added;
+        out->counters[2] = edges;
+        out->counters[5] = scanned;
+        out->counters[6] = bp_pruned;  /* here: checks the BP bound pruned */
+    }
+done:
+    if (rc) { oracle_labels_free(out); oracle_bp_free(B); }
+    if (L) vlists_free(L, n);
+    free(T); free(visited); free(qv); free(qd); free(rank); free(used); free(dr); free(ds); free(nb);
+    return rc;
+}
+
+/* Pair query with BP labels: min of the BP bound and the 2-hop merge. */
+void oracle_query_bp(const uint64_t* offsets, const uint32_t* hub_rank, const uint8_t* dist, const oracle_bp* B,
+                     uint64_t count, const uint32_t* qu, const uint32_t* qv, uint32_t* out) {
+    oracle_query(offsets, hub_rank, dist, count, qu, qv, out, NULL);
+    for (uint64_t q = 0; q < count; ++q) {
+        uint32_t b = bp_bound(B, qu[q], qv[q]);
+        if (b < out[q]) out[q] = b;
+    }
 }

@@ -96,7 +96,9 @@ typedef struct {
     uint32_t max_gang;      /* batched build: most workgroups on one graph, 1..16 (0 = 16) */
     uint32_t max_workgroups; /* batched build: most workgroups in the persistent launch (0 = as many as fit
                                 on the device at once); a smaller launch leaves room for concurrent work */
-    uint32_t reserved[4];   /* must be zero */
+    uint32_t bp_roots;      /* bit-parallel roots, 0..64 (Section 5.2); 0 = none.  Single-graph undirected
+                               unweighted builds only (PLL_EINVAL elsewhere, and with PLL_FLAG_PERSISTENT) */
+    uint32_t reserved[3];   /* must be zero */
 } pll_build_opts;
 
 typedef struct {
@@ -126,6 +128,9 @@ typedef struct {
     uint32_t weighted;        /* 1 for an index of pll_build_labels_weighted */
     uint64_t in_entries;      /* directed: sum of |L_in(v)|; undirected: total_entries (one label serves both) */
     uint64_t out_entries;     /* directed: sum of |L_out(v)|; undirected: total_entries */
+    uint32_t bp_roots;        /* bit-parallel roots the build chose (<= pll_build_opts.bp_roots) */
+    uint32_t bp_vertices;     /* vertices they use (roots plus their neighbour sets) */
+    uint64_t bp_pruned;       /* candidates the bit-parallel bound pruned */
 } pll_index_info;
 
 /* One graph of a batched build (all pointers are device pointers). */
@@ -208,6 +213,33 @@ int pll_build_labels_directed(uint32_t n, uint64_t nnz, const uint64_t* d_row_pt
 int pll_build_labels_weighted(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
                               const uint8_t* d_w, const uint32_t* d_order, const pll_build_opts* opts,
                               hipStream_t stream, pll_index** out);
+
+/*
+ * Bit-parallel labels (Section 5.2, adopted from the original PLL).  With
+ * opts->bp_roots = t > 0, pll_build_labels first picks up to t BP roots: each
+ * is the highest-ranked vertex not used yet, with S_r = its first (up to) 64
+ * unused neighbours in ascending rank, which all become used.  Every vertex v
+ * gets, per BP root r: d_r(v) = d(r, v) (255: unreachable), S^-1_r(v) = the
+ * members s of S_r with d(s, v) = d_r(v) - 1 and S^0_r(v) = those with
+ * d(s, v) = d_r(v), as 64-bit sets (bit j = the j-th member).  The BP bound
+ * of a pair is the minimum over BP roots of d_r(u) + d_r(v), minus 2 when
+ * S^-1_r(u) and S^-1_r(v) meet, else minus 1 when S^-1 of one meets S^0 of
+ * the other.  The batches then run over the unused vertices only, and a
+ * candidate (u, d) at v is pruned first when its BP bound is <= d.  So the
+ * stored labels are: (u, d(u,v)) with u unused, no used vertex on any
+ * shortest u-v path, and u the highest-ranked vertex on every such path.
+ * pll_query returns the smaller of the BP bound and the 2-hop merge.
+ *
+ * pll_export_bp copies the BP part out (vertex ids):
+ *   d_roots     uint32[t]          BP root i
+ *   d_nbrs      uint32[t * 64]     member j of S_{r_i}; PLL_DIST_INF past |S|
+ *   d_dist      uint8[n * t]       d_dist[v * t + i] = d_{r_i}(v)
+ *   d_sm1, d_s0 uint64[n * t]      S^-1 and S^0 of (v, root i)
+ * t is pll_index_info.bp_roots; with t = 0 nothing is copied.  Asynchronous
+ * on `stream`.
+ */
+int pll_export_bp(const pll_index* idx, uint32_t* d_roots, uint32_t* d_nbrs, uint8_t* d_dist, uint64_t* d_sm1,
+                  uint64_t* d_s0, hipStream_t stream);
 
 /*
  * Exact distances for `count` pairs (Section 2.1, the 2-hop query).

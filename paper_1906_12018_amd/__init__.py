@@ -33,7 +33,7 @@ LABELS_IN, LABELS_OUT = 0, 1
 
 EXPORTED_SYMBOLS = (
     "pll_build_labels", "pll_build_labels_directed", "pll_build_labels_weighted", "pll_query", "pll_index_info_get", "pll_export_labels",
-    "pll_export_labels_side",
+    "pll_export_labels_side", "pll_export_bp",
     "pll_build_labels_batched", "pll_index_free", "pll_status_string",
     "pll_server_create", "pll_server_add_index", "pll_server_index", "pll_server_submit", "pll_server_poll",
     "pll_server_replay", "pll_server_destroy",
@@ -57,7 +57,8 @@ class BuildOpts(ctypes.Structure):
         ("gang_scale", ctypes.c_uint32),
         ("max_gang", ctypes.c_uint32),
         ("max_workgroups", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 4),
+        ("bp_roots", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 3),
     ]
 
 
@@ -89,6 +90,9 @@ class IndexInfo(ctypes.Structure):
         ("weighted", ctypes.c_uint32),
         ("in_entries", ctypes.c_uint64),
         ("out_entries", ctypes.c_uint64),
+        ("bp_roots", ctypes.c_uint32),
+        ("bp_vertices", ctypes.c_uint32),
+        ("bp_pruned", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:
@@ -180,6 +184,8 @@ def load_library(path: str = LIB_PATH):
     lib.pll_export_labels.restype = ctypes.c_int
     lib.pll_export_labels_side.argtypes = [P, U32, P, P, P, P]
     lib.pll_export_labels_side.restype = ctypes.c_int
+    lib.pll_export_bp.argtypes = [P, P, P, P, P, P, P]
+    lib.pll_export_bp.restype = ctypes.c_int
     lib.pll_build_labels_directed.argtypes = [U32, U64, P, P, P, ctypes.POINTER(BuildOpts), P, ctypes.POINTER(P)]
     lib.pll_build_labels_directed.restype = ctypes.c_int
     lib.pll_build_labels_weighted.argtypes = [U32, U64, P, P, P, P, ctypes.POINTER(BuildOpts), P, ctypes.POINTER(P)]
@@ -229,7 +235,7 @@ def _dev(t: torch.Tensor, dtype: torch.dtype, name: str) -> torch.Tensor:
 
 
 def _opts(batch_size: int, flags: int, arena_entries: int, query_lanes: int, gang_scale: int = 0,
-          max_gang: int = 0, max_workgroups: int = 0) -> BuildOpts:
+          max_gang: int = 0, max_workgroups: int = 0, bp_roots: int = 0) -> BuildOpts:
     o = BuildOpts()
     o.batch_size = batch_size
     o.flags = flags
@@ -238,6 +244,7 @@ def _opts(batch_size: int, flags: int, arena_entries: int, query_lanes: int, gan
     o.gang_scale = gang_scale
     o.max_gang = max_gang
     o.max_workgroups = max_workgroups
+    o.bp_roots = bp_roots
     return o
 
 
@@ -302,6 +309,24 @@ class Index:
             raise PllError(rc, "pll_export_labels_side")
         return ExportedLabels(off, hubs[:total], dists[:total])
 
+    def export_bp(self, stream=None) -> dict:
+        """Bit-parallel part (vertex ids): roots [t], nbrs [t, 64] (-1 past a
+        set), dist [n, t] uint8, sm1 / s0 [n, t] (int64 views of the uint64 sets)."""
+        inf = self.info()
+        n, t = inf["n"], inf["bp_roots"]
+        dev = self.device
+        roots = torch.empty(max(t, 1), dtype=torch.int32, device=dev)
+        nbrs = torch.empty(max(t, 1) * 64, dtype=torch.int32, device=dev)
+        dist = torch.empty(max(n * t, 1), dtype=torch.uint8, device=dev)
+        sm1 = torch.empty(max(n * t, 1), dtype=torch.int64, device=dev)
+        s0 = torch.empty(max(n * t, 1), dtype=torch.int64, device=dev)
+        rc = load_library().pll_export_bp(self.handle, roots.data_ptr(), nbrs.data_ptr(), dist.data_ptr(),
+                                          sm1.data_ptr(), s0.data_ptr(), _stream_handle(stream))
+        if rc:
+            raise PllError(rc, "pll_export_bp")
+        return {"roots": roots[:t], "nbrs": nbrs[:t * 64].view(t, 64), "dist": dist[:n * t].view(n, t),
+                "sm1": sm1[:n * t].view(n, t), "s0": s0[:n * t].view(n, t)}
+
     def free(self):
         if self._h:
             load_library().pll_index_free(self._h)
@@ -316,9 +341,11 @@ class Index:
 
 def build_labels(row_ptr: torch.Tensor, col: torch.Tensor, order: torch.Tensor, batch_size: int = DEFAULT_BATCH,
                  flags: int = FLAG_VALIDATE, arena_entries: int = 0, query_lanes: int = 0, max_workgroups: int = 0,
-                 stream=None) -> Index:
+                 bp_roots: int = 0, stream=None) -> Index:
     """Canonical 2-hop labels of the CSR graph (row_ptr int64 [n+1], col
-    int32 [nnz], order int32 [n]: order[k] = vertex of rank k)."""
+    int32 [nnz], order int32 [n]: order[k] = vertex of rank k).  With
+    bp_roots > 0, bit-parallel labels of that many roots come first and the
+    stored labels cover only what they do not (Section 5.2)."""
     row_ptr = _dev(row_ptr, torch.int64, "row_ptr")
     col = _dev(col, torch.int32, "col")
     order = _dev(order, torch.int32, "order")
@@ -326,7 +353,7 @@ def build_labels(row_ptr: torch.Tensor, col: torch.Tensor, order: torch.Tensor, 
     if row_ptr.numel() != n + 1:
         raise PllError(PLL_EINVAL, "row_ptr must have n+1 entries")
     h = ctypes.c_void_p()
-    o = _opts(batch_size, flags, arena_entries, query_lanes, max_workgroups=max_workgroups)
+    o = _opts(batch_size, flags, arena_entries, query_lanes, max_workgroups=max_workgroups, bp_roots=bp_roots)
     rc = load_library().pll_build_labels(n, col.numel(), row_ptr.data_ptr(), col.data_ptr(), order.data_ptr(),
                                          ctypes.byref(o), _stream_handle(stream), ctypes.byref(h))
     if rc:

@@ -35,6 +35,12 @@ void free_index(pll_index* idx) {
         (void)hipFree(idx->d_off_out);
         (void)hipFree(idx->d_ent_out);
     }
+    if (idx->d_bp_roots) {
+        (void)hipFree(idx->d_bp_roots);
+        (void)hipFree(idx->d_bp_nbrs);
+        (void)hipFree(idx->d_bp_dist);
+        (void)hipFree(idx->d_bp_sets);
+    }
     if (idx->store) {
         if (idx->store->refs.fetch_sub(1) == 1) {
             (void)hipFree(idx->store->ptr);
@@ -90,6 +96,30 @@ int pll_export_labels_side(const pll_index* idx, uint32_t side, uint64_t* d_offs
         if (blocks > 65536) blocks = 65536;
         k_export<<<(uint32_t)blocks, kBlock, 0, stream>>>(total, ent, idx->d_order, d_hubs, d_dists);
         if (hipGetLastError() != hipSuccess) return PLL_EDEVICE;
+    }
+    return PLL_OK;
+}
+
+int pll_export_bp(const pll_index* idx, uint32_t* d_roots, uint32_t* d_nbrs, uint8_t* d_dist, uint64_t* d_sm1,
+                  uint64_t* d_s0, hipStream_t stream) {
+    if (!idx) return PLL_EINVAL;
+    const uint32_t t = idx->info.bp_roots;
+    if (t == 0) return PLL_OK;
+    if (!d_roots || !d_nbrs || !d_dist || !d_sm1 || !d_s0) return PLL_EINVAL;
+    const size_t nt = (size_t)idx->n * t;
+    if (hipMemcpyAsync(d_roots, idx->d_bp_roots, sizeof(uint32_t) * t, hipMemcpyDeviceToDevice, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(d_nbrs, idx->d_bp_nbrs, sizeof(uint32_t) * 64 * t, hipMemcpyDeviceToDevice, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(d_dist, idx->d_bp_dist, nt, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+        return PLL_EDEVICE;
+    if (nt) {
+        // the (S^-1, S^0) pairs split into two arrays
+        if (hipMemcpy2DAsync(d_sm1, sizeof(uint64_t), idx->d_bp_sets, sizeof(ulonglong2), sizeof(uint64_t), nt,
+                             hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+            hipMemcpy2DAsync(d_s0, sizeof(uint64_t), reinterpret_cast<const char*>(idx->d_bp_sets) + sizeof(uint64_t),
+                             sizeof(ulonglong2), sizeof(uint64_t), nt, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+            return PLL_EDEVICE;
     }
     return PLL_OK;
 }

@@ -265,8 +265,8 @@ __device__ inline pll::Exec grid_exec(const BuildArgs& A) {
 // into the workgroup's shard.  Every thread of the block must call this.
 template <int N>
 __device__ inline void block_add_stats(DevCounters* ctr, const unsigned long long (&v)[N], const int (&which)[N]) {
-    static_assert(N <= 6, "at most 6 statistics per call");
-    __shared__ unsigned long long s_part[kWavesPerBlock][6];
+    static_assert(N <= 8, "at most 8 statistics per call");
+    __shared__ unsigned long long s_part[kWavesPerBlock][8];
     const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -334,9 +334,10 @@ __global__ void __launch_bounds__(kBlock) k_check(BuildArgs A, uint32_t ib, uint
                                                   uint32_t relaxed) {
     PhaseStats st;
     pll::phase_check<WM>(A, grid_exec(A), ib, bs, j, p, relaxed != 0, st);
-    const unsigned long long v[6] = {st.cand, st.acc, st.read, st.table, st.cost_pos, st.cost_neg};
-    const int which[6] = {PLL_ST_CAND, PLL_ST_ACC, PLL_ST_READ, PLL_ST_TABLE, PLL_ST_COST_POS, PLL_ST_COST_NEG};
-    block_add_stats<6>(A.ctr, v, which);
+    const unsigned long long v[7] = {st.cand, st.acc, st.read, st.table, st.cost_pos, st.cost_neg, st.bp};
+    const int which[7] = {PLL_ST_CAND,     PLL_ST_ACC,      PLL_ST_READ, PLL_ST_TABLE,
+                          PLL_ST_COST_POS, PLL_ST_COST_NEG, PLL_ST_BP};
+    block_add_stats<7>(A.ctr, v, which);
 }
 
 template <int WM>
@@ -404,6 +405,227 @@ __global__ void k_check_weights(uint64_t nnz, const uint8_t* w, DevCounters* ctr
 
 __global__ void __launch_bounds__(kBlock) k_clear_table(BuildArgs A, uint32_t ib, uint32_t bs) {
     pll::phase_clear_table(A, grid_exec(A), ib, bs);
+}
+
+// ---- bit-parallel labels (Section 5.2) ------------------------------------------------------------
+
+// Choose up to t_req BP roots in rank space (one workgroup of 1,024
+// threads): the root is the smallest unused rank; its neighbour set is its
+// (up to) 64 smallest unused neighbour ranks, found by an 8-bit radix
+// select over the 24-bit ranks (three histogram passes over the row), then
+// ordered by counting.  The root and the set become used.
+constexpr int kSelBlock = 1024;
+
+__global__ void __launch_bounds__(kSelBlock) k_bp_select(uint32_t n, uint32_t t_req, const uint64_t* rrow,
+                                                         const uint32_t* rcol, uint8_t* used, uint32_t* roots,
+                                                         uint32_t* nbrs, uint32_t* t_out /* [2]: roots, used */) {
+    __shared__ uint32_t s_hist[256];
+    __shared__ uint32_t s_sel[64];
+    __shared__ uint32_t s_next, s_cnt, s_prefix, s_kth;
+    const uint32_t tid = threadIdx.x;
+    uint32_t cursor = 0, t = 0, nused = 0;
+    for (; t < t_req; ++t) {
+        if (tid == 0) s_next = 0xFFFFFFFFu;
+        __syncthreads();
+        uint32_t r = 0xFFFFFFFFu;
+        for (uint32_t base = cursor; base < n; base += kSelBlock) {
+            const uint32_t x = base + tid;
+            if (x < n && !used[x]) atomicMin(&s_next, x);
+            __syncthreads();
+            r = s_next;
+            __syncthreads();  // every thread has read s_next before the next chunk writes it
+            if (r != 0xFFFFFFFFu) break;
+        }
+        if (r == 0xFFFFFFFFu) break;
+        cursor = r + 1;
+        const uint64_t beg = rrow[r], end = rrow[r + 1];
+        if (tid == 0) {
+            used[r] = 1;
+            s_cnt = 0;
+        }
+        __syncthreads();
+        uint32_t c = 0;
+        for (uint64_t e = beg + tid; e < end; e += kSelBlock) c += used[rcol[e]] ? 0u : 1u;
+        if (c) atomicAdd(&s_cnt, c);
+        __syncthreads();
+        const uint32_t cnt = s_cnt;
+        uint32_t limit = 0xFFFFFFFFu;  // largest rank taken
+        if (cnt > 64) {
+            if (tid == 0) {
+                s_prefix = 0;
+                s_kth = 64;
+            }
+            for (int shift = 16; shift >= 0; shift -= 8) {
+                for (uint32_t b = tid; b < 256; b += kSelBlock) s_hist[b] = 0;
+                __syncthreads();
+                const uint32_t prefix = s_prefix;
+                for (uint64_t e = beg + tid; e < end; e += kSelBlock) {
+                    const uint32_t x = rcol[e];
+                    if (!used[x] && (x >> (shift + 8)) == (prefix >> (shift + 8)))
+                        atomicAdd(&s_hist[(x >> shift) & 255u], 1u);
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    uint32_t cum = 0, kth = s_kth;
+                    for (uint32_t b = 0; b < 256; ++b) {
+                        if (cum + s_hist[b] >= kth) {
+                            s_prefix = prefix | (b << shift);
+                            s_kth = kth - cum;
+                            break;
+                        }
+                        cum += s_hist[b];
+                    }
+                }
+                __syncthreads();
+            }
+            limit = s_prefix;  // the 64th smallest unused neighbour rank
+        }
+        if (tid == 0) s_cnt = 0;
+        __syncthreads();
+        for (uint64_t e = beg + tid; e < end; e += kSelBlock) {
+            const uint32_t x = rcol[e];
+            if (!used[x] && x <= limit) {
+                const uint32_t slot = atomicAdd(&s_cnt, 1u);
+                if (slot < 64) s_sel[slot] = x;  // more only with duplicate neighbours (an invalid CSR)
+            }
+        }
+        __syncthreads();
+        const uint32_t m = min(s_cnt, 64u);
+        if (tid < 64) {
+            uint32_t pos = tid;
+            if (tid < m) {
+                const uint32_t x = s_sel[tid];
+                pos = 0;
+                for (uint32_t q = 0; q < m; ++q) pos += s_sel[q] < x ? 1u : 0u;
+                nbrs[t * 64 + pos] = x;
+            } else {
+                nbrs[t * 64 + tid] = 0xFFFFFFFFu;
+            }
+        }
+        if (tid == 0) {
+            roots[t] = r;
+            nused += 1 + m;
+        }
+        __syncthreads();
+        if (tid < m) used[s_sel[tid]] = 1;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        t_out[0] = t;
+        t_out[1] = nused;
+    }
+}
+
+// Level 0 and the neighbour sets at level 1 of every BP root (block i = root i).
+__global__ void k_bp_seed(uint32_t t, const uint32_t* roots, const uint32_t* nbrs, uint8_t* bp_dist,
+                          ulonglong2* bp_sets) {
+    const uint32_t i = blockIdx.x, j = threadIdx.x;
+    if (j == 64) {
+        bp_dist[(size_t)roots[i] * t + i] = 0;
+    } else if (j < 64) {
+        const uint32_t s = nbrs[i * 64 + j];
+        if (s != 0xFFFFFFFFu) {
+            bp_dist[(size_t)s * t + i] = 1;
+            bp_sets[(size_t)s * t + i] = make_ulonglong2(1ull << j, 0ull);
+        }
+    }
+}
+
+// Level L+1 of every BP root, pulled by each unreached vertex from its
+// neighbours at level L: S^-1 and S^0 are the ORs of theirs (a member s of
+// S_r at distance L - 1 or L from a parent is at distance L or L + 1 from
+// the vertex).  Waves own vertices, so nothing a wave reads is written in
+// the same launch (a neighbour turning L + 1 is not at level L either way).
+__global__ void __launch_bounds__(kBlock) k_bp_pull(uint32_t n, uint32_t t, uint32_t L, const uint64_t* rrow,
+                                                    const uint32_t* rcol, uint8_t* bp_dist, ulonglong2* bp_sets,
+                                                    DevCounters* ctr) {
+    const uint32_t lane = lane_id();
+    for (uint32_t v = global_wave(); v < n; v += num_waves()) {
+        const uint64_t need = ballot64(lane < t && bp_dist[(size_t)v * t + lane] == PLL_INF8);
+        if (!need) continue;
+        const uint64_t beg = rrow[v], end = rrow[v + 1];
+        uint64_t todo = need;
+        while (todo) {
+            const uint32_t i = (uint32_t)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            bool found = false;
+            uint64_t s1 = 0, s0 = 0;
+            for (uint64_t e = beg + lane; e < end; e += 64) {
+                const uint32_t w = rcol[e];
+                if (bp_dist[(size_t)w * t + i] == L) {
+                    const ulonglong2 sw = bp_sets[(size_t)w * t + i];
+                    found = true;
+                    s1 |= sw.x;
+                    s0 |= sw.y;
+                }
+            }
+            if (!ballot64(found)) continue;
+            s1 = wave_or64(s1);
+            s0 = wave_or64(s0);
+            if (lane == 0) {
+                if (L + 1 >= PLL_INF8) {
+                    atomicOr(&ctr->error, PLL_ERR_DIST);
+                } else {
+                    bp_dist[(size_t)v * t + i] = (uint8_t)(L + 1);
+                    bp_sets[(size_t)v * t + i] = make_ulonglong2(s1, s0);
+                }
+            }
+        }
+    }
+}
+
+// Siblings at level L: S^0(v) gains S^-1 of every neighbour at the same
+// level, then drops what S^-1(v) holds.  Counts the (vertex, root) pairs at
+// level L into the first shard's receiver counter (the loop stops at 0).
+__global__ void __launch_bounds__(kBlock) k_bp_sibling(uint32_t n, uint32_t t, uint32_t L, const uint64_t* rrow,
+                                                       const uint32_t* rcol, const uint8_t* bp_dist,
+                                                       ulonglong2* bp_sets, DevCounters* ctr) {
+    const uint32_t lane = lane_id();
+    uint32_t seen = 0;
+    for (uint32_t v = global_wave(); v < n; v += num_waves()) {
+        const uint64_t at_l = ballot64(lane < t && bp_dist[(size_t)v * t + lane] == L);
+        if (!at_l) continue;
+        seen += (uint32_t)__builtin_popcountll(at_l);
+        const uint64_t beg = rrow[v], end = rrow[v + 1];
+        uint64_t todo = at_l;
+        while (todo) {
+            const uint32_t i = (uint32_t)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            uint64_t acc = 0;
+            for (uint64_t e = beg + lane; e < end; e += 64) {
+                const uint32_t w = rcol[e];
+                if (bp_dist[(size_t)w * t + i] == L) acc |= bp_sets[(size_t)w * t + i].x;
+            }
+            acc = wave_or64(acc);
+            if (lane == 0) {
+                ulonglong2* p = &bp_sets[(size_t)v * t + i];
+                p->y = (p->y | acc) & ~p->x;
+            }
+        }
+    }
+    if (lane == 0 && seen) atomicAdd(&ctr->sh[0].recv[0], seen);
+}
+
+// BP data by vertex id for the index, and the roots and sets as vertex ids.
+__global__ void k_bp_by_vertex(uint32_t n, uint32_t t, const uint32_t* rank, const uint8_t* bp_dist,
+                               const ulonglong2* bp_sets, uint8_t* out_dist, ulonglong2* out_sets) {
+    const uint64_t total = (uint64_t)n * t;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < total;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = (uint32_t)(x / t), i = (uint32_t)(x % t);
+        const size_t src = (size_t)rank[v] * t + i;
+        out_dist[x] = bp_dist[src];
+        out_sets[x] = bp_sets[src];
+    }
+}
+
+__global__ void k_bp_ids(uint32_t t, const uint32_t* order, const uint32_t* roots, const uint32_t* nbrs,
+                         uint32_t* out_roots, uint32_t* out_nbrs) {
+    for (uint32_t x = threadIdx.x; x < t * 64; x += blockDim.x) {
+        const uint32_t s = nbrs[x];
+        out_nbrs[x] = s == 0xFFFFFFFFu ? s : order[s];
+        if (x < t) out_roots[x] = order[roots[x]];
+    }
 }
 
 // ---- finalize -----------------------------------------------------------------------------------
@@ -825,9 +1047,58 @@ int finalize_labels(DevAllocs& M, const BuildArgs& A, const uint32_t* rank, uint
 }
 
 // One complete build attempt with a given initial arena size.
+// Bit-parallel labels of up to t_req roots in rank space (Section 5.2):
+// choose the roots and their sets, then grow every root's levels together,
+// one pull and one sibling launch per level, until a level is empty.
+struct BpState {
+    uint32_t t = 0, used_count = 0;
+    uint8_t* used = nullptr;
+    uint32_t* roots = nullptr;
+    uint32_t* nbrs = nullptr;
+    uint8_t* dist = nullptr;
+    ulonglong2* sets = nullptr;
+};
+
+int build_bp(DevAllocs& M, uint32_t n, uint32_t t_req, const uint64_t* rrow, const uint32_t* rcol, DevCounters* ctr,
+             DevCounters* h, hipStream_t s, BpState* B) {
+    B->used = M.get<uint8_t>(n);
+    B->roots = M.get<uint32_t>(64);
+    B->nbrs = M.get<uint32_t>(64 * 64);
+    uint32_t* tcount = M.get<uint32_t>(2);
+    if (M.err != hipSuccess) return status_of(M.err);
+    TRY_HIP(hipMemsetAsync(B->used, 0, n, s));
+    k_bp_select<<<1, kSelBlock, 0, s>>>(n, t_req, rrow, rcol, B->used, B->roots, B->nbrs, tcount);
+    TRY_HIP(hipGetLastError());
+    uint32_t th[2] = {0, 0};
+    TRY_HIP(hipMemcpyAsync(th, tcount, sizeof(th), hipMemcpyDeviceToHost, s));
+    TRY_HIP(hipStreamSynchronize(s));
+    B->t = th[0];
+    B->used_count = th[1];
+    const uint32_t t = B->t;
+    if (t == 0) return PLL_OK;
+    B->dist = M.get<uint8_t>((size_t)n * t);
+    B->sets = M.get<ulonglong2>((size_t)n * t);
+    if (M.err != hipSuccess) return status_of(M.err);
+    TRY_HIP(hipMemsetAsync(B->dist, 0xFF, (size_t)n * t, s));
+    TRY_HIP(hipMemsetAsync(B->sets, 0, sizeof(ulonglong2) * n * t, s));
+    k_bp_seed<<<t, 65, 0, s>>>(t, B->roots, B->nbrs, B->dist, B->sets);
+    for (uint32_t L = 1; L < PLL_INF8; ++L) {
+        k_bp_pull<<<blocks_for_waves(n), kBlock, 0, s>>>(n, t, L - 1, rrow, rcol, B->dist, B->sets, ctr);
+        TRY_HIP(hipMemsetAsync(&ctr->sh[0].recv[0], 0, sizeof(uint32_t), s));
+        k_bp_sibling<<<blocks_for_waves(n), kBlock, 0, s>>>(n, t, L, rrow, rcol, B->dist, B->sets, ctr);
+        TRY_HIP(hipGetLastError());
+        int rc = read_counters(ctr, h, s);
+        if (rc) return rc;
+        if (h->error) return device_error_status(h->error);
+        if (h->sh[0].recv[0] == 0) break;
+    }
+    TRY_HIP(hipMemsetAsync(&ctr->sh[0].recv[0], 0, sizeof(uint32_t), s));
+    return PLL_OK;
+}
+
 int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* order,
                   uint32_t b, uint32_t flags, uint64_t arena_hint, bool arena_fixed, uint32_t max_workgroups,
-                  hipStream_t s, pll_index* idx, uint64_t* used_arena) {
+                  uint32_t bp_req, hipStream_t s, pll_index* idx, uint64_t* used_arena) {
     DevAllocs M;
     M.s = s;
     HostCounters HC;
@@ -854,6 +1125,15 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     uint64_t* spare_off = nullptr;
     rc = init_state(M, A, n, nnz, W, RC.rrow, RC.rcol, ctr, s, &spare_off);
     if (rc) return rc;
+    BpState BP;
+    if (bp_req) {
+        rc = build_bp(M, n, bp_req, RC.rrow, RC.rcol, ctr, h, s, &BP);
+        if (rc) return rc;
+        A.bp_t = BP.t;
+        A.bp_used = BP.used;
+        A.bp_dist = BP.dist;
+        A.bp_sets = BP.sets;
+    }
     // initial label layout: capacities 16/32, then the bump regions
     uint64_t region_cap = std::max<uint64_t>(4096, arena_hint / PLL_SHARDS);
     rc = relayout_arena(M, A, spare_off, tmp32, scan_scratch, true, region_cap, arena_fixed ? arena_hint : 0, s);
@@ -975,6 +1255,16 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     uint32_t* d_order = M.get_out<uint32_t>(n);
     if (M.err != hipSuccess) return status_of(M.err);
     TRY_HIP(hipMemcpyAsync(d_order, order, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+    if (BP.t) {
+        idx->d_bp_roots = M.get_out<uint32_t>(BP.t);
+        idx->d_bp_nbrs = M.get_out<uint32_t>((size_t)BP.t * 64);
+        idx->d_bp_dist = M.get_out<uint8_t>((size_t)n * BP.t);
+        idx->d_bp_sets = M.get_out<ulonglong2>((size_t)n * BP.t);
+        if (M.err != hipSuccess) return status_of(M.err);
+        k_bp_by_vertex<<<blocks_for_threads((uint64_t)n * BP.t), kBlock, 0, s>>>(n, BP.t, RC.rank, BP.dist, BP.sets,
+                                                                                 idx->d_bp_dist, idx->d_bp_sets);
+        k_bp_ids<<<1, kBlock, 0, s>>>(BP.t, order, BP.roots, BP.nbrs, idx->d_bp_roots, idx->d_bp_nbrs);
+    }
     TRY_HIP(hipGetLastError());
     P.span(PLL_PHASE_FINAL, e_fin, P.mark(), 5);
     rc = read_counters(ctr, h, s);
@@ -989,12 +1279,19 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     M.forget(d_off);
     M.forget(d_ent);
     M.forget(d_order);
+    M.forget(idx->d_bp_roots);
+    M.forget(idx->d_bp_nbrs);
+    M.forget(idx->d_bp_dist);
+    M.forget(idx->d_bp_sets);
     pll_index_info& I = idx->info;
     I.n = n;
     I.batch_size = b;
     I.total_entries = total;
     I.in_entries = total;
     I.out_entries = total;
+    I.bp_roots = BP.t;
+    I.bp_vertices = BP.used_count;
+    I.bp_pruned = sum_stat(h, PLL_ST_BP);
     I.label_bytes = total * sizeof(uint32_t) + ((uint64_t)n + 1) * sizeof(uint64_t);
     I.max_dist = h->max_dist;
     I.max_label = h->max_label;
@@ -1388,6 +1685,8 @@ int build_index(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint3
     if (o.flags & ~(PLL_FLAG_VALIDATE | PLL_FLAG_RECHECK | PLL_FLAG_RELAXED | PLL_FLAG_PROFILE | PLL_FLAG_PERSISTENT))
         return PLL_EINVAL;
     if ((directed || weighted) && (o.flags & (PLL_FLAG_RELAXED | PLL_FLAG_PERSISTENT))) return PLL_EINVAL;
+    if (o.bp_roots > 64 || (o.bp_roots && (directed || weighted || (o.flags & PLL_FLAG_PERSISTENT))))
+        return PLL_EINVAL;
     const uint32_t ql = o.query_lanes;
     if (!(ql == 0 || ql == 1 || ql == 4 || ql == 8 || ql == 16 || ql == 32 || ql == 64)) return PLL_EINVAL;
     if (n > 0 && (!d_row_ptr || !d_order || (nnz && !d_col))) return PLL_EINVAL;
@@ -1445,7 +1744,7 @@ int build_index(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint3
                                             idx, &used);
             else
                 rc = build_attempt(n, nnz, d_row_ptr, d_col, d_order, b, o.flags, cap, fixed, o.max_workgroups,
-                                   stream, idx, &used);
+                                   o.bp_roots, stream, idx, &used);
             idx->info.build_attempts = attempt;
             idx->info.arena_entries = used;
             if (rc == PLL_ENOSPC && !fixed && attempt < 8) {

@@ -43,6 +43,7 @@ enum {
     PLL_ST_RECHECK = 6,  // entries dropped by the recheck
     PLL_ST_COST_POS = 7, // sum of |L(v)| over checks that added an entry
     PLL_ST_COST_NEG = 8, // sum of |L(v)| over checks that pruned
+    PLL_ST_BP = 9,       // candidates pruned by the bit-parallel bound
     PLL_NUM_ST = 12
 };
 
@@ -101,6 +102,13 @@ struct BuildArgs {
     uint32_t* act_v[2];      // active list by parity (compact)
     uint64_t* act_delta[2];  // W words per active slot: delta L of that vertex
     uint2* act_rng[2];       // weighted graphs: (first, count) of the label entries the slot's vertex accepted
+    // bit-parallel labels (rank space; bp_t = 0: none): bp_used[r] marks the
+    // BP roots and their neighbour sets; per (rank r, BP root i) at r * bp_t + i:
+    // bp_dist = d_i(r), bp_sets = (S^-1, S^0)
+    uint32_t bp_t;
+    const uint8_t* bp_used;
+    const uint8_t* bp_dist;
+    const ulonglong2* bp_sets;
     uint2* hq[2];            // (active slot, chunk) items for rows longer than the heavy threshold
     uint64_t hq_seg;
     uint32_t* recv;          // receivers of the current round, segment per shard (seg = n)
@@ -252,5 +260,10 @@ struct pll_index {
     uint32_t query_lanes;
     pll_shared_store* store;  // non-null when d_ent points into a shared allocation
     pll_shared_store* meta;   // non-null when d_off and d_order point into a shared allocation
+    // bit-parallel labels (info.bp_roots roots; null when none), by vertex id
+    uint32_t* d_bp_roots;      // [t] vertex ids
+    uint32_t* d_bp_nbrs;       // [t * 64] vertex ids, PLL_DIST_INF padding
+    uint8_t* d_bp_dist;        // [n * t]
+    ulonglong2* d_bp_sets;     // [n * t] (S^-1, S^0)
     pll_index_info info;
 };

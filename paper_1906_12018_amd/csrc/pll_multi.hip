@@ -607,6 +607,10 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
         A.T = (uint8_t*)(tp + o.T);
         A.Tchk = A.T;
         A.rmchk = A.rowmask;
+        A.rw = nullptr;  // unweighted, no bit-parallel labels
+        A.D = nullptr;
+        A.act_rng[0] = A.act_rng[1] = nullptr;
+        A.bp_t = 0;
         J.rank = (uint32_t*)(op + o.rank);
         A.rrow = (uint64_t*)(op + o.rrow);
         A.rcol = (uint32_t*)(op + o.rcol);
@@ -767,6 +771,7 @@ int pll_build_multi(uint32_t count, const pll_graph_desc* graphs, const pll_buil
     if (count == 0) return PLL_OK;
     pll_build_opts o{};
     if (opts) o = *opts;
+    if (o.bp_roots) return PLL_EINVAL;  // bit-parallel labels: single-graph builds only
     for (uint32_t r : o.reserved)
         if (r) return PLL_EINVAL;
     const uint32_t b = o.batch_size ? o.batch_size : PLL_BMAX;

@@ -27,7 +27,7 @@ struct Exec {
 
 // Per-lane statistics a phase accumulates (summed over lanes by the caller).
 struct PhaseStats {
-    unsigned long long cand = 0, acc = 0, edges = 0, read = 0, table = 0, removed = 0;
+    unsigned long long cand = 0, acc = 0, edges = 0, read = 0, table = 0, removed = 0, bp = 0;
     // cost of the positive / negative checks: |L(v)| at each check that
     // added / pruned a candidate (Section 4.3, Table 3)
     unsigned long long cost_pos = 0, cost_neg = 0;
@@ -210,6 +210,11 @@ __device__ inline void phase_batch_init(const BuildArgs& A, const Exec& X, uint3
             A.touched[tpos] = u;
             A.tstart[tpos] = len;
         }
+        if (A.bp_t && A.bp_used[u]) {  // a bit-parallel vertex is no root of the rounds
+            if (lane == 0) A.act_v[0][k] = u;
+            if (lane < A.W) A.act_delta[0][(size_t)k * A.W + lane] = 0ull;
+            continue;
+        }
         const uint64_t off = wave_reserve(A, X, u, A.loff[u], len, 1);
         if (off == ~0ull) continue;
         const uint32_t kw = 1u << (k >> 6);
@@ -314,6 +319,54 @@ __device__ inline void phase_push(const BuildArgs& A, const Exec& X, uint32_t ib
     }
 }
 
+// Bit-parallel bound (Section 5.2) of every candidate in `mine` at v for
+// distance j: candidate u_k is pruned when, for some BP root i,
+// d_i(u_k) + d_i(v) - c <= j, with c = 2 when the S^-1 sets of u_k and v
+// meet, else 1 when S^-1 of one meets S^0 of the other, else 0.  Lane i
+// (< bp_t) holds v's data of root i; lanes run over the candidates of one
+// word at a time.  Returns, in lane w, the pruned bits of word w.
+template <int WM>
+__device__ inline uint64_t bp_prune_words(const BuildArgs& A, uint32_t v, uint32_t ib, uint32_t j, uint64_t mine) {
+    const uint32_t lane = lane_id();
+    const uint32_t t = A.bp_t;
+    uint32_t dv = PLL_INF8;
+    ulonglong2 sv = make_ulonglong2(0ull, 0ull);
+    if (lane < t) {
+        dv = A.bp_dist[(size_t)v * t + lane];
+        sv = A.bp_sets[(size_t)v * t + lane];
+    }
+    const uint64_t roots_v = ballot64(lane < t && dv != PLL_INF8);
+    uint64_t out = 0;
+#pragma unroll
+    for (int w = 0; w < WM; ++w) {
+        const uint64_t m = readlane64(mine, w);
+        if (!m) continue;
+        const bool cand = (m >> lane) & 1ull;
+        const size_t ubase = (size_t)(ib + 64u * w + lane) * t;
+        uint32_t bound = 0xFFFFFFFFu;
+        uint64_t todo = roots_v;
+        while (todo) {
+            const uint32_t i = (uint32_t)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint32_t dvi = readlane32(dv, i);
+            const uint64_t v1 = readlane64(sv.x, i), v0 = readlane64(sv.y, i);
+            if (cand) {
+                const uint32_t du = A.bp_dist[ubase + i];
+                if (du != PLL_INF8) {
+                    const ulonglong2 su = A.bp_sets[ubase + i];
+                    uint32_t td = du + dvi;
+                    if (su.x & v1) td -= 2;
+                    else if ((su.x & v0) | (su.y & v1)) td -= 1;
+                    bound = min(bound, td);
+                }
+            }
+        }
+        const uint64_t pr = ballot64(cand && bound <= j);
+        if (lane == (uint32_t)w) out = pr;
+    }
+    return out;
+}
+
 // Gather phase (Algorithm 4, lines 11-19) for round j: one wave per
 // receiver.  Receiver i (in shard order) becomes slot i of the next active
 // list (with an empty delta when nothing was accepted).
@@ -339,8 +392,14 @@ __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t i
         }
         const uint32_t len = A.llen[v];
         uint64_t off = A.loff[v];
-        const uint64_t pw = prune_scan<WM>(A, off, len, j, mine, relaxed, ib, st);
-        const uint64_t acc = lane < W ? (mine & ~pw) : 0ull;
+        uint64_t scan = mine;
+        if (A.bp_t) {
+            const uint64_t bpp = bp_prune_words<WM>(A, v, ib, j, mine);
+            st.bp += __builtin_popcountll(lane < W ? bpp : 0ull);
+            scan &= ~bpp;
+        }
+        const uint64_t pw = prune_scan<WM>(A, off, len, j, scan, relaxed, ib, st);
+        const uint64_t acc = lane < W ? (scan & ~pw) : 0ull;
         const uint32_t cnt = (uint32_t)__builtin_popcountll(acc);
         const uint32_t pos = wave_excl_scan32(cnt);
         const uint32_t total = readlane32(pos + cnt, 63);

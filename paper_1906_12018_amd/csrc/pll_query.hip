@@ -18,6 +18,8 @@
 //    The pair's minimum is reduced across the group at the end.
 // For a directed index (Section 5.1) the distance from u to v merges
 // L_out(u) with L_in(v); the kernels take the two lists' arrays apart.
+// With bit-parallel labels (Section 5.2) the answer is the smaller of the
+// merge and the BP bound; the group's lanes split the BP roots.
 #include <atomic>
 
 #include "pll_internal.h"
@@ -25,6 +27,24 @@
 namespace {
 
 constexpr int kBlock = 256;
+
+// Bit-parallel bound of (u, v) over BP roots i = first, first + step, ...
+// (Section 5.2): d_i(u) + d_i(v), minus 2 when the S^-1 sets meet, else
+// minus 1 when S^-1 of one meets S^0 of the other.
+__device__ inline uint32_t bp_bound(const uint8_t* __restrict__ bpd, const ulonglong2* __restrict__ bps, uint32_t t,
+                                    uint32_t u, uint32_t v, uint32_t first, uint32_t step) {
+    uint32_t best = PLL_DIST_INF;
+    for (uint32_t i = first; i < t; i += step) {
+        const uint32_t du = bpd[(size_t)u * t + i], dv = bpd[(size_t)v * t + i];
+        if (du == PLL_INF8 || dv == PLL_INF8) continue;
+        const ulonglong2 su = bps[(size_t)u * t + i], sv = bps[(size_t)v * t + i];
+        uint32_t td = du + dv;
+        if (su.x & sv.x) td -= 2;
+        else if ((su.x & sv.y) | (su.y & sv.x)) td -= 1;
+        best = min(best, td);
+    }
+    return best;
+}
 constexpr uint32_t kAfter = 0xFFFFFFFFu;  // sorts after every key
 
 __global__ void __launch_bounds__(kBlock) k_query_lane(const uint64_t* __restrict__ offu,
@@ -32,7 +52,9 @@ __global__ void __launch_bounds__(kBlock) k_query_lane(const uint64_t* __restric
                                                        const uint64_t* __restrict__ offv,
                                                        const uint32_t* __restrict__ entv, uint32_t n, uint64_t count,
                                                        const uint32_t* __restrict__ qu,
-                                                       const uint32_t* __restrict__ qv, uint32_t* __restrict__ out) {
+                                                       const uint32_t* __restrict__ qv, uint32_t* __restrict__ out,
+                                                       const uint8_t* __restrict__ bpd,
+                                                       const ulonglong2* __restrict__ bps, uint32_t bpt) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t u = qu[i], v = qv[i];
@@ -62,6 +84,7 @@ __global__ void __launch_bounds__(kBlock) k_query_lane(const uint64_t* __restric
                 }
             }
         }
+        if (bpt && u < n && v < n) best = min(best, bp_bound(bpd, bps, bpt, u, v, 0, 1));
         out[i] = best;
     }
 }
@@ -139,7 +162,9 @@ __global__ void __launch_bounds__(kBlock) k_query_group(const uint64_t* __restri
                                                         const uint64_t* __restrict__ offv,
                                                         const uint32_t* __restrict__ entv, uint32_t n, uint64_t count,
                                                         const uint32_t* __restrict__ qu,
-                                                        const uint32_t* __restrict__ qv, uint32_t* __restrict__ out) {
+                                                        const uint32_t* __restrict__ qv, uint32_t* __restrict__ out,
+                                                        const uint8_t* __restrict__ bpd,
+                                                        const ulonglong2* __restrict__ bps, uint32_t bpt) {
     static_assert(G >= 4 && G <= 64 && (G & (G - 1)) == 0, "group size");
     constexpr int32_t kWinU = kEntriesU * G, kWinV = kEntriesV * G;
     __shared__ uint4 s_win[kBlock];
@@ -225,6 +250,7 @@ __global__ void __launch_bounds__(kBlock) k_query_group(const uint64_t* __restri
                 if (b_hi > 0) load_window<kEntriesV>(wb, b_lo, b_hi, gl, kb);
             }
         }
+        if (bpt && u < n && v < n) best = min(best, bp_bound(bpd, bps, bpt, u, v, gl, G));
 #pragma unroll
         for (int s = G / 2; s >= 1; s >>= 1) best = min(best, (uint32_t)__shfl_xor((int)best, s, G));
         if (gl == 0) out[p] = best;
@@ -260,7 +286,8 @@ void launch_group(const pll_index* idx, uint64_t count, const uint32_t* d_u, con
     const uint64_t* offu = idx->directed ? idx->d_off_out : idx->d_off;
     const uint32_t* entu = idx->directed ? idx->d_ent_out : idx->d_ent;
     k_query_group<G><<<(uint32_t)blocks, kBlock, 0, stream>>>(offu, entu, idx->d_off, idx->d_ent, idx->n, count, d_u,
-                                                               d_v, d_out);
+                                                               d_v, d_out, idx->d_bp_dist, idx->d_bp_sets,
+                                                               idx->info.bp_roots);
 }
 
 // Lanes per pair when the index leaves it open: the window (4 entries per
@@ -284,7 +311,7 @@ int pll_query_launch(const pll_index* idx, uint64_t count, const uint32_t* d_u, 
             if (blocks > 65536) blocks = 65536;
             k_query_lane<<<(uint32_t)blocks, kBlock, 0, stream>>>(
                 idx->directed ? idx->d_off_out : idx->d_off, idx->directed ? idx->d_ent_out : idx->d_ent, idx->d_off,
-                idx->d_ent, idx->n, count, d_u, d_v, d_out);
+                idx->d_ent, idx->n, count, d_u, d_v, d_out, idx->d_bp_dist, idx->d_bp_sets, idx->info.bp_roots);
             break;
         }
         case 4: launch_group<4>(idx, count, d_u, d_v, d_out, stream); break;

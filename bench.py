@@ -10,8 +10,8 @@ events; --steps profiled builds follow, and their HIP events give the
 kernel times of the roofline entry.  Other modes: --mode query (queries
 alone), --mode batched (the 256-graph one-launch build), --mode serve (the
 serving loop), --mode directed (directed R-MAT build and query), --mode
-weighted (R-MAT with 1..7 weights, build and query), each printing its own
-JSON line.
+weighted (R-MAT with 1..7 weights, build and query), --mode bp (builds with
+bit-parallel labels), each printing its own JSON line.
 """
 from __future__ import annotations
 
@@ -429,6 +429,75 @@ def weighted_mode(args):
     print(json.dumps(res), flush=True)
 
 
+def bp_mode(args):
+    """Bit-parallel labels (Section 5.2) on the bench graph: R-MAT of scale
+    --bp-scale, degree order, b = --batch-size, for each BP root count in
+    --bp-roots: a step is one build (BP part and normal labels) followed by
+    one batched query of 10^6 uniform pairs (seed 2).  Reports build time,
+    normal-label entries, BP data bytes and query rate per root count; the
+    CPU baseline is the BP oracle at the first nonzero root count."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1906_12018_amd as pll
+    dev = torch.device("cuda:0")
+    g = synth.rmat_graph(args.bp_scale, 16, seed=1)
+    order = synth.degree_order(g)
+    rp, cl = pll.graph_to_device(g, dev)
+    od = torch.from_numpy(order.view(np.int32)).to(dev)
+    pairs = 1_000_000
+    u, v = synth.query_pairs(g.n, pairs, seed=2)
+    du = torch.from_numpy(u.view(np.int32)).to(dev)
+    dv = torch.from_numpy(v.view(np.int32)).to(dev)
+    out = torch.empty_like(du)
+    rows, ref_out = [], None
+    for t in args.bp_roots:
+        build_ms, query_ms = [], []
+        for it in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            idx = pll.build_labels(rp, cl, od, batch_size=args.batch_size, flags=0, bp_roots=t)
+            t1 = time.perf_counter()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            idx.query(du, dv, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            if ref_out is None:
+                ref_out = out.clone()
+            assert torch.equal(out, ref_out), "distances differ between root counts"
+            if it >= args.warmup:
+                build_ms.append((t1 - t0) * 1e3)
+                query_ms.append(e0.elapsed_time(e1))
+            if it < args.warmup + args.steps - 1:
+                idx.free()
+        pidx = pll.build_labels(rp, cl, od, batch_size=args.batch_size, flags=pll.FLAG_PROFILE, bp_roots=t)
+        info = pidx.info()
+        pidx.free()
+        idx.free()
+        rows.append({"bp_roots": info["bp_roots"], "bp_vertices": info["bp_vertices"],
+                     "build_ms_p50": float(np.median(build_ms)), "label_entries": info["total_entries"],
+                     "bp_bytes": g.n * info["bp_roots"] * 17,
+                     "candidates": info["candidates"], "bp_pruned": info["bp_pruned"],
+                     "queries_per_s": pairs / (float(np.median(query_ms)) / 1e3),
+                     "build_phase_ms": {k: round(x, 3) for k, x in info["phase_ms"].items()}})
+    res = {"mode": "bp", "workload": f"rmat{args.bp_scale} build with bit-parallel labels + {pairs} query pairs",
+           "n": g.n, "undirected_edges": g.num_edges, "batch_size": args.batch_size, "steps": args.steps,
+           "runs": rows}
+    t_cpu = next((t for t in args.bp_roots if t), 0)
+    if t_cpu and not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        lab, bp = oracle.pll_labels_bp(g, order, t_cpu)
+        dt = time.perf_counter() - t0
+        want = oracle.query_bp(lab, bp, u, v)
+        assert np.array_equal(want, ref_out.cpu().numpy().view(np.uint32)), "oracle and GPU distances differ"
+        res["cpu_baseline"] = {"value": dt, "unit": "s per build", "cores": 1, "kind": "oracle",
+                               "sample": f"full sequential BP oracle build with {t_cpu} roots (BP data from "
+                                         "one BFS per root and per set member, then PLL)", "label_entries": lab.total}
+    print(json.dumps(res), flush=True)
+
+
 def serve_mode(args):
     """Serving workload: R-MAT scale-20 index resident; open-loop Poisson
     arrivals (stream 4) of query requests with sizes log-uniform in [1, 65536]
@@ -542,7 +611,10 @@ def main():
     ap.add_argument("--workload", default="rmat16", choices=sorted(WORKLOADS))
     ap.add_argument("--batch-size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="build", choices=["build", "query", "batched", "serve", "directed", "weighted"])
+    ap.add_argument("--mode", default="build",
+                    choices=["build", "query", "batched", "serve", "directed", "weighted", "bp"])
+    ap.add_argument("--bp-scale", type=int, default=16)
+    ap.add_argument("--bp-roots", type=int, nargs="+", default=[0, 4, 16, 64])
     ap.add_argument("--directed-scale", type=int, default=16)
     ap.add_argument("--weighted-scale", type=int, default=16)
     ap.add_argument("--tune-cache", default="", help="batched mode: autotuner cache file")
@@ -570,6 +642,9 @@ def main():
         return
     if args.mode == "weighted":
         weighted_mode(args)
+        return
+    if args.mode == "bp":
+        bp_mode(args)
         return
     if args.mode == "query":
         query_mode(args)

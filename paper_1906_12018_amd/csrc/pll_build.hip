@@ -329,11 +329,11 @@ __global__ void __launch_bounds__(kBlock) k_push(BuildArgs A, uint32_t ib, uint3
     block_add_stats<1>(A.ctr, v, which);
 }
 
-template <int WM>
+template <int WM, bool BP>
 __global__ void __launch_bounds__(kBlock) k_check(BuildArgs A, uint32_t ib, uint32_t bs, uint32_t j, uint32_t p,
                                                   uint32_t relaxed) {
     PhaseStats st;
-    pll::phase_check<WM>(A, grid_exec(A), ib, bs, j, p, relaxed != 0, st);
+    pll::phase_check<WM, BP>(A, grid_exec(A), ib, bs, j, p, relaxed != 0, st);
     const unsigned long long v[7] = {st.cand, st.acc, st.read, st.table, st.cost_pos, st.cost_neg, st.bp};
     const int which[7] = {PLL_ST_CAND,     PLL_ST_ACC,      PLL_ST_READ, PLL_ST_TABLE,
                           PLL_ST_COST_POS, PLL_ST_COST_NEG, PLL_ST_BP};
@@ -531,44 +531,38 @@ __global__ void k_bp_seed(uint32_t t, const uint32_t* roots, const uint32_t* nbr
     }
 }
 
-// Level L+1 of every BP root, pulled by each unreached vertex from its
-// neighbours at level L: S^-1 and S^0 are the ORs of theirs (a member s of
-// S_r at distance L - 1 or L from a parent is at distance L or L + 1 from
-// the vertex).  Waves own vertices, so nothing a wave reads is written in
-// the same launch (a neighbour turning L + 1 is not at level L either way).
-__global__ void __launch_bounds__(kBlock) k_bp_pull(uint32_t n, uint32_t t, uint32_t L, const uint64_t* rrow,
+// Level L+1 of every BP root, pushed from the vertices at level L: a
+// neighbour that is unreached, or already reached at L+1 in this launch,
+// is at L+1 and ORs in the vertex's S^-1 and S^0 (a member s of S_r at
+// distance L - 1 or L from a parent is at distance L or L + 1 from the
+// child).  The sets of level L are final here and nothing at level L is
+// written, so the pushes of one launch do not interfere.
+__global__ void __launch_bounds__(kBlock) k_bp_push(uint32_t n, uint32_t t, uint32_t L, const uint64_t* rrow,
                                                     const uint32_t* rcol, uint8_t* bp_dist, ulonglong2* bp_sets,
                                                     DevCounters* ctr) {
     const uint32_t lane = lane_id();
     for (uint32_t v = global_wave(); v < n; v += num_waves()) {
-        const uint64_t need = ballot64(lane < t && bp_dist[(size_t)v * t + lane] == PLL_INF8);
-        if (!need) continue;
+        const uint64_t at_l = ballot64(lane < t && bp_dist[(size_t)v * t + lane] == L);
+        if (!at_l) continue;
+        if (L + 1 >= PLL_INF8) {
+            if (lane == 0) atomicOr(&ctr->error, PLL_ERR_DIST);
+            continue;
+        }
         const uint64_t beg = rrow[v], end = rrow[v + 1];
-        uint64_t todo = need;
+        uint64_t todo = at_l;
         while (todo) {
             const uint32_t i = (uint32_t)__builtin_ctzll(todo);
             todo &= todo - 1;
-            bool found = false;
-            uint64_t s1 = 0, s0 = 0;
+            const ulonglong2 sv = bp_sets[(size_t)v * t + i];
             for (uint64_t e = beg + lane; e < end; e += 64) {
                 const uint32_t w = rcol[e];
-                if (bp_dist[(size_t)w * t + i] == L) {
-                    const ulonglong2 sw = bp_sets[(size_t)w * t + i];
-                    found = true;
-                    s1 |= sw.x;
-                    s0 |= sw.y;
-                }
-            }
-            if (!ballot64(found)) continue;
-            s1 = wave_or64(s1);
-            s0 = wave_or64(s0);
-            if (lane == 0) {
-                if (L + 1 >= PLL_INF8) {
-                    atomicOr(&ctr->error, PLL_ERR_DIST);
-                } else {
-                    bp_dist[(size_t)v * t + i] = (uint8_t)(L + 1);
-                    bp_sets[(size_t)v * t + i] = make_ulonglong2(s1, s0);
-                }
+                uint8_t* dw = &bp_dist[(size_t)w * t + i];
+                const uint32_t d = *dw;
+                if (d != PLL_INF8 && d != L + 1) continue;
+                if (d == PLL_INF8) *dw = (uint8_t)(L + 1);
+                ulonglong2* sw = &bp_sets[(size_t)w * t + i];
+                if (sv.x) atomicOr((unsigned long long*)&sw->x, (unsigned long long)sv.x);
+                if (sv.y) atomicOr((unsigned long long*)&sw->y, (unsigned long long)sv.y);
             }
         }
     }
@@ -604,6 +598,18 @@ __global__ void __launch_bounds__(kBlock) k_bp_sibling(uint32_t n, uint32_t t, u
         }
     }
     if (lane == 0 && seen) atomicAdd(&ctr->sh[0].recv[0], seen);
+}
+
+// Transposed copy of the batch vertices' BP data (root-major, so that the
+// check's lanes over batch vertices read consecutive addresses).
+__global__ void k_bp_batch_stage(BuildArgs A, uint32_t ib, uint32_t bs) {
+    const uint32_t t = A.bp_t;
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < t * bs; x += gridDim.x * blockDim.x) {
+        const uint32_t i = x / bs, k = x % bs;
+        const size_t src = (size_t)(ib + k) * t + i;
+        A.bpb_dist[(size_t)i * A.bstride + k] = A.bp_dist[src];
+        A.bpb_sets[(size_t)i * A.bstride + k] = A.bp_sets[src];
+    }
 }
 
 // BP data by vertex id for the index, and the roots and sets as vertex ids.
@@ -807,7 +813,10 @@ int device_error_status(uint32_t err) {
 template <int WM>
 void launch_check(uint32_t blocks, hipStream_t s, const BuildArgs& A, uint32_t ib, uint32_t bs, uint32_t j,
                   uint32_t p, uint32_t relaxed) {
-    k_check<WM><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, p, relaxed);
+    if (A.bp_t)
+        k_check<WM, true><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, p, relaxed);
+    else
+        k_check<WM, false><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, p, relaxed);
 }
 
 template <int WM>
@@ -1049,7 +1058,7 @@ int finalize_labels(DevAllocs& M, const BuildArgs& A, const uint32_t* rank, uint
 // One complete build attempt with a given initial arena size.
 // Bit-parallel labels of up to t_req roots in rank space (Section 5.2):
 // choose the roots and their sets, then grow every root's levels together,
-// one pull and one sibling launch per level, until a level is empty.
+// one push and one sibling launch per level, until a level is empty.
 struct BpState {
     uint32_t t = 0, used_count = 0;
     uint8_t* used = nullptr;
@@ -1083,7 +1092,7 @@ int build_bp(DevAllocs& M, uint32_t n, uint32_t t_req, const uint64_t* rrow, con
     TRY_HIP(hipMemsetAsync(B->sets, 0, sizeof(ulonglong2) * n * t, s));
     k_bp_seed<<<t, 65, 0, s>>>(t, B->roots, B->nbrs, B->dist, B->sets);
     for (uint32_t L = 1; L < PLL_INF8; ++L) {
-        k_bp_pull<<<blocks_for_waves(n), kBlock, 0, s>>>(n, t, L - 1, rrow, rcol, B->dist, B->sets, ctr);
+        k_bp_push<<<blocks_for_waves(n), kBlock, 0, s>>>(n, t, L - 1, rrow, rcol, B->dist, B->sets, ctr);
         TRY_HIP(hipMemsetAsync(&ctr->sh[0].recv[0], 0, sizeof(uint32_t), s));
         k_bp_sibling<<<blocks_for_waves(n), kBlock, 0, s>>>(n, t, L, rrow, rcol, B->dist, B->sets, ctr);
         TRY_HIP(hipGetLastError());
@@ -1133,6 +1142,11 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
         A.bp_used = BP.used;
         A.bp_dist = BP.dist;
         A.bp_sets = BP.sets;
+        if (BP.t) {
+            A.bpb_dist = M.get<uint8_t>((size_t)BP.t * A.bstride);
+            A.bpb_sets = M.get<ulonglong2>((size_t)BP.t * A.bstride);
+            if (M.err != hipSuccess) return status_of(M.err);
+        }
     }
     // initial label layout: capacities 16/32, then the bump regions
     uint64_t region_cap = std::max<uint64_t>(4096, arena_hint / PLL_SHARDS);
@@ -1187,8 +1201,9 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
         ++batches;
         hipEvent_t e0 = P.mark();
         k_batch_prep<<<1, 64, 0, s>>>(ctr);
+        if (A.bp_t) k_bp_batch_stage<<<blocks_for_threads((uint64_t)A.bp_t * bs), kBlock, 0, s>>>(A, ib, bs);
         k_batch_init<<<blocks_for_waves(bs), kBlock, 0, s>>>(A, ib, bs, bstamp);
-        P.span(PLL_PHASE_INIT, e0, P.mark(), 2);
+        P.span(PLL_PHASE_INIT, e0, P.mark(), A.bp_t ? 3 : 2);
         uint32_t p = 0, nact = bs;
         uint64_t heavy_waves = 1024;  // heavy items of the first round are not known on the host
         for (uint32_t j = 1;; ++j) {

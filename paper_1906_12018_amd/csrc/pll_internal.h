@@ -109,6 +109,11 @@ struct BuildArgs {
     const uint8_t* bp_used;
     const uint8_t* bp_dist;
     const ulonglong2* bp_sets;
+    // the same data of the current batch's vertices, transposed so that
+    // lanes over batch vertices read consecutive addresses: root i, batch
+    // vertex k at i * bstride + k
+    uint8_t* bpb_dist;
+    ulonglong2* bpb_sets;
     uint2* hq[2];            // (active slot, chunk) items for rows longer than the heavy threshold
     uint64_t hq_seg;
     uint32_t* recv;          // receivers of the current round, segment per shard (seg = n)

@@ -324,7 +324,8 @@ __device__ inline void phase_push(const BuildArgs& A, const Exec& X, uint32_t ib
 // d_i(u_k) + d_i(v) - c <= j, with c = 2 when the S^-1 sets of u_k and v
 // meet, else 1 when S^-1 of one meets S^0 of the other, else 0.  Lane i
 // (< bp_t) holds v's data of root i; lanes run over the candidates of one
-// word at a time.  Returns, in lane w, the pruned bits of word w.
+// word at a time, reading the batch vertices' data from the transposed
+// per-batch copy.  Returns, in lane w, the pruned bits of word w.
 template <int WM>
 __device__ inline uint64_t bp_prune_words(const BuildArgs& A, uint32_t v, uint32_t ib, uint32_t j, uint64_t mine) {
     const uint32_t lane = lane_id();
@@ -342,7 +343,7 @@ __device__ inline uint64_t bp_prune_words(const BuildArgs& A, uint32_t v, uint32
         const uint64_t m = readlane64(mine, w);
         if (!m) continue;
         const bool cand = (m >> lane) & 1ull;
-        const size_t ubase = (size_t)(ib + 64u * w + lane) * t;
+        const uint32_t kk = 64u * w + lane;
         uint32_t bound = 0xFFFFFFFFu;
         uint64_t todo = roots_v;
         while (todo) {
@@ -351,9 +352,9 @@ __device__ inline uint64_t bp_prune_words(const BuildArgs& A, uint32_t v, uint32
             const uint32_t dvi = readlane32(dv, i);
             const uint64_t v1 = readlane64(sv.x, i), v0 = readlane64(sv.y, i);
             if (cand) {
-                const uint32_t du = A.bp_dist[ubase + i];
+                const uint32_t du = A.bpb_dist[(size_t)i * A.bstride + kk];
                 if (du != PLL_INF8) {
-                    const ulonglong2 su = A.bp_sets[ubase + i];
+                    const ulonglong2 su = A.bpb_sets[(size_t)i * A.bstride + kk];
                     uint32_t td = du + dvi;
                     if (su.x & v1) td -= 2;
                     else if ((su.x & v0) | (su.y & v1)) td -= 1;
@@ -370,7 +371,10 @@ __device__ inline uint64_t bp_prune_words(const BuildArgs& A, uint32_t v, uint32
 // Gather phase (Algorithm 4, lines 11-19) for round j: one wave per
 // receiver.  Receiver i (in shard order) becomes slot i of the next active
 // list (with an empty delta when nothing was accepted).
-template <int WM>
+//
+// BP (bit-parallel labels present) is a separate instantiation: the BP
+// bound's registers would otherwise cost every build occupancy.
+template <int WM, bool BP = false>
 __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t bs, uint32_t j, uint32_t p,
                                    bool relaxed, PhaseStats& st) {
     const uint32_t lane = lane_id();
@@ -393,7 +397,7 @@ __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t i
         const uint32_t len = A.llen[v];
         uint64_t off = A.loff[v];
         uint64_t scan = mine;
-        if (A.bp_t) {
+        if (BP) {
             const uint64_t bpp = bp_prune_words<WM>(A, v, ib, j, mine);
             st.bp += __builtin_popcountll(lane < W ? bpp : 0ull);
             scan &= ~bpp;

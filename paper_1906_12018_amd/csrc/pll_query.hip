@@ -47,6 +47,7 @@ __device__ inline uint32_t bp_bound(const uint8_t* __restrict__ bpd, const ulong
 }
 constexpr uint32_t kAfter = 0xFFFFFFFFu;  // sorts after every key
 
+template <bool BP>
 __global__ void __launch_bounds__(kBlock) k_query_lane(const uint64_t* __restrict__ offu,
                                                        const uint32_t* __restrict__ entu,
                                                        const uint64_t* __restrict__ offv,
@@ -84,7 +85,7 @@ __global__ void __launch_bounds__(kBlock) k_query_lane(const uint64_t* __restric
                 }
             }
         }
-        if (bpt && u < n && v < n) best = min(best, bp_bound(bpd, bps, bpt, u, v, 0, 1));
+        if (BP && u < n && v < n) best = min(best, bp_bound(bpd, bps, bpt, u, v, 0, 1));
         out[i] = best;
     }
 }
@@ -156,7 +157,7 @@ __device__ __forceinline__ uint64_t group_uniform(uint64_t x) {
 constexpr int kEntriesU = 2;
 constexpr int kEntriesV = 4;
 
-template <int G>
+template <int G, bool BP>
 __global__ void __launch_bounds__(kBlock) k_query_group(const uint64_t* __restrict__ offu,
                                                         const uint32_t* __restrict__ entu,
                                                         const uint64_t* __restrict__ offv,
@@ -250,7 +251,7 @@ __global__ void __launch_bounds__(kBlock) k_query_group(const uint64_t* __restri
                 if (b_hi > 0) load_window<kEntriesV>(wb, b_lo, b_hi, gl, kb);
             }
         }
-        if (bpt && u < n && v < n) best = min(best, bp_bound(bpd, bps, bpt, u, v, gl, G));
+        if (BP && u < n && v < n) best = min(best, bp_bound(bpd, bps, bpt, u, v, gl, G));
 #pragma unroll
         for (int s = G / 2; s >= 1; s >>= 1) best = min(best, (uint32_t)__shfl_xor((int)best, s, G));
         if (gl == 0) out[p] = best;
@@ -271,7 +272,7 @@ void launch_group(const pll_index* idx, uint64_t count, const uint32_t* d_u, con
     uint64_t cap = dev >= 0 && dev < 64 ? cap_cache[dev].load(std::memory_order_relaxed) : 0;
     if (cap == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query_group<G>, kBlock, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query_group<G, false>, kBlock, 0) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1 ||
             cus < 1) {
             per_cu = 8;
@@ -285,9 +286,13 @@ void launch_group(const pll_index* idx, uint64_t count, const uint32_t* d_u, con
     // label serves both for an undirected index)
     const uint64_t* offu = idx->directed ? idx->d_off_out : idx->d_off;
     const uint32_t* entu = idx->directed ? idx->d_ent_out : idx->d_ent;
-    k_query_group<G><<<(uint32_t)blocks, kBlock, 0, stream>>>(offu, entu, idx->d_off, idx->d_ent, idx->n, count, d_u,
-                                                               d_v, d_out, idx->d_bp_dist, idx->d_bp_sets,
-                                                               idx->info.bp_roots);
+    if (idx->info.bp_roots)
+        k_query_group<G, true><<<(uint32_t)blocks, kBlock, 0, stream>>>(offu, entu, idx->d_off, idx->d_ent, idx->n,
+                                                                         count, d_u, d_v, d_out, idx->d_bp_dist,
+                                                                         idx->d_bp_sets, idx->info.bp_roots);
+    else
+        k_query_group<G, false><<<(uint32_t)blocks, kBlock, 0, stream>>>(offu, entu, idx->d_off, idx->d_ent, idx->n,
+                                                                          count, d_u, d_v, d_out, nullptr, nullptr, 0);
 }
 
 // Lanes per pair when the index leaves it open: the window (4 entries per
@@ -309,9 +314,16 @@ int pll_query_launch(const pll_index* idx, uint64_t count, const uint32_t* d_u, 
         case 1: {
             uint64_t blocks = (count + kBlock - 1) / kBlock;
             if (blocks > 65536) blocks = 65536;
-            k_query_lane<<<(uint32_t)blocks, kBlock, 0, stream>>>(
-                idx->directed ? idx->d_off_out : idx->d_off, idx->directed ? idx->d_ent_out : idx->d_ent, idx->d_off,
-                idx->d_ent, idx->n, count, d_u, d_v, d_out, idx->d_bp_dist, idx->d_bp_sets, idx->info.bp_roots);
+            const uint64_t* offu = idx->directed ? idx->d_off_out : idx->d_off;
+            const uint32_t* entu = idx->directed ? idx->d_ent_out : idx->d_ent;
+            if (idx->info.bp_roots)
+                k_query_lane<true><<<(uint32_t)blocks, kBlock, 0, stream>>>(offu, entu, idx->d_off, idx->d_ent, idx->n,
+                                                                            count, d_u, d_v, d_out, idx->d_bp_dist,
+                                                                            idx->d_bp_sets, idx->info.bp_roots);
+            else
+                k_query_lane<false><<<(uint32_t)blocks, kBlock, 0, stream>>>(offu, entu, idx->d_off, idx->d_ent, idx->n,
+                                                                             count, d_u, d_v, d_out, nullptr, nullptr,
+                                                                             0);
             break;
         }
         case 4: launch_group<4>(idx, count, d_u, d_v, d_out, stream); break;

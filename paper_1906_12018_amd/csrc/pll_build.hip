@@ -310,8 +310,8 @@ __global__ void __launch_bounds__(kBlock) k_compact(uint32_t n, const uint64_t* 
 __global__ void k_batch_prep(DevCounters* ctr) {
     if (threadIdx.x < PLL_SHARDS) {
         Shard& sh = ctr->sh[threadIdx.x];
-        sh.recv[0] = 0;
-        sh.hq[0] = 0;
+        sh.recv[0] = sh.recv[1] = sh.recv[2] = 0;
+        sh.hq[0] = sh.hq[1] = 0;
         sh.touched = 0;
     }
 }
@@ -338,6 +338,43 @@ __global__ void __launch_bounds__(kBlock) k_check(BuildArgs A, uint32_t ib, uint
     const int which[7] = {PLL_ST_CAND,     PLL_ST_ACC,      PLL_ST_READ, PLL_ST_TABLE,
                           PLL_ST_COST_POS, PLL_ST_COST_NEG, PLL_ST_BP};
     block_add_stats<7>(A.ctr, v, which);
+}
+
+// Round j's check fused with round j+1's push (NextRound in pll_phases.h).
+template <int WM, bool BP>
+__device__ inline void check_push_body(const BuildArgs& A, uint32_t ib, uint32_t bs, uint32_t j,
+                                       const pll::NextRound& nr, uint32_t relaxed) {
+    PhaseStats st;
+    pll::phase_check<WM, BP, true>(A, grid_exec(A), ib, bs, j, nr.rin, relaxed != 0, st, &nr);
+    const unsigned long long v[8] = {st.cand, st.acc, st.read, st.table, st.cost_pos, st.cost_neg, st.bp, st.edges};
+    const int which[8] = {PLL_ST_CAND,     PLL_ST_ACC,      PLL_ST_READ, PLL_ST_TABLE,
+                          PLL_ST_COST_POS, PLL_ST_COST_NEG, PLL_ST_BP,   PLL_ST_EDGES};
+    block_add_stats<8>(A.ctr, v, which);
+}
+
+// at most 128 VGPRs, i.e. 4 waves per SIMD, like the unfused check
+template <int WM>
+__global__ void __launch_bounds__(kBlock, 4) k_check_push(BuildArgs A, uint32_t ib, uint32_t bs, uint32_t j,
+                                                          pll::NextRound nr, uint32_t relaxed) {
+    check_push_body<WM, false>(A, ib, bs, j, nr, relaxed);
+}
+
+// with bit-parallel labels (no register cap: it would spill)
+template <int WM>
+__global__ void __launch_bounds__(kBlock) k_check_push_bp(BuildArgs A, uint32_t ib, uint32_t bs, uint32_t j,
+                                                          pll::NextRound nr, uint32_t relaxed) {
+    check_push_body<WM, true>(A, ib, bs, j, nr, relaxed);
+}
+
+// The heavy rows the fused round queued, pushed for the next round.
+__global__ void __launch_bounds__(kBlock) k_push_heavy(BuildArgs A, uint32_t ib, uint32_t hp, uint32_t rq,
+                                                       uint64_t* msgs, uint32_t* recv, uint32_t rstamp,
+                                                       uint32_t bstamp) {
+    PhaseStats st;
+    pll::phase_push_heavy(A, grid_exec(A), ib, hp, rq, msgs, recv, rstamp, bstamp, st);
+    const unsigned long long v[1] = {st.edges};
+    const int which[1] = {PLL_ST_EDGES};
+    block_add_stats<1>(A.ctr, v, which);
 }
 
 template <int WM>
@@ -838,6 +875,26 @@ void dispatch_check(uint32_t blocks, hipStream_t s, const BuildArgs& A, uint32_t
     }
 }
 
+template <int WM>
+void launch_check_push(uint32_t blocks, hipStream_t s, const BuildArgs& A, uint32_t ib, uint32_t bs, uint32_t j,
+                       const pll::NextRound& nr, uint32_t relaxed) {
+    if (A.bp_t)
+        k_check_push_bp<WM><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, nr, relaxed);
+    else
+        k_check_push<WM><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, nr, relaxed);
+}
+
+void dispatch_check_push(uint32_t blocks, hipStream_t s, const BuildArgs& A, uint32_t ib, uint32_t bs, uint32_t j,
+                         const pll::NextRound& nr, uint32_t relaxed) {
+    switch (words_class(A.W)) {
+        case 1: launch_check_push<1>(blocks, s, A, ib, bs, j, nr, relaxed); break;
+        case 2: launch_check_push<2>(blocks, s, A, ib, bs, j, nr, relaxed); break;
+        case 4: launch_check_push<4>(blocks, s, A, ib, bs, j, nr, relaxed); break;
+        case 8: launch_check_push<8>(blocks, s, A, ib, bs, j, nr, relaxed); break;
+        default: launch_check_push<16>(blocks, s, A, ib, bs, j, nr, relaxed); break;
+    }
+}
+
 void dispatch_batch_end(uint32_t blocks, hipStream_t s, const BuildArgs& A, uint32_t ib, uint32_t bs,
                         uint32_t recheck) {
     switch (words_class(A.W)) {
@@ -1167,6 +1224,16 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     // or (PLL_FLAG_PERSISTENT) one persistent launch that hands back to the
     // host only for arena compaction
     uint32_t grid_workgroups = 0;
+    // the second message buffer and receiver list of the fused rounds:
+    // round j's messages and receivers live in mbuf[j & 1] and rbuf[j & 1]
+    uint64_t* mbuf[2] = {A.msgs, nullptr};
+    uint32_t* rbuf[2] = {A.recv, nullptr};
+    if (!(flags & PLL_FLAG_PERSISTENT)) {
+        mbuf[1] = M.get<uint64_t>((size_t)n * W);
+        rbuf[1] = M.get<uint32_t>((size_t)PLL_SHARDS * n);
+        if (M.err != hipSuccess) return status_of(M.err);
+        TRY_HIP(hipMemsetAsync(mbuf[1], 0, sizeof(uint64_t) * n * W, s));
+    }
     if (flags & PLL_FLAG_PERSISTENT) {
         TRY_HIP(hipStreamSynchronize(s));
         P.resolve();
@@ -1204,23 +1271,34 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
         if (A.bp_t) k_bp_batch_stage<<<blocks_for_threads((uint64_t)A.bp_t * bs), kBlock, 0, s>>>(A, ib, bs);
         k_batch_init<<<blocks_for_waves(bs), kBlock, 0, s>>>(A, ib, bs, bstamp);
         P.span(PLL_PHASE_INIT, e0, P.mark(), A.bp_t ? 3 : 2);
-        uint32_t p = 0, nact = bs;
-        uint64_t heavy_waves = 1024;  // heavy items of the first round are not known on the host
-        for (uint32_t j = 1;; ++j) {
-            ++rstamp;
-            ++rounds;
+        // round 1's push from the batch vertices (active list 0) into
+        // receiver queue 0 and message buffer 1; afterwards every round j is
+        // one fused launch (check of round j, push of round j+1 into buffer
+        // (j+1) & 1), plus a launch for heavy rows when there are any
+        ++rstamp;
+        {
+            BuildArgs A1 = A;
+            A1.msgs = mbuf[1];
+            A1.recv = rbuf[1];
             hipEvent_t r0 = P.mark();
-            k_push<<<blocks_for_waves(nact + heavy_waves), kBlock, 0, s>>>(A, ib, p, nact, rstamp, bstamp);
+            k_push<<<blocks_for_waves((uint64_t)bs + 1024), kBlock, 0, s>>>(A1, ib, 0, bs, rstamp, bstamp);
+            P.span(PLL_PHASE_PUSH, r0, P.mark(), 1);
+        }
+        uint64_t next_est = bs;
+        for (uint32_t j = 1;; ++j) {
+            ++rounds;
+            const pll::NextRound nr{mbuf[(j + 1) & 1u], rbuf[(j + 1) & 1u], (j - 1) % 3, j % 3, (j + 1) % 3, j & 1u,
+                                    rstamp + 1, bstamp};
+            ++rstamp;
+            BuildArgs Aj = A;
+            Aj.msgs = mbuf[j & 1u];
+            Aj.recv = rbuf[j & 1u];
             hipEvent_t r1 = P.mark();
-            // receivers are unknown until the push has run; the grid-stride
-            // loop covers any count, the grid only sets how many waves share it
-            const uint32_t check_blocks = blocks_for_waves(std::min<uint64_t>(n, 16ull * nact + 2048));
-            dispatch_check(check_blocks, s, A, ib, bs, j, p, relaxed);
-            hipEvent_t r2 = P.mark();
-            P.span(PLL_PHASE_PUSH, r0, r1, 1);
-            P.span(PLL_PHASE_CHECK, r1, r2, 1);
+            dispatch_check_push(blocks_for_waves(std::min<uint64_t>(n, next_est + 2048)), s, Aj, ib, bs, j, nr,
+                                relaxed);
+            P.span(PLL_PHASE_CHECK, r1, P.mark(), 1);
             TRY_HIP(hipGetLastError());
-            const double push_ms0 = P.ms[PLL_PHASE_PUSH], check_ms0 = P.ms[PLL_PHASE_CHECK];
+            const double check_ms0 = P.ms[PLL_PHASE_CHECK];
             rc = read_counters(ctr, h, s);
             if (rc) return rc;
             P.resolve();
@@ -1229,20 +1307,25 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
                 unsigned long long cur[PLL_NUM_ST];
                 for (int k = 0; k < PLL_NUM_ST; ++k) cur[k] = sum_stat(h, k);
                 std::fprintf(stderr,
-                             "pll-trace batch=%u round=%u active=%u recv=%u cand=%llu acc=%llu read=%llu table=%llu "
-                             "grow=%llu push_us=%.1f check_us=%.1f\n",
-                             (unsigned)(ib / b), j, nact, sum_recv(h, p), cur[PLL_ST_CAND] - last[PLL_ST_CAND],
-                             cur[PLL_ST_ACC] - last[PLL_ST_ACC], cur[PLL_ST_READ] - last[PLL_ST_READ],
-                             cur[PLL_ST_TABLE] - last[PLL_ST_TABLE], cur[PLL_ST_GROW] - last[PLL_ST_GROW],
-                             (P.ms[PLL_PHASE_PUSH] - push_ms0) * 1e3, (P.ms[PLL_PHASE_CHECK] - check_ms0) * 1e3);
+                             "pll-trace batch=%u round=%u recv=%u next=%u heavy=%u cand=%llu acc=%llu read=%llu "
+                             "table=%llu grow=%llu check_us=%.1f\n",
+                             (unsigned)(ib / b), j, sum_recv(h, nr.rin), sum_recv(h, nr.rout), sum_hq(h, nr.hout),
+                             cur[PLL_ST_CAND] - last[PLL_ST_CAND], cur[PLL_ST_ACC] - last[PLL_ST_ACC],
+                             cur[PLL_ST_READ] - last[PLL_ST_READ], cur[PLL_ST_TABLE] - last[PLL_ST_TABLE],
+                             cur[PLL_ST_GROW] - last[PLL_ST_GROW], (P.ms[PLL_PHASE_CHECK] - check_ms0) * 1e3);
                 for (int k = 0; k < PLL_NUM_ST; ++k) last[k] = cur[k];
             }
             if (h->error) return device_error_status(h->error);
             if (acc_now == accepted_seen) break;  // nobody accepted anything: the batch is done
             accepted_seen = acc_now;
-            nact = sum_recv(h, p);
-            p ^= 1u;
-            heavy_waves = sum_hq(h, p);
+            const uint32_t nh = sum_hq(h, nr.hout);
+            if (nh) {
+                hipEvent_t r2 = P.mark();
+                k_push_heavy<<<blocks_for_waves(nh), kBlock, 0, s>>>(A, ib, nr.hout, nr.rout, nr.msgs, nr.recv,
+                                                                     nr.rstamp, bstamp);
+                P.span(PLL_PHASE_PUSH, r2, P.mark(), 1);
+            }
+            next_est = (uint64_t)sum_recv(h, nr.rout) + 1024ull * nh;
         }
         hipEvent_t e1 = P.mark();
         dispatch_batch_end(blocks_for_waves(sum_touched(h)), s, A, ib, bs, recheck);

@@ -48,10 +48,10 @@ enum {
 };
 
 struct alignas(128) Shard {
-    uint32_t recv[2];     // receivers appended to this shard's segment, by round parity
+    uint32_t recv[3];     // receivers appended to this shard's segment, by round (parity; the
+                          // fused check-and-push rounds rotate over three)
     uint32_t hq[2];       // heavy push items, by active-list parity
     uint32_t touched;     // vertices first touched in the batch
-    uint32_t pad;
     unsigned long long arena_top;  // bump pointer of this shard's arena region (entries, region-relative)
     unsigned long long stat[PLL_NUM_ST];
 };
@@ -85,7 +85,8 @@ struct BuildArgs {
     uint64_t region_cap;   // entries per region
     // per-vertex bit-vectors (W words each)
     uint64_t* C;     // candidate bit-vector C(v) of the batch (Section 4.1)
-    uint64_t* msgs;  // candidates received this round, already filtered by C
+    uint64_t* msgs;  // candidates received this round, already filtered by C (the fused
+                     // check-and-push rounds alternate two buffers and filter in the check)
     // per-batch distance table: T[h * bstride + k] = d(u_k, h) for (h, d) in L(u_k)
     uint8_t* T;
     uint32_t* rowmask;  // bit w set when row h of T has an entry in word w

@@ -238,9 +238,11 @@ __device__ inline void phase_batch_init(const BuildArgs& A, const Exec& X, uint3
 }
 
 // Push delta L(a) (lane w < W holds word w in dl; nz marks the nonzero
-// words) along the CSR entries [beg, end) of the active vertex a.
-__device__ inline void push_edges(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t p, uint32_t rstamp,
-                                  uint32_t bstamp, uint64_t dl, uint64_t nz, uint64_t beg, uint64_t end) {
+// words) along the CSR entries [beg, end) of the active vertex a, into the
+// message buffer msgs and receiver queue rq (counters) stored in recv.
+__device__ inline void push_edges(const BuildArgs& A, const Exec& X, uint64_t* msgs, uint32_t* recv, uint32_t ib,
+                                  uint32_t rq, uint32_t rstamp, uint32_t bstamp, uint64_t dl, uint64_t nz,
+                                  uint64_t beg, uint64_t end) {
     const uint32_t lane = lane_id();
     for (uint64_t e0 = beg; e0 < end; e0 += 64) {
         const uint64_t e = e0 + lane;
@@ -256,7 +258,7 @@ __device__ inline void push_edges(const BuildArgs& A, const Exec& X, uint32_t ib
                 if (m) {
                     m &= ~A.C[(size_t)r * A.W + w];
                     if (m) {
-                        atomicOr((unsigned long long*)&A.msgs[(size_t)r * A.W + w], (unsigned long long)m);
+                        atomicOr((unsigned long long*)&msgs[(size_t)r * A.W + w], (unsigned long long)m);
                         any = true;
                     }
                 }
@@ -272,14 +274,37 @@ __device__ inline void push_edges(const BuildArgs& A, const Exec& X, uint32_t ib
             first = true;
         }
         if (ballot64(enq)) {
-            const uint32_t rp = shard_append(&X.qs[X.my].recv[p], enq, (uint64_t)X.my * X.seg);
-            if (enq) A.recv[rp] = r;
+            const uint32_t rp = shard_append(&X.qs[X.my].recv[rq], enq, (uint64_t)X.my * X.seg);
+            if (enq) recv[rp] = r;
             const uint32_t tp = shard_append(&X.qs[X.my].touched, first, (uint64_t)X.my * X.seg);
             if (first) {
                 A.touched[tp] = r;
                 A.tstart[tp] = A.llen[r];
             }
         }
+    }
+}
+
+// The heavy-row items of active list p, spread over every wave: pushes
+// into msgs and receiver queue rq stored in recv.
+__device__ inline void phase_push_heavy(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t p, uint32_t rq,
+                                        uint64_t* msgs, uint32_t* recv, uint32_t rstamp, uint32_t bstamp,
+                                        PhaseStats& st) {
+    const uint32_t lane = lane_id();
+    const uint32_t* act_v = A.act_v[p];
+    const uint64_t* act_d = A.act_delta[p];
+    uint32_t pre;
+    const uint32_t nh = shard_prefix(lane < X.nq ? X.qs[lane].hq[p] : 0u, pre);
+    for (uint32_t t = X.w; t < nh; t += X.nw) {
+        const uint32_t s = shard_of(X.nq, pre, t);
+        const uint2 item = A.hq[p][s * A.hq_seg + (t - readlane32(pre, s))];
+        const uint64_t dl = lane < A.W ? act_d[(size_t)item.x * A.W + lane] : 0ull;
+        const uint64_t nz = ballot64(dl != 0);
+        const uint32_t a = act_v[item.x];
+        const uint64_t beg = A.rrow[a] + (uint64_t)item.y * kHeavy;
+        const uint64_t end = min(A.rrow[a + 1], beg + kHeavy);
+        if (lane == 0) st.edges += end - beg;
+        push_edges(A, X, msgs, recv, ib, rq, rstamp, bstamp, dl, nz, beg, end);
     }
 }
 
@@ -302,21 +327,9 @@ __device__ inline void phase_push(const BuildArgs& A, const Exec& X, uint32_t ib
         const uint64_t beg = A.rrow[a], end = A.rrow[a + 1];
         if (end - beg > kHeavy) continue;
         if (lane == 0) st.edges += end - beg;
-        push_edges(A, X, ib, p, rstamp, bstamp, dl, nz, beg, end);
+        push_edges(A, X, A.msgs, A.recv, ib, p, rstamp, bstamp, dl, nz, beg, end);
     }
-    uint32_t pre;
-    const uint32_t nh = shard_prefix(lane < X.nq ? X.qs[lane].hq[p] : 0u, pre);
-    for (uint32_t t = X.w; t < nh; t += X.nw) {
-        const uint32_t s = shard_of(X.nq, pre, t);
-        const uint2 item = A.hq[p][s * A.hq_seg + (t - readlane32(pre, s))];
-        const uint64_t dl = lane < A.W ? act_d[(size_t)item.x * A.W + lane] : 0ull;
-        const uint64_t nz = ballot64(dl != 0);
-        const uint32_t a = act_v[item.x];
-        const uint64_t beg = A.rrow[a] + (uint64_t)item.y * kHeavy;
-        const uint64_t end = min(A.rrow[a + 1], beg + kHeavy);
-        if (lane == 0) st.edges += end - beg;
-        push_edges(A, X, ib, p, rstamp, bstamp, dl, nz, beg, end);
-    }
+    phase_push_heavy(A, X, ib, p, p, A.msgs, A.recv, rstamp, bstamp, st);
 }
 
 // Bit-parallel bound (Section 5.2) of every candidate in `mine` at v for
@@ -374,16 +387,41 @@ __device__ inline uint64_t bp_prune_words(const BuildArgs& A, uint32_t v, uint32
 //
 // BP (bit-parallel labels present) is a separate instantiation: the BP
 // bound's registers would otherwise cost every build occupancy.
-template <int WM, bool BP = false>
+//
+// FUSE: the wave of a receiver that accepted something also pushes its
+// delta L for round j+1 right away (rows up to kHeavy; longer rows become
+// heavy items for a separate launch), into the other message buffer nr->msgs
+// and receiver queue nr->rout, whose entries go to nr->recv (this round's
+// receivers are read from A.recv, so the two lists never share storage).
+// C(r) of a neighbour may not hold this round's arrivals yet when the push
+// reads it, so the check filters its messages by C(v) itself.  Receiver
+// counters rotate over three (this round's nr->rin = p, the next round's,
+// and nr->rclr, cleared here); active lists and heavy items use parity
+// nr->hout.
+struct NextRound {
+    uint64_t* msgs;
+    uint32_t* recv;
+    uint32_t rin, rout, rclr, hout;
+    uint32_t rstamp, bstamp;
+};
+
+template <int WM, bool BP = false, bool FUSE = false>
 __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t bs, uint32_t j, uint32_t p,
-                                   bool relaxed, PhaseStats& st) {
+                                   bool relaxed, PhaseStats& st, const NextRound* nr = nullptr) {
     const uint32_t lane = lane_id();
     const uint32_t W = A.W;
-    const uint32_t q = p ^ 1u;
+    const uint32_t q = FUSE ? nr->hout : p ^ 1u;
     uint32_t pre;
     const uint32_t nrecv = shard_prefix(lane < X.nq ? X.qs[lane].recv[p] : 0u, pre);
-    // clear the other parity's receiver counts for the next round's push
-    if (X.zero_i < X.nq) X.qs[X.zero_i].recv[q] = 0;
+    // clear the counts the next launch appends to
+    if (X.zero_i < X.nq) {
+        if (FUSE) {
+            X.qs[X.zero_i].recv[nr->rclr] = 0;
+            X.qs[X.zero_i].hq[q ^ 1u] = 0;
+        } else {
+            X.qs[X.zero_i].recv[q] = 0;
+        }
+    }
     for (uint32_t i = X.w; i < nrecv; i += X.nw) {
         const uint32_t s = shard_of(X.nq, pre, i);
         const uint32_t v = A.recv[(size_t)s * X.seg + (i - readlane32(pre, s))];
@@ -392,6 +430,7 @@ __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t i
             const size_t at = (size_t)v * W + lane;
             mine = A.msgs[at];
             A.msgs[at] = 0;
+            if (FUSE) mine &= ~A.C[at];
             A.C[at] |= mine;
         }
         const uint32_t len = A.llen[v];
@@ -438,7 +477,14 @@ __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t i
             }
         }
         if (lane == 0) A.llen[v] = len + total;
-        enqueue_heavy(A, X, q, i, A.rrow[v + 1] - A.rrow[v]);
+        const uint64_t beg = A.rrow[v], end = A.rrow[v + 1];
+        if (FUSE && end - beg <= kHeavy) {
+            if (lane == 0) st.edges += end - beg;
+            push_edges(A, X, nr->msgs, nr->recv, ib, nr->rout, nr->rstamp, nr->bstamp, acc, ballot64(acc != 0), beg,
+                       end);
+        } else {
+            enqueue_heavy(A, X, q, i, end - beg);
+        }
     }
 }
 

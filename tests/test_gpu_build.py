@@ -237,3 +237,18 @@ def test_persistent_flag_is_accepted_and_unknown_flags_are_not():
     with pytest.raises(pll.PllError) as e:
         build(g, order, flags=0x400)
     assert e.value.status == pll.PLL_EINVAL
+
+
+@pytest.mark.parametrize("n,m,seed", [(4797, 3, 1001), (6575, 8, 1005), (7051, 8, 1007), (12000, 6, 77)])
+def test_many_batches_large_rounds(n, m, seed):
+    """Graphs of several batches whose rounds have thousands of receivers:
+    the check of a round and the push of the next share a launch, so the two
+    rounds' receiver lists and messages must not share storage."""
+    g = synth.ba_graph(n, m, seed)
+    order = synth.degree_order(g)
+    want = oracle.pll_labels(g, order)
+    idx = build(g, order)
+    assert_labels_equal(idx, want, order)
+    check_counters(idx, g, order, 1024, want)
+    u, v = synth.query_pairs(g.n, 20000, seed=3)
+    assert np.array_equal(gpu_query(idx, u, v), oracle.query(want, u, v))

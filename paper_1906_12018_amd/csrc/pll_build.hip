@@ -342,10 +342,10 @@ __global__ void __launch_bounds__(kBlock) k_check(BuildArgs A, uint32_t ib, uint
 
 // Round j's check fused with round j+1's push (NextRound in pll_phases.h).
 template <int WM, bool BP>
-__device__ inline void check_push_body(const BuildArgs& A, uint32_t ib, uint32_t bs, uint32_t j,
+__device__ inline void check_push_body(const BuildArgs& A, const pll::Exec& X, uint32_t ib, uint32_t bs, uint32_t j,
                                        const pll::NextRound& nr, uint32_t relaxed) {
     PhaseStats st;
-    pll::phase_check<WM, BP, true>(A, grid_exec(A), ib, bs, j, nr.rin, relaxed != 0, st, &nr);
+    pll::phase_check<WM, BP, true>(A, X, ib, bs, j, nr.rin, relaxed != 0, st, &nr);
     const unsigned long long v[8] = {st.cand, st.acc, st.read, st.table, st.cost_pos, st.cost_neg, st.bp, st.edges};
     const int which[8] = {PLL_ST_CAND,     PLL_ST_ACC,      PLL_ST_READ, PLL_ST_TABLE,
                           PLL_ST_COST_POS, PLL_ST_COST_NEG, PLL_ST_BP,   PLL_ST_EDGES};
@@ -356,14 +356,41 @@ __device__ inline void check_push_body(const BuildArgs& A, uint32_t ib, uint32_t
 template <int WM>
 __global__ void __launch_bounds__(kBlock, 4) k_check_push(BuildArgs A, uint32_t ib, uint32_t bs, uint32_t j,
                                                           pll::NextRound nr, uint32_t relaxed) {
-    check_push_body<WM, false>(A, ib, bs, j, nr, relaxed);
+    check_push_body<WM, false>(A, grid_exec(A), ib, bs, j, nr, relaxed);
+}
+
+// The blocks [b0, b0 + nb) of the grid run a phase on their own: queue
+// counters are the build's 32 shards, the first block clears them.
+__device__ inline pll::Exec side_exec(const BuildArgs& A, uint32_t b0, uint32_t nb) {
+    pll::Exec X;
+    X.w = ((blockIdx.x - b0) * blockDim.x + threadIdx.x) >> 6;
+    X.nw = (nb * blockDim.x) >> 6;
+    X.qs = A.ctr->sh;
+    X.nq = PLL_SHARDS;
+    X.my = (blockIdx.x - b0) % PLL_SHARDS;
+    X.seg = A.n;
+    X.zero_i = blockIdx.x == b0 ? threadIdx.x : ~0u;
+    X.arena_sh = X.my;
+    return X;
+}
+
+// Directed graphs: both sides' fused rounds in one launch, blocks [0, nb0)
+// on the forward side and the rest on the backward side.
+template <int WM>
+__global__ void __launch_bounds__(kBlock, 4) k_check_push2(BuildArgs A0, pll::NextRound nr0, BuildArgs A1,
+                                                           pll::NextRound nr1, uint32_t ib, uint32_t bs, uint32_t j,
+                                                           uint32_t nb0) {
+    if (blockIdx.x < nb0)
+        check_push_body<WM, false>(A0, side_exec(A0, 0, nb0), ib, bs, j, nr0, 0);
+    else
+        check_push_body<WM, false>(A1, side_exec(A1, nb0, gridDim.x - nb0), ib, bs, j, nr1, 0);
 }
 
 // with bit-parallel labels (no register cap: it would spill)
 template <int WM>
 __global__ void __launch_bounds__(kBlock) k_check_push_bp(BuildArgs A, uint32_t ib, uint32_t bs, uint32_t j,
                                                           pll::NextRound nr, uint32_t relaxed) {
-    check_push_body<WM, true>(A, ib, bs, j, nr, relaxed);
+    check_push_body<WM, true>(A, grid_exec(A), ib, bs, j, nr, relaxed);
 }
 
 // The heavy rows the fused round queued, pushed for the next round.
@@ -882,6 +909,18 @@ void launch_check_push(uint32_t blocks, hipStream_t s, const BuildArgs& A, uint3
         k_check_push_bp<WM><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, nr, relaxed);
     else
         k_check_push<WM><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, nr, relaxed);
+}
+
+void dispatch_check_push2(uint32_t nb0, uint32_t nb1, hipStream_t s, const BuildArgs& A0, const pll::NextRound& nr0,
+                          const BuildArgs& A1, const pll::NextRound& nr1, uint32_t ib, uint32_t bs, uint32_t j) {
+    const uint32_t g = nb0 + nb1;
+    switch (words_class(A0.W)) {
+        case 1: k_check_push2<1><<<g, kBlock, 0, s>>>(A0, nr0, A1, nr1, ib, bs, j, nb0); break;
+        case 2: k_check_push2<2><<<g, kBlock, 0, s>>>(A0, nr0, A1, nr1, ib, bs, j, nb0); break;
+        case 4: k_check_push2<4><<<g, kBlock, 0, s>>>(A0, nr0, A1, nr1, ib, bs, j, nb0); break;
+        case 8: k_check_push2<8><<<g, kBlock, 0, s>>>(A0, nr0, A1, nr1, ib, bs, j, nb0); break;
+        default: k_check_push2<16><<<g, kBlock, 0, s>>>(A0, nr0, A1, nr1, ib, bs, j, nb0); break;
+    }
 }
 
 void dispatch_check_push(uint32_t blocks, hipStream_t s, const BuildArgs& A, uint32_t ib, uint32_t bs, uint32_t j,
@@ -1617,6 +1656,15 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
         A[d].Tchk = A[d ^ 1].T;
         A[d].rmchk = A[d ^ 1].rowmask;
     }
+    // second message buffer and receiver list of each side's fused rounds
+    uint64_t* mbuf[2][2] = {{A[0].msgs, nullptr}, {A[1].msgs, nullptr}};
+    uint32_t* rbuf[2][2] = {{A[0].recv, nullptr}, {A[1].recv, nullptr}};
+    for (int d = 0; d < 2; ++d) {
+        mbuf[d][1] = M.get<uint64_t>((size_t)n * W);
+        rbuf[d][1] = M.get<uint32_t>((size_t)PLL_SHARDS * n);
+        if (M.err != hipSuccess) return status_of(M.err);
+        TRY_HIP(hipMemsetAsync(mbuf[d][1], 0, sizeof(uint64_t) * n * W, s));
+    }
     const uint64_t region_cap = std::max<uint64_t>(4096, arena_hint / (2 * PLL_SHARDS));
     for (int d = 0; d < 2; ++d) {
         rc = relayout_arena(M, A[d], spare_off[d], tmp32, scan_scratch, true, region_cap,
@@ -1645,24 +1693,35 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
             k_batch_init<<<blocks_for_waves(bs), kBlock, 0, s>>>(A[d], ib, bs, bstamp);
         }
         P.span(PLL_PHASE_INIT, e0, P.mark(), 4);
-        uint32_t p[2] = {0, 0}, nact[2] = {bs, bs};
-        uint64_t heavy_waves[2] = {1024, 1024};
+        // fused rounds as in the undirected build, both sides in one launch
+        ++rstamp;
+        for (int d = 0; d < 2; ++d) {
+            BuildArgs A1 = A[d];
+            A1.msgs = mbuf[d][1];
+            A1.recv = rbuf[d][1];
+            hipEvent_t r0 = P.mark();
+            k_push<<<blocks_for_waves((uint64_t)bs + 1024), kBlock, 0, s>>>(A1, ib, 0, bs, rstamp, bstamp);
+            P.span(PLL_PHASE_PUSH, r0, P.mark(), 1);
+        }
+        uint64_t next_est[2] = {bs, bs};
         bool live[2] = {true, true};
         for (uint32_t j = 1; live[0] || live[1]; ++j) {
-            ++rstamp;
             ++rounds;
+            pll::NextRound nr[2];
+            BuildArgs Aj[2];
+            uint32_t nb[2] = {0, 0};
             for (int d = 0; d < 2; ++d) {
-                if (!live[d]) continue;
-                hipEvent_t r0 = P.mark();
-                k_push<<<blocks_for_waves(nact[d] + heavy_waves[d]), kBlock, 0, s>>>(A[d], ib, p[d], nact[d], rstamp,
-                                                                                    bstamp);
-                hipEvent_t r1 = P.mark();
-                const uint32_t check_blocks = blocks_for_waves(std::min<uint64_t>(n, 16ull * nact[d] + 2048));
-                dispatch_check(check_blocks, s, A[d], ib, bs, j, p[d], 0);
-                hipEvent_t r2 = P.mark();
-                P.span(PLL_PHASE_PUSH, r0, r1, 1);
-                P.span(PLL_PHASE_CHECK, r1, r2, 1);
+                nr[d] = pll::NextRound{mbuf[d][(j + 1) & 1u], rbuf[d][(j + 1) & 1u], (j - 1) % 3, j % 3, (j + 1) % 3,
+                                       j & 1u, rstamp + 1, bstamp};
+                Aj[d] = A[d];
+                Aj[d].msgs = mbuf[d][j & 1u];
+                Aj[d].recv = rbuf[d][j & 1u];
+                if (live[d]) nb[d] = blocks_for_waves(std::min<uint64_t>(n, next_est[d] + 2048));
             }
+            ++rstamp;
+            hipEvent_t r1 = P.mark();
+            dispatch_check_push2(nb[0], nb[1], s, Aj[0], nr[0], Aj[1], nr[1], ib, bs, j);
+            P.span(PLL_PHASE_CHECK, r1, P.mark(), 1);
             TRY_HIP(hipGetLastError());
             rc = read_both();
             if (rc) return rc;
@@ -1676,9 +1735,14 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
                     continue;
                 }
                 accepted_seen[d] = acc_now;
-                nact[d] = sum_recv(h[d], p[d]);
-                p[d] ^= 1u;
-                heavy_waves[d] = sum_hq(h[d], p[d]);
+                const uint32_t nh = sum_hq(h[d], nr[d].hout);
+                if (nh) {
+                    hipEvent_t r2 = P.mark();
+                    k_push_heavy<<<blocks_for_waves(nh), kBlock, 0, s>>>(A[d], ib, nr[d].hout, nr[d].rout, nr[d].msgs,
+                                                                         nr[d].recv, nr[d].rstamp, bstamp);
+                    P.span(PLL_PHASE_PUSH, r2, P.mark(), 1);
+                }
+                next_est[d] = (uint64_t)sum_recv(h[d], nr[d].rout) + 1024ull * nh;
             }
         }
         // both sides' batch ends read the other side's table, so the tables

@@ -59,7 +59,7 @@ def consumed_entries(off, hubs_rank, rank, u, v):
 # profiles/hbm_traffic.txt is used only while their hash is unchanged.
 PKG_CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1906_12018_amd", "csrc")
 KERNEL_SOURCES = {
-    "k_check": ["pll_build.hip", "pll_phases.h", "pll_internal.h"],
+    "k_check_push": ["pll_build.hip", "pll_phases.h", "pll_internal.h"],
     "k_query_group": ["pll_query.hip", "pll_internal.h"],
 }
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic.txt")
@@ -318,7 +318,8 @@ def directed_mode(args):
     info = prof[-1]
     total = info["total_entries"]
     check_ms = float(np.mean([i["phase_ms"]["check"] for i in prof]))
-    check_bytes = 4 * info["check_entries_read"] + 64 * info["check_table_reads"] + 4 * info["accepted"]
+    check_bytes = (4 * info["check_entries_read"] + 64 * info["check_table_reads"] + 4 * info["accepted"]
+                   + 4 * info["check_push_edges"])
     check_gbs = check_bytes / (check_ms / 1e3) / 1e9
     res = {"mode": "directed", "workload": f"directed rmat{args.directed_scale} (arcs not symmetrised) build + "
                                            f"{pairs} query pairs",
@@ -330,7 +331,7 @@ def directed_mode(args):
            "query_batch_ms_p50": float(np.median(query_ms)),
            "rounds": info["rounds"], "batches": info["batches"], "candidates": info["candidates"],
            "build_phase_ms": {k: round(x, 3) for k, x in info["phase_ms"].items()},
-           "roofline": {"kernel": "k_check", "bound": "hbm", "achieved": check_gbs, "peak": HBM_PEAK_GBS,
+           "roofline": {"kernel": "k_check_push2", "bound": "hbm", "achieved": check_gbs, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": check_gbs / HBM_PEAK_GBS, "traffic": None,
                         "launches_per_step": info["phase_launches"]["check"], "bytes_per_step": check_bytes}}
     if not args.no_cpu_baseline:
@@ -712,18 +713,21 @@ def main():
     value = total * K / sum_build_s
     qps = w["pairs"] / (np.median(query_ms) / 1e3)
 
-    # roofline, dominant kernel: the pruning check (k_check), bytes per the
-    # kernel's traffic model, time from HIP events on the build stream
+    # roofline, dominant kernel: the fused pruning check and push
+    # (k_check_push), bytes per the kernel's traffic model (label entries and
+    # 64-byte table segments the scans read, entries appended, CSR entries the
+    # fused pushes read; the message atomics are not counted), time from HIP
+    # events on the build stream
     check_ms = np.mean([i["phase_ms"]["check"] for i in prof])
     check_launches = info["phase_launches"]["check"]
     check_bytes = (4 * info["check_entries_read"] + 64 * info["check_table_reads"]
-                   + 4 * info["accepted"])
+                   + 4 * info["accepted"] + 4 * info["check_push_edges"])
     check_gbs = check_bytes / (check_ms / 1e3) / 1e9
     cons = consumed_for(idx, g, order, u, v)
     q_bytes = w["pairs"] * (8 + 32 + 4) + 4 * cons
     q_gbs = q_bytes / (np.median(query_ms) / 1e3) / 1e9
 
-    tr_check = measured_traffic("k_check", args.workload)
+    tr_check = measured_traffic("k_check_push", args.workload)
     tr_query = measured_traffic("k_query_group", args.workload)
     res = {
         "metric": "index build s + label entries/s; batched queries/s with p50/p99 latency",
@@ -750,13 +754,13 @@ def main():
         "build_phase_ms": {k: round(x, 3) for k, x in info["phase_ms"].items()},
         "profiled_build_s": float(np.median([i["build_ms"] for i in prof]) / 1e3),
         "rounds": info["rounds"], "batches": info["batches"], "candidates": info["candidates"],
-        "roofline": {"kernel": "k_check", "bound": "hbm", "achieved": check_gbs, "peak": HBM_PEAK_GBS,
+        "roofline": {"kernel": "k_check_push", "bound": "hbm", "achieved": check_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": check_gbs / HBM_PEAK_GBS,
                      "traffic": tr_check["bytes"] if tr_check else None,
                      "launches_per_step": check_launches,
                      "avg_launch_us": check_ms * 1e3 / max(check_launches, 1),
                      "bytes_per_step": check_bytes,
-                     "timing": "HIP events around every k_check launch on the build stream, over --steps "
+                     "timing": "HIP events around every k_check_push launch on the build stream, over --steps "
                                "profiled builds run right after the timed steps"},
         "roofline_query": {"kernel": "k_query_group", "bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": q_gbs / HBM_PEAK_GBS,

@@ -131,6 +131,9 @@ typedef struct {
     uint32_t bp_roots;        /* bit-parallel roots the build chose (<= pll_build_opts.bp_roots) */
     uint32_t bp_vertices;     /* vertices they use (roots plus their neighbour sets) */
     uint64_t bp_pruned;       /* candidates the bit-parallel bound pruned */
+    uint64_t check_push_edges; /* CSR entries pushed by the check launches themselves (the rounds fuse the
+                                  check of round j with the push of round j+1); the rest of edges_scanned is
+                                  the first push of each batch and rows longer than 1,024 entries */
 } pll_index_info;
 
 /* One graph of a batched build (all pointers are device pointers). */

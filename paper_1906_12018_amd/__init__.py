@@ -93,6 +93,7 @@ class IndexInfo(ctypes.Structure):
         ("bp_roots", ctypes.c_uint32),
         ("bp_vertices", ctypes.c_uint32),
         ("bp_pruned", ctypes.c_uint64),
+        ("check_push_edges", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:

@@ -265,8 +265,8 @@ __device__ inline pll::Exec grid_exec(const BuildArgs& A) {
 // into the workgroup's shard.  Every thread of the block must call this.
 template <int N>
 __device__ inline void block_add_stats(DevCounters* ctr, const unsigned long long (&v)[N], const int (&which)[N]) {
-    static_assert(N <= 8, "at most 8 statistics per call");
-    __shared__ unsigned long long s_part[kWavesPerBlock][8];
+    static_assert(N <= 10, "at most 10 statistics per call");
+    __shared__ unsigned long long s_part[kWavesPerBlock][10];
     const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -346,10 +346,11 @@ __device__ inline void check_push_body(const BuildArgs& A, const pll::Exec& X, u
                                        const pll::NextRound& nr, uint32_t relaxed) {
     PhaseStats st;
     pll::phase_check<WM, BP, true>(A, X, ib, bs, j, nr.rin, relaxed != 0, st, &nr);
-    const unsigned long long v[8] = {st.cand, st.acc, st.read, st.table, st.cost_pos, st.cost_neg, st.bp, st.edges};
-    const int which[8] = {PLL_ST_CAND,     PLL_ST_ACC,      PLL_ST_READ, PLL_ST_TABLE,
-                          PLL_ST_COST_POS, PLL_ST_COST_NEG, PLL_ST_BP,   PLL_ST_EDGES};
-    block_add_stats<8>(A.ctr, v, which);
+    const unsigned long long v[9] = {st.cand,     st.acc, st.read,  st.table, st.cost_pos,
+                                     st.cost_neg, st.bp,  st.edges, st.edges};
+    const int which[9] = {PLL_ST_CAND,     PLL_ST_ACC, PLL_ST_READ,  PLL_ST_TABLE,      PLL_ST_COST_POS,
+                          PLL_ST_COST_NEG, PLL_ST_BP,  PLL_ST_EDGES, PLL_ST_FUSED_EDGES};
+    block_add_stats<9>(A.ctr, v, which);
 }
 
 // at most 128 VGPRs, i.e. 4 waves per SIMD, like the unfused check
@@ -965,6 +966,15 @@ void dispatch_batch_end_w(uint32_t blocks, hipStream_t s, const BuildArgs& A, ui
     }
 }
 
+// Keeps the stream busy for `ticks` of the device wall clock (bounded).
+// Profiled builds run it ahead of each timed launch so that the host has
+// queued the launch before its start event is stamped: the event span is
+// then the kernel's run, not the host's launch overhead.
+__global__ void k_delay(uint64_t ticks) {
+    const uint64_t t0 = wall_clock64();
+    while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(2);
+}
+
 __global__ void k_reset_tops(DevCounters* ctr) {
     if (threadIdx.x < PLL_SHARDS) ctr->sh[threadIdx.x].arena_top = 0;
 }
@@ -1263,6 +1273,14 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     // or (PLL_FLAG_PERSISTENT) one persistent launch that hands back to the
     // host only for arena compaction
     uint32_t grid_workgroups = 0;
+    // profiled builds: 30 us of device wall clock ahead of each timed check
+    uint64_t delay_ticks = 0;
+    if (P.on) {
+        int khz = 0, dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            delay_ticks = (uint64_t)khz * 30 / 1000;
+    }
     // the second message buffer and receiver list of the fused rounds:
     // round j's messages and receivers live in mbuf[j & 1] and rbuf[j & 1]
     uint64_t* mbuf[2] = {A.msgs, nullptr};
@@ -1332,6 +1350,7 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
             BuildArgs Aj = A;
             Aj.msgs = mbuf[j & 1u];
             Aj.recv = rbuf[j & 1u];
+            if (P.on) k_delay<<<1, 1, 0, s>>>(delay_ticks);
             hipEvent_t r1 = P.mark();
             dispatch_check_push(blocks_for_waves(std::min<uint64_t>(n, next_est + 2048)), s, Aj, ib, bs, j, nr,
                                 relaxed);
@@ -1429,6 +1448,7 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     I.bp_roots = BP.t;
     I.bp_vertices = BP.used_count;
     I.bp_pruned = sum_stat(h, PLL_ST_BP);
+    I.check_push_edges = sum_stat(h, PLL_ST_FUSED_EDGES);
     I.label_bytes = total * sizeof(uint32_t) + ((uint64_t)n + 1) * sizeof(uint64_t);
     I.max_dist = h->max_dist;
     I.max_label = h->max_label;
@@ -1819,6 +1839,7 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
     I.check_table_reads = both(PLL_ST_TABLE);
     I.check_cost_pos = both(PLL_ST_COST_POS);
     I.check_cost_neg = both(PLL_ST_COST_NEG);
+    I.check_push_edges = both(PLL_ST_FUSED_EDGES);
     for (int ph = 0; ph < PLL_NUM_PHASES; ++ph) {
         I.phase_ms[ph] = P.ms[ph];
         I.phase_launches[ph] = P.launches[ph];

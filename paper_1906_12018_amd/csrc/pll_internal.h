@@ -44,6 +44,7 @@ enum {
     PLL_ST_COST_POS = 7, // sum of |L(v)| over checks that added an entry
     PLL_ST_COST_NEG = 8, // sum of |L(v)| over checks that pruned
     PLL_ST_BP = 9,       // candidates pruned by the bit-parallel bound
+    PLL_ST_FUSED_EDGES = 10,  // CSR entries pushed inside the fused check-and-push launches
     PLL_NUM_ST = 12
 };
 

@@ -126,6 +126,12 @@ def query_mode(args):
     du = torch.from_numpy(u.view(np.int32)).to(dev)
     dv = torch.from_numpy(v.view(np.int32)).to(dev)
     out = torch.empty_like(du)
+    tuned = None
+    if args.tune_query:
+        from paper_1906_12018_amd import autotune
+        # tune on the first tenth of the pairs, then time all of them
+        k = max(1, w["pairs"] // 10)
+        tuned = autotune.tune_query(idx, du[:k], dv[:k], save=False)
     for _ in range(args.warmup):
         idx.query(du, dv, out=out)
     torch.cuda.synchronize()
@@ -148,7 +154,9 @@ def query_mode(args):
                                    "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                                    "traffic": tr["bytes"] if tr else None,
                                    "bytes_per_launch": q_bytes, "entries_consumed": cons},
-                      "label_entries": idx.info()["total_entries"]}), flush=True)
+                      "label_entries": idx.info()["total_entries"],
+                      "query_lanes": tuned["best"] if tuned else "auto",
+                      "tuning": tuned["results"] if tuned else None}), flush=True)
     idx.free()
 
 
@@ -619,6 +627,7 @@ def main():
     ap.add_argument("--directed-scale", type=int, default=16)
     ap.add_argument("--weighted-scale", type=int, default=16)
     ap.add_argument("--tune-cache", default="", help="batched mode: autotuner cache file")
+    ap.add_argument("--tune-query", action="store_true", help="query mode: autotune the lanes per pair first")
     ap.add_argument("--calibrate", action="store_true",
                     help="finish with a 256 MiB read + 256 MiB write elementwise kernel (counter scale)")
     ap.add_argument("--serve-scale", type=int, default=20)

@@ -257,6 +257,16 @@ int pll_export_bp(const pll_index* idx, uint32_t* d_roots, uint32_t* d_nbrs, uin
 int pll_query(const pll_index* idx, uint64_t count, const uint32_t* d_u, const uint32_t* d_v, uint32_t* d_out,
               hipStream_t stream);
 
+/*
+ * Change the lanes per pair of later pll_query calls on `idx` (the value
+ * opts->query_lanes set at build time: 0 = automatic, else 1, 4, 8, 16, 32 or
+ * 64; the window of a pair is 4 * lanes entries of each label).  Answers do
+ * not depend on it.  Another value is PLL_EINVAL.  Not synchronised with
+ * pll_query calls other threads make on the same index.  Used by the query
+ * autotuner (paper_1906_12018_amd.autotune.tune_query).
+ */
+int pll_index_set_query_lanes(pll_index* idx, uint32_t lanes);
+
 /* Summary and counters of an index (host struct, filled synchronously). */
 int pll_index_info_get(const pll_index* idx, pll_index_info* out);
 

@@ -33,7 +33,7 @@ LABELS_IN, LABELS_OUT = 0, 1
 
 EXPORTED_SYMBOLS = (
     "pll_build_labels", "pll_build_labels_directed", "pll_build_labels_weighted", "pll_query", "pll_index_info_get", "pll_export_labels",
-    "pll_export_labels_side", "pll_export_bp",
+    "pll_export_labels_side", "pll_export_bp", "pll_index_set_query_lanes",
     "pll_build_labels_batched", "pll_index_free", "pll_status_string",
     "pll_server_create", "pll_server_add_index", "pll_server_index", "pll_server_submit", "pll_server_poll",
     "pll_server_replay", "pll_server_destroy",
@@ -187,6 +187,8 @@ def load_library(path: str = LIB_PATH):
     lib.pll_export_labels_side.restype = ctypes.c_int
     lib.pll_export_bp.argtypes = [P, P, P, P, P, P, P]
     lib.pll_export_bp.restype = ctypes.c_int
+    lib.pll_index_set_query_lanes.argtypes = [P, U32]
+    lib.pll_index_set_query_lanes.restype = ctypes.c_int
     lib.pll_build_labels_directed.argtypes = [U32, U64, P, P, P, ctypes.POINTER(BuildOpts), P, ctypes.POINTER(P)]
     lib.pll_build_labels_directed.restype = ctypes.c_int
     lib.pll_build_labels_weighted.argtypes = [U32, U64, P, P, P, P, ctypes.POINTER(BuildOpts), P, ctypes.POINTER(P)]
@@ -309,6 +311,12 @@ class Index:
         if rc:
             raise PllError(rc, "pll_export_labels_side")
         return ExportedLabels(off, hubs[:total], dists[:total])
+
+    def set_query_lanes(self, lanes: int) -> None:
+        """Lanes per pair of later queries (0 = automatic, 1, 4, ..., 64)."""
+        rc = load_library().pll_index_set_query_lanes(self.handle, lanes)
+        if rc:
+            raise PllError(rc, "pll_index_set_query_lanes")
 
     def export_bp(self, stream=None) -> dict:
         """Bit-parallel part (vertex ids): roots [t], nbrs [t, 64] (-1 past a

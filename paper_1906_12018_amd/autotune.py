@@ -1,4 +1,5 @@
-"""Autotuner for the many-graph build (one persistent launch).
+"""Autotuners: the many-graph build (one persistent launch) and the query's
+label windows.
 
 Tunes, per workload class, the launch parameters that do not change the
 labels: the batch size b (which sets the width of the per-batch distance-table
@@ -9,6 +10,12 @@ candidate is timed on the caller's graphs through the C ABI; a candidate
 whose label totals differ from the others is rejected (labels are invariant
 under all of these, so a difference would be a bug).  Results are cached in a
 JSON file keyed by a coarse signature of the workload.
+
+For queries it tunes the lanes per pair G of an index (the merge reads
+windows of 2G entries of one label and 4G of the other): every G is timed on
+a sample of the caller's pairs, a G whose answers differ is rejected, and
+the best is set on the index and cached per index class (vertex count and
+mean label length, bucketed).
 """
 from __future__ import annotations
 
@@ -20,6 +27,8 @@ import time
 import torch
 
 from . import DEFAULT_BATCH, FLAG_VALIDATE, build_labels_batched
+
+QUERY_LANES = (1, 4, 8, 16, 32, 64)
 
 DEFAULT_CANDIDATES = [
     dict(batch_size=b, gang_scale=s, max_gang=16)
@@ -121,3 +130,60 @@ def build_tuned(graphs, flags: int = FLAG_VALIDATE, tune_if_missing: bool = Fals
         cfg = dict(batch_size=DEFAULT_BATCH)
     cfg.update(kw)
     return build_labels_batched(graphs, flags=flags, **cfg)
+
+
+def index_key(index) -> str:
+    """Class of an index for the query tuner: vertex count and mean label
+    length (both sides of a directed index), bucketed to powers of two."""
+    inf = index.info()
+    n = max(inf["n"], 1)
+    mean = (inf["in_entries"] + inf["out_entries"]) / (2 * n)
+    def b2(x):
+        return int(round(math.log2(max(x, 1))))
+    return f"query_n{b2(n)}_mean{b2(mean)}_bp{inf['bp_roots']}"
+
+
+def tune_query(index, u, v, candidates=QUERY_LANES, reps: int = 3, save: bool = True, verbose: bool = False):
+    """Time pll_query on the pairs (u, v) (device int32 tensors) for each lanes
+    value (median of `reps` after one warm-up), check that every value gives
+    the same answers, set the fastest on the index and return
+    {"best": lanes, "results": [...]}."""
+    out = torch.empty_like(u)
+    ref = None
+    results = []
+    for g in candidates:
+        index.set_query_lanes(g)
+        times = []
+        for rep in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            index.query(u, v, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            if rep > 0:
+                times.append(e0.elapsed_time(e1))
+        if ref is None:
+            ref = out.clone()
+        elif not torch.equal(out, ref):
+            raise RuntimeError(f"query lanes {g} gave different answers")
+        times.sort()
+        results.append(dict(lanes=g, ms=times[len(times) // 2]))
+        if verbose:
+            print(f"tune query lanes {g}: {results[-1]['ms']:.3f} ms", flush=True)
+    best = min(results, key=lambda r: r["ms"])
+    index.set_query_lanes(best["lanes"])
+    res = {"best": best["lanes"], "results": results}
+    if save:
+        cache = _load_cache()
+        cache[index_key(index)] = res
+        _save_cache(cache)
+    return res
+
+
+def apply_cached_query_lanes(index) -> bool:
+    """Set the cached best lanes of this index class, if any."""
+    ent = _load_cache().get(index_key(index))
+    if not ent:
+        return False
+    index.set_query_lanes(int(ent["best"]))
+    return True

@@ -74,6 +74,14 @@ int pll_query(const pll_index* idx, uint64_t count, const uint32_t* d_u, const u
     return pll_query_launch(idx, count, d_u, d_v, d_out, stream);
 }
 
+int pll_index_set_query_lanes(pll_index* idx, uint32_t lanes) {
+    if (!idx) return PLL_EINVAL;
+    if (!(lanes == 0 || lanes == 1 || lanes == 4 || lanes == 8 || lanes == 16 || lanes == 32 || lanes == 64))
+        return PLL_EINVAL;
+    idx->query_lanes = lanes;
+    return PLL_OK;
+}
+
 int pll_index_info_get(const pll_index* idx, pll_index_info* out) {
     if (!idx || !out) return PLL_EINVAL;
     *out = idx->info;

@@ -22,3 +22,19 @@ def test_cache_roundtrip(tmp_path, monkeypatch):
     cache = {autotune.workload_key(gs): {"best": {"batch_size": 512, "gang_scale": 100, "max_gang": 8}}}
     autotune._save_cache(cache)
     assert autotune.cached_config(gs) == {"batch_size": 512, "gang_scale": 100, "max_gang": 8}
+
+
+class _FakeIndex:
+    def __init__(self, n, entries, bp=0):
+        self._i = {"n": n, "in_entries": entries, "out_entries": entries, "bp_roots": bp}
+
+    def info(self):
+        return self._i
+
+
+def test_index_key_buckets():
+    a = autotune.index_key(_FakeIndex(65536, 5_000_000))
+    b = autotune.index_key(_FakeIndex(60000, 4_700_000))
+    c = autotune.index_key(_FakeIndex(1 << 20, 252_000_000))
+    d = autotune.index_key(_FakeIndex(65536, 5_000_000, bp=16))
+    assert a == b and a != c and a != d

@@ -3,12 +3,13 @@ setting: the scalar merge (1 lane) and the windowed group merge (4..64 lanes,
 windows of 4 entries per lane).  Distances are integers: compared exactly
 with the oracle's query on the same labels."""
 import numpy as np
+import torch
 import pytest
 
 import oracle
 import paper_1906_12018_amd as pll
 import synth
-from gpu_util import build, gpu_query, to_dev
+from gpu_util import DEV, build, gpu_query, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -70,4 +71,24 @@ def test_query_lanes_rejects_other_values():
     g = synth.ba_graph(100, 2, 1)
     with pytest.raises(pll.PllError) as e:
         build(g, synth.degree_order(g), query_lanes=3)
+    assert e.value.status == pll.PLL_EINVAL
+
+
+def test_query_lane_autotuner_keeps_answers():
+    """The query autotuner times every lanes value on the caller's pairs,
+    refuses a value whose answers differ and sets the fastest; the answers
+    afterwards are still the oracle's."""
+    from paper_1906_12018_amd import autotune
+    g = synth.rmat_graph(12, 16, seed=1)
+    order = synth.degree_order(g)
+    want = oracle.pll_labels(g, order)
+    idx = build(g, order)
+    u, v = synth.query_pairs(g.n, 20000, seed=9)
+    du = torch.from_numpy(u.view(np.int32)).to(DEV)
+    dv = torch.from_numpy(v.view(np.int32)).to(DEV)
+    res = autotune.tune_query(idx, du, dv, reps=1, save=False)
+    assert res["best"] in autotune.QUERY_LANES and len(res["results"]) == len(autotune.QUERY_LANES)
+    assert np.array_equal(gpu_query(idx, u, v), oracle.query(want, u, v))
+    with pytest.raises(pll.PllError) as e:
+        idx.set_query_lanes(3)
     assert e.value.status == pll.PLL_EINVAL

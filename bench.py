@@ -326,7 +326,7 @@ def directed_mode(args):
     info = prof[-1]
     total = info["total_entries"]
     check_ms = float(np.mean([i["phase_ms"]["check"] for i in prof]))
-    check_bytes = (4 * info["check_entries_read"] + 64 * info["check_table_reads"] + 4 * info["accepted"]
+    check_bytes = (4 * info["check_entries_read"] + 16 * info["check_table_reads"] + 4 * info["accepted"]
                    + 4 * info["check_push_edges"])
     check_gbs = check_bytes / (check_ms / 1e3) / 1e9
     res = {"mode": "directed", "workload": f"directed rmat{args.directed_scale} (arcs not symmetrised) build + "
@@ -406,7 +406,7 @@ def weighted_mode(args):
     pidx.free()
     total = info["total_entries"]
     check_ms = info["phase_ms"]["check"]
-    check_bytes = 4 * info["check_entries_read"] + 64 * info["check_table_reads"] + 4 * info["accepted"]
+    check_bytes = 4 * info["check_entries_read"] + 16 * info["check_table_reads"] + 4 * info["accepted"]
     res = {"mode": "weighted", "workload": f"rmat{args.weighted_scale} with weights uniform 1..7 build + "
                                           f"{pairs} query pairs",
            "n": g.n, "undirected_edges": g.num_edges, "batch_size": args.batch_size, "steps": args.steps,
@@ -724,12 +724,12 @@ def main():
 
     # roofline, dominant kernel: the fused pruning check and push
     # (k_check_push), bytes per the kernel's traffic model (label entries and
-    # 64-byte table segments the scans read, entries appended, CSR entries the
+    # 16-byte table quarters the scans read, entries appended, CSR entries the
     # fused pushes read; the message atomics are not counted), time from HIP
     # events on the build stream
     check_ms = np.mean([i["phase_ms"]["check"] for i in prof])
     check_launches = info["phase_launches"]["check"]
-    check_bytes = (4 * info["check_entries_read"] + 64 * info["check_table_reads"]
+    check_bytes = (4 * info["check_entries_read"] + 16 * info["check_table_reads"]
                    + 4 * info["accepted"] + 4 * info["check_push_edges"])
     check_gbs = check_bytes / (check_ms / 1e3) / 1e9
     cons = consumed_for(idx, g, order, u, v)

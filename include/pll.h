@@ -119,7 +119,7 @@ typedef struct {
     uint32_t gang;            /* batched build: workgroups that built this graph (1 otherwise) */
     double build_ms;          /* host wall time of pll_build_labels */
     uint64_t check_entries_read;  /* label entries the pruning checks read */
-    uint64_t check_table_reads;   /* 64-byte distance-table segments the pruning checks read */
+    uint64_t check_table_reads;   /* 16-byte distance-table quarters the pruning checks read */
     uint64_t check_cost_pos;      /* sum over distance checks that added an entry of |L(v)| at the check */
     uint64_t check_cost_neg;      /* the same over checks that pruned (Section 4.3, the quantities of Table 3) */
     double phase_ms[PLL_NUM_PHASES];         /* device time per phase (PLL_FLAG_PROFILE, else 0) */

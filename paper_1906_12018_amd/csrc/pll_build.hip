@@ -1114,7 +1114,7 @@ int init_state(DevAllocs& M, BuildArgs& A, uint32_t n, uint64_t nnz, uint32_t W,
     A.C = M.get<uint64_t>((size_t)n * W);
     A.msgs = M.get<uint64_t>((size_t)n * W);
     A.T = M.get<uint8_t>((size_t)n * A.bstride);
-    A.rowmask = M.get<uint32_t>(n);
+    A.rowmask = M.get<uint64_t>(n);
     A.Tchk = A.T;
     A.rmchk = A.rowmask;
     A.hq_seg = 2 * (nnz / kHeavy) + 64;
@@ -1134,7 +1134,7 @@ int init_state(DevAllocs& M, BuildArgs& A, uint32_t n, uint64_t nnz, uint32_t W,
     TRY_HIP(hipMemsetAsync(A.C, 0, sizeof(uint64_t) * n * W, s));
     TRY_HIP(hipMemsetAsync(A.msgs, 0, sizeof(uint64_t) * n * W, s));
     TRY_HIP(hipMemsetAsync(A.T, 0xFF, (size_t)n * A.bstride, s));
-    TRY_HIP(hipMemsetAsync(A.rowmask, 0, sizeof(uint32_t) * n, s));
+    TRY_HIP(hipMemsetAsync(A.rowmask, 0, sizeof(uint64_t) * n, s));
     TRY_HIP(hipMemsetAsync(A.recv_stamp, 0, sizeof(uint32_t) * n, s));
     TRY_HIP(hipMemsetAsync(A.touch_stamp, 0, sizeof(uint32_t) * n, s));
     return PLL_OK;
@@ -1384,6 +1384,10 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
                 P.span(PLL_PHASE_PUSH, r2, P.mark(), 1);
             }
             next_est = (uint64_t)sum_recv(h, nr.rout) + 1024ull * nh;
+            if (next_est == 0) {  // nobody receives in round j+1: it would accept nothing
+                ++rounds;
+                break;
+            }
         }
         hipEvent_t e1 = P.mark();
         dispatch_batch_end(blocks_for_waves(sum_touched(h)), s, A, ib, bs, recheck);

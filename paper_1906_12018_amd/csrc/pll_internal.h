@@ -38,7 +38,7 @@ enum {
     PLL_ST_ACC = 1,      // entries accepted by round checks
     PLL_ST_EDGES = 2,    // CSR entries read by push
     PLL_ST_READ = 3,     // label entries read by pruning scans
-    PLL_ST_TABLE = 4,    // 64-byte table segments read by pruning scans
+    PLL_ST_TABLE = 4,    // 16-byte table quarters read by pruning scans
     PLL_ST_GROW = 5,     // label lists moved to a larger block
     PLL_ST_RECHECK = 6,  // entries dropped by the recheck
     PLL_ST_COST_POS = 7, // sum of |L(v)| over checks that added an entry
@@ -90,12 +90,12 @@ struct BuildArgs {
                      // check-and-push rounds alternate two buffers and filter in the check)
     // per-batch distance table: T[h * bstride + k] = d(u_k, h) for (h, d) in L(u_k)
     uint8_t* T;
-    uint32_t* rowmask;  // bit w set when row h of T has an entry in word w
+    uint64_t* rowmask;  // bit q set when row h of T has an entry for a batch vertex u_k with k / 16 = q
     // table the pruning checks read: T itself for an undirected graph; for a
     // directed one, the other side's table (a forward check of candidate u_k
     // at v scans L_in(v) against the table of L_out(u_k), and vice versa)
     const uint8_t* Tchk;
-    const uint32_t* rmchk;
+    const uint64_t* rmchk;
     // weighted graphs: D[v * bstride + k] = the smallest candidate distance
     // of u_k that reached v in this batch (255: none); it plays the part of
     // C(v), since a candidate may come back shorter in a later round

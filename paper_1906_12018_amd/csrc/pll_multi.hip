@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(kMultiBlock) k_multi_build(const GraphJob* __r
                 // the counter of round j+1 was last read after round j-1
                 if (r == 0 && tid == 0) gc->round_acc[(j + 1) & 1u] = 0;
                 const unsigned long long acc0 = st.acc;
-                pll::phase_check<WM>(A, X, ib, bs, j, p, relaxed, st);
+                pll::phase_check<WM, false, false, true>(A, X, ib, bs, j, p, relaxed, st);
                 if (lane == 0 && st.acc != acc0) atomicAdd(&gc->round_acc[j & 1u], (uint32_t)(st.acc - acc0));
                 if (gang_sync(gc, G, k, ctr, spin_limit, &s_flag)) { failed = true; break; }
                 if (load_agent(&gc->round_acc[j & 1u]) == 0) break;
@@ -512,7 +512,7 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
         o.lcap = take(zb, 4 * n);
         o.C = take(zb, 8 * n * W);
         o.msgs = take(zb, 8 * n * W);
-        o.rowmask = take(zb, 4 * n);
+        o.rowmask = take(zb, 8 * n);
         o.recv_stamp = take(zb, 4 * n);
         o.touch_stamp = take(zb, 4 * (n + 1));
         o.T = take(tb, n * bstride);
@@ -601,7 +601,7 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
         A.lcap = (uint32_t*)(zp + o.lcap);
         A.C = (uint64_t*)(zp + o.C);
         A.msgs = (uint64_t*)(zp + o.msgs);
-        A.rowmask = (uint32_t*)(zp + o.rowmask);
+        A.rowmask = (uint64_t*)(zp + o.rowmask);
         A.recv_stamp = (uint32_t*)(zp + o.recv_stamp);
         A.touch_stamp = (uint32_t*)(zp + o.touch_stamp);
         A.T = (uint8_t*)(tp + o.T);

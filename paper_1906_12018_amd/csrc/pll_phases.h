@@ -56,6 +56,28 @@ __device__ inline uint64_t le_mask64(const uint8_t* p, uint32_t tt) {
     return m;
 }
 
+// le_mask64 over the 16-byte quarters selected by `need` (bit i: bytes
+// 16i .. 16i+15); the other quarters are neither loaded nor matched.
+__device__ inline uint64_t le_mask64_q(const uint8_t* p, uint32_t tt, uint32_t need) {
+    const uint4* q = reinterpret_cast<const uint4*>(p);
+    uint64_t m = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if ((need >> i) & 1u) {
+            const uint4 v = q[i];
+            const uint32_t b = le4(v.x, tt) | (le4(v.y, tt) << 4) | (le4(v.z, tt) << 8) | (le4(v.w, tt) << 12);
+            m |= (uint64_t)b << (16 * i);
+        }
+    }
+    return m;
+}
+
+// Bit i set when quarter i (candidates 16i .. 16i+15) of a word has a bit.
+__device__ inline uint32_t quarters(uint64_t x) {
+    return (uint32_t)((x & 0xFFFFull) != 0) | ((uint32_t)((x & 0xFFFF0000ull) != 0) << 1) |
+           ((uint32_t)((x & 0xFFFF00000000ull) != 0) << 2) | ((uint32_t)((x >> 48) != 0) << 3);
+}
+
 // OR over the 64 lanes (DPP wave reduction); the result is wave-uniform.
 __device__ inline uint64_t wave_or64_u(uint64_t x) {
     const unsigned lo = __reduce_or_sync(~0ull, (unsigned)x);
@@ -71,8 +93,13 @@ __device__ inline uint64_t wave_or64_u(uint64_t x) {
 // With `relaxed`, entries whose hub is in the current batch are skipped.
 // The table loads of all candidate words of a chunk are independent; lanes
 // are OR-reduced every 4 chunks (and at the end), which is also where the
-// scan stops once every candidate is pruned.
-template <int WM>
+// scan stops once every candidate is pruned.  With QGATE only the 16-byte
+// quarters of a table segment that both hold entries (row mask) and have
+// live candidates are loaded; without it a segment is loaded whole when any
+// of its quarters qualifies (fewer, wider loads: measured faster on the large
+// single-graph builds, while the many-graph kernel, whose small graphs leave
+// table rows sparse, gains from the gating).
+template <int WM, bool QGATE = false>
 __device__ inline uint64_t prune_scan(const BuildArgs& A, uint64_t off, uint32_t len, uint32_t j, uint64_t cw,
                                       bool relaxed, uint32_t ib, PhaseStats& st) {
     const uint32_t lane = lane_id();
@@ -89,16 +116,22 @@ __device__ inline uint64_t prune_scan(const BuildArgs& A, uint64_t off, uint32_t
         const uint32_t h = ent >> 8, d = ent & 255u;
         ok = ok && d < j;
         if (relaxed) ok = ok && h < ib;
-        const uint32_t rm = ok ? A.rmchk[h] : 0u;
+        const uint64_t rm = ok ? A.rmchk[h] : 0ull;
         const uint32_t tt = ok ? (j - d) * 0x01010101u : 0u;
         const uint8_t* row = A.Tchk + (size_t)h * A.bstride;
         const uint64_t live_lane = cw & ~pw;
 #pragma unroll
         for (int w = 0; w < WM; ++w) {
             const uint64_t live = readlane64(live_lane, w);
-            if (live != 0 && ((rm >> w) & 1u)) {
+            if (QGATE) {
+                const uint32_t need = (uint32_t)(rm >> (4 * w)) & quarters(live);
+                if (need & 15u) {
+                    accm[w] |= le_mask64_q(row + 64u * w, tt, need) & live;
+                    st.table += __builtin_popcount(need & 15u);
+                }
+            } else if (live != 0 && ((rm >> (4 * w)) & 15u)) {
                 accm[w] |= le_mask64(row + 64u * w, tt) & live;
-                ++st.table;
+                st.table += 4;
             }
         }
         if ((chunk & 3u) == 3u || base + 64 >= len) {
@@ -217,18 +250,18 @@ __device__ inline void phase_batch_init(const BuildArgs& A, const Exec& X, uint3
         }
         const uint64_t off = wave_reserve(A, X, u, A.loff[u], len, 1);
         if (off == ~0ull) continue;
-        const uint32_t kw = 1u << (k >> 6);
+        const unsigned long long kq = 1ull << (k >> 4);
         if (lane == 0) {
             A.arena[off + len] = pll_pack(u, 0);
             A.llen[u] = len + 1;
             A.T[(size_t)u * A.bstride + k] = 0;
-            atomicOr(&A.rowmask[u], kw);
+            atomicOr((unsigned long long*)&A.rowmask[u], kq);
         }
         for (uint32_t i = lane; i < len; i += 64) {
             const uint32_t e = A.arena[off + i];
             const uint32_t h = e >> 8;
             A.T[(size_t)h * A.bstride + k] = (uint8_t)(e & 255u);
-            atomicOr(&A.rowmask[h], kw);
+            atomicOr((unsigned long long*)&A.rowmask[h], kq);
         }
         if (lane == 0) A.act_v[0][k] = u;
         if (lane == 0 && A.act_rng[0]) A.act_rng[0][k] = make_uint2(len, 1u);  // the self entry
@@ -405,7 +438,7 @@ struct NextRound {
     uint32_t rstamp, bstamp;
 };
 
-template <int WM, bool BP = false, bool FUSE = false>
+template <int WM, bool BP = false, bool FUSE = false, bool QGATE = false>
 __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t bs, uint32_t j, uint32_t p,
                                    bool relaxed, PhaseStats& st, const NextRound* nr = nullptr) {
     const uint32_t lane = lane_id();
@@ -441,7 +474,7 @@ __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t i
             st.bp += __builtin_popcountll(lane < W ? bpp : 0ull);
             scan &= ~bpp;
         }
-        const uint64_t pw = prune_scan<WM>(A, off, len, j, scan, relaxed, ib, st);
+        const uint64_t pw = prune_scan<WM, QGATE>(A, off, len, j, scan, relaxed, ib, st);
         const uint64_t acc = lane < W ? (scan & ~pw) : 0ull;
         const uint32_t cnt = (uint32_t)__builtin_popcountll(acc);
         const uint32_t pos = wave_excl_scan32(cnt);
@@ -472,7 +505,7 @@ __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t i
                 A.arena[off + len + pwos + __builtin_popcountll(aw & lt)] = pll_pack(ib + k, j);
                 if (in_batch) {
                     A.T[(size_t)(ib + k) * A.bstride + (v - ib)] = (uint8_t)j;
-                    atomicOr(&A.rowmask[ib + k], 1u << ((v - ib) >> 6));
+                    atomicOr((unsigned long long*)&A.rowmask[ib + k], 1ull << ((v - ib) >> 4));
                 }
             }
         }
@@ -650,16 +683,16 @@ __device__ inline uint64_t prune_scan_w(const BuildArgs& A, uint64_t off, uint32
         st.read += ok;
         const uint32_t ent = ok ? A.arena[off + idx] : 0u;
         const uint32_t h = ent >> 8;
-        const uint32_t rm = ok ? A.rmchk[h] : 0u;
+        const uint64_t rm = ok ? A.rmchk[h] : 0ull;
         const uint32_t dd = (ent & 255u) * 0x01010101u;
         const uint8_t* row = A.Tchk + (size_t)h * A.bstride;
         const uint64_t live_lane = cw & ~pw;
 #pragma unroll
         for (int w = 0; w < WM; ++w) {
             const uint64_t live = readlane64(live_lane, w);
-            if (live != 0 && ((rm >> w) & 1u)) {
+            if (live != 0 && ((rm >> (4 * w)) & 15u)) {
                 accm[w] |= sum_le_mask64(row + 64u * w, dd, s_thr + 4 * w) & live;
-                ++st.table;
+                st.table += 4;
             }
         }
         if ((chunk & 3u) == 3u || base + 64 >= len) {
@@ -833,7 +866,7 @@ __device__ inline void phase_check_w(const BuildArgs& A, const Exec& X, uint32_t
                         A.arena[off + len + pwos + __builtin_popcountll(aw & lt)] = pll_pack(ib + k, dk);
                         if (in_batch) {
                             A.T[(size_t)(ib + k) * A.bstride + (v - ib)] = (uint8_t)dk;
-                            atomicOr(&A.rowmask[ib + k], 1u << ((v - ib) >> 6));
+                            atomicOr((unsigned long long*)&A.rowmask[ib + k], 1ull << ((v - ib) >> 4));
                         }
                     }
                 }

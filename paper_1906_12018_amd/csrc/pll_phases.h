@@ -384,6 +384,34 @@ __device__ inline uint64_t bp_prune_words(const BuildArgs& A, uint32_t v, uint32
     }
     const uint64_t roots_v = ballot64(lane < t && dv != PLL_INF8);
     uint64_t out = 0;
+    // few candidates: lanes over the BP roots, one candidate at a time (its
+    // data of all roots is one coalesced load); otherwise lanes over the
+    // candidates of a word, one root at a time
+    const uint32_t ncand = wave_sum32(lane < WM ? (uint32_t)__builtin_popcountll(mine) : 0u);
+    const uint32_t nwords = (uint32_t)__builtin_popcountll(ballot64(lane < WM && mine != 0));
+    if (ncand < nwords * (uint32_t)__builtin_popcountll(roots_v)) {
+#pragma unroll
+        for (int w = 0; w < WM; ++w) {
+            uint64_t m = readlane64(mine, w);
+            while (m) {
+                const uint32_t bit = (uint32_t)__builtin_ctzll(m);
+                m &= m - 1;
+                const size_t at = (size_t)(ib + 64u * w + bit) * t + lane;
+                uint32_t td = 0xFFFFFFFFu;
+                if (lane < t && dv != PLL_INF8) {
+                    const uint32_t du = A.bp_dist[at];
+                    if (du != PLL_INF8) {
+                        const ulonglong2 su = A.bp_sets[at];
+                        td = du + dv;
+                        if (su.x & sv.x) td -= 2;
+                        else if ((su.x & sv.y) | (su.y & sv.x)) td -= 1;
+                    }
+                }
+                if (wave_min32(td) <= j && lane == (uint32_t)w) out |= 1ull << bit;
+            }
+        }
+        return out;
+    }
 #pragma unroll
     for (int w = 0; w < WM; ++w) {
         const uint64_t m = readlane64(mine, w);

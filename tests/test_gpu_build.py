@@ -252,3 +252,22 @@ def test_many_batches_large_rounds(n, m, seed):
     check_counters(idx, g, order, 1024, want)
     u, v = synth.query_pairs(g.n, 20000, seed=3)
     assert np.array_equal(gpu_query(idx, u, v), oracle.query(want, u, v))
+
+
+def test_size_limits_rejected_before_any_work():
+    """n at the 24-bit hub-rank limit and nnz beyond 2^33 are PLL_EINVAL
+    (checked on the host before anything is read)."""
+    import ctypes
+    g = synth.ba_graph(50, 2, 1)
+    rp, cl, od = to_dev(g, synth.degree_order(g))
+    lib = pll.load_library()
+    o = pll._opts(1024, 0, 0, 0)
+    h = ctypes.c_void_p()
+    for n, nnz in (((1 << 24), g.nnz), (g.n, 0xFFFFFFFF * 2 + 1)):
+        rc = lib.pll_build_labels(n, nnz, rp.data_ptr(), cl.data_ptr(), od.data_ptr(), ctypes.byref(o), None,
+                                  ctypes.byref(h))
+        assert rc == pll.PLL_EINVAL and not h.value
+    for bad in (dict(batch_size=1025), dict(query_lanes=3)):
+        with pytest.raises(pll.PllError) as e:
+            build(g, synth.degree_order(g), **bad)
+        assert e.value.status == pll.PLL_EINVAL

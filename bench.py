@@ -243,6 +243,24 @@ def _pool_query(args):
     return oracle.query(_POOL_LABELS, u, v)
 
 
+def host_info():
+    """CPU model and core counts of the host the CPU baseline ran on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
 def cpu_baseline(g, order, total_entries, u, v):
     """The oracle's sequential PLL (Algorithm 1) on the host, one thread, on
     the whole graph (the R-MAT scale-16 build takes a few seconds); then the
@@ -266,7 +284,7 @@ def cpu_baseline(g, order, total_entries, u, v):
         t0 = time.perf_counter()
         pool.map(_pool_query, chunks)
         qn = time.perf_counter() - t0
-    return {"value": lab.total / dt, "unit": "label entries/s", "cores": 1, "kind": "oracle",
+    return {"value": lab.total / dt, "unit": "label entries/s", "cores": 1, "kind": "oracle", "host": host_info(),
             "sample": f"full sequential PLL build of the same graph ({g.n} vertices, {lab.total} entries), "
                       f"1 run, {dt:.2f} s", "seconds": dt,
             "pll_check_cost": {"pos": lab.counters["cost_pos"], "neg": lab.counters["cost_neg"]},

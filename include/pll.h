@@ -373,7 +373,9 @@ int pll_server_index(pll_server* server, uint32_t index_id, pll_index** idx);
 int pll_server_submit(pll_server* server, const pll_request* req, uint64_t* id);
 /* Up to `max` finished results; with `wait`, block until at least one is ready or nothing is outstanding. */
 int pll_server_poll(pll_server* server, pll_result* out, uint32_t max, uint32_t* got, int wait);
-/* Open-loop replay: submit reqs[i] at reqs[i].at seconds after the call, wait for all, results in request order. */
+/* Open-loop replay: submit reqs[i] at reqs[i].at seconds after the call, wait for all, results in request order.
+   Requests go in array order (sorted by `at` is the intended use); every request already due when the
+   replay thread wakes is submitted under one lock with one wake-up of the scheduler. */
 int pll_server_replay(pll_server* server, uint64_t count, const pll_request* reqs, pll_result* results);
 /* Finish in-flight work, free the server and the indexes it owns. */
 void pll_server_destroy(pll_server* server);

@@ -507,7 +507,7 @@ int pll_server_replay(pll_server* s, uint64_t count, const pll_request* reqs, pl
     if (!s || (count && (!reqs || !results))) return PLL_EINVAL;
     std::vector<uint64_t> ids(count, 0);
     const double start = s->now();
-    for (uint64_t i = 0; i < count; ++i) {
+    for (uint64_t i = 0; i < count;) {
         const double due = start + reqs[i].at;
         for (;;) {  // open loop: wait for the arrival time, never for earlier requests
             const double t = s->now();
@@ -515,10 +515,16 @@ int pll_server_replay(pll_server* s, uint64_t count, const pll_request* reqs, pl
             if (due - t > 2e-4)
                 std::this_thread::sleep_for(std::chrono::duration<double>(due - t - 1e-4));
         }
-        int rc;
+        // every request already due goes in under one lock and one wake-up,
+        // so a burst reaches the scheduler whole instead of one by one
+        int rc = PLL_OK;
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            rc = submit_locked(s, &reqs[i], due, &ids[i]);
+            const double t = s->now();
+            do {
+                rc = submit_locked(s, &reqs[i], start + reqs[i].at, &ids[i]);
+                ++i;
+            } while (rc == PLL_OK && i < count && start + reqs[i].at <= t);
         }
         s->cv.notify_all();
         if (rc != PLL_OK) return rc;

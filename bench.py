@@ -526,14 +526,16 @@ def bp_mode(args):
 
 
 def serve_mode(args):
-    """Serving workload: R-MAT scale-20 index resident; open-loop Poisson
-    arrivals (stream 4) of query requests with sizes log-uniform in [1, 65536]
-    pairs, a fraction of arrivals being labeling jobs for Barabasi-Albert
-    graphs (n log-uniform in [1000, 50000], m in {2..8}) admitted by free
-    memory.  Saturation = the request rate of one burst of the whole mix; the
-    load levels offer fractions of it.  Latency = completion - arrival.  Each
-    level runs on a fresh server (the indexes its labeling jobs built are
-    dropped with it)."""
+    """Serving workload: R-MAT scale-20 index resident; query requests with
+    sizes log-uniform in [1, 65536] pairs and labeling jobs for
+    Barabasi-Albert graphs (n log-uniform in [1000, 50000], m in {2..8})
+    admitted by free memory.  Two saturation bursts (every query request at
+    t = 0 alone; every labeling job at t = 0 alone) give each stream's
+    capacity.  A load level `f` then offers two independent open-loop Poisson
+    streams at the same time, queries at f x the query capacity (stream 4)
+    and labeling jobs at f x the labeling capacity (stream 7), over the span
+    of the query stream.  Latency = completion - arrival.  Each run uses a
+    fresh server (the indexes its labeling jobs built are dropped with it)."""
     # the server runs slots + 1 streams besides torch's; with fewer hardware
     # queues than that, streams share a queue and a query batch can wait
     # behind a long labeling launch (read by HIP when it starts)
@@ -553,14 +555,13 @@ def serve_mode(args):
     N = args.serve_requests
     x = synth.splitmix64(4, 0, 4 * N)
     sizes = np.maximum(1, np.round(np.exp(synth.uniform01(x[0::4]) * np.log(65536)))).astype(np.int64)
-    is_build = synth.uniform01(x[1::4]) < args.serve_build_frac
     pool = 1 << 24
     pu, pv = synth.query_pairs(g.n, pool, seed=5)
     pout = np.zeros(pool, dtype=np.uint32)
     starts = synth.bounded(x[2::4], pool - 65536).astype(np.int64)
-    # labeling jobs (host CSR), generated once and reused by every load level
-    nb = int(is_build.sum())
-    bx = synth.splitmix64(6, 0, 2 * max(nb, 1))
+    # labeling jobs (host CSR), generated once; a level draws them in order
+    nb = args.serve_jobs
+    bx = synth.splitmix64(6, 0, 2 * nb)
     lo, hi = np.log(1000), np.log(50000)
     jobs = []
     for i in range(nb):
@@ -568,65 +569,75 @@ def serve_mode(args):
         m = 2 + int(synth.bounded(bx[2 * i + 1:2 * i + 2], 7)[0])
         bg = synth.ba_graph(n, m, 5000 + i)
         jobs.append((bg.row_ptr, bg.col, synth.degree_order(bg)))
-    pairs = int(sizes[~is_build].sum())
+    pairs = int(sizes.sum())
 
-    def run(at, with_jobs=True):
+    def run(q_at, j_at):
+        """Replay queries arriving at q_at (None: none) and jobs[:len(j_at)] at j_at."""
         srv = pll.Server(slots=args.serve_slots)
         iid = srv.add_index(idx, take_ownership=False)
-        reqs, bi = [], 0
-        for i in range(N):
-            if is_build[i]:
-                rp_, cl_, od_ = jobs[bi]
-                bi += 1
-                if with_jobs:
-                    reqs.append(pll.Server.build_request(rp_, cl_, od_, at=at[i]))
-            else:
+        reqs = []
+        if q_at is not None:
+            for i in range(N):
                 a, c = int(starts[i]), int(sizes[i])
-                reqs.append(pll.Server.query_request(iid, pu[a:a + c], pv[a:a + c], pout[a:a + c], at=at[i]))
+                reqs.append(pll.Server.query_request(iid, pu[a:a + c], pv[a:a + c], pout[a:a + c], at=q_at[i]))
+        for i, t in enumerate(j_at):
+            rp_, cl_, od_ = jobs[i]
+            reqs.append(pll.Server.build_request(rp_, cl_, od_, at=t))
+        reqs.sort(key=lambda r: r[0].at)
         res = srv.replay(reqs)
         srv.close()
-        wall = max(r["t_done"] for r in res) - min(r["t_arrival"] for r in res)
-        return res, wall
+        return res
 
-    def summarize(res, wall):
+    def span(rs):
+        return max(r["t_done"] for r in rs) - min(r["t_arrival"] for r in rs)
+
+    def summarize(res):
         q = [r for r in res if r["kind"] == pll.REQ_QUERY]
         b = [r for r in res if r["kind"] == pll.REQ_BUILD]
-        lat = np.array([r["t_done"] - r["t_arrival"] for r in q]) * 1e3
-        qspan = max(r["t_done"] for r in q) - min(r["t_arrival"] for r in q)
-        out = {"query_requests": len(q), "pairs": pairs, "wall_s": wall, "query_span_s": qspan,
-               "pairs_per_s": pairs / qspan, "query_requests_per_s": len(q) / qspan,
-               "p50_ms": float(np.percentile(lat, 50)),
-               "p99_ms": float(np.percentile(lat, 99)),
-               "mean_requests_per_batch": float(np.mean([r["batch_requests"] for r in q if r["batch_requests"]])),
-               "query_errors": int(sum(r["status"] != 0 for r in q))}
+        out = {}
+        if q:
+            lat = np.array([r["t_done"] - r["t_arrival"] for r in q]) * 1e3
+            qspan = span(q)
+            out.update({"query_requests": len(q), "pairs": pairs, "query_span_s": qspan,
+                        "pairs_per_s": pairs / qspan, "query_requests_per_s": len(q) / qspan,
+                        "p50_ms": float(np.percentile(lat, 50)),
+                        "p99_ms": float(np.percentile(lat, 99)),
+                        "mean_requests_per_batch": float(np.mean([r["batch_requests"] for r in q
+                                                                  if r["batch_requests"]])),
+                        "query_errors": int(sum(r["status"] != 0 for r in q))})
         if b:
             bl = np.array([r["t_done"] - r["t_arrival"] for r in b]) * 1e3
-            out.update({"labeling_jobs": len(b), "labeling_jobs_per_s": len(b) / wall,
+            out.update({"labeling_jobs": len(b), "labeling_span_s": span(b),
+                        "labeling_jobs_per_s": len(b) / span(b),
                         "labeling_p50_ms": float(np.percentile(bl, 50)),
                         "labeling_p99_ms": float(np.percentile(bl, 99)),
                         "labeling_errors": int(sum(r["status"] != 0 for r in b))})
         return out
 
-    # saturation of the query stream: every query request at t = 0, no jobs
-    res, _ = run(np.zeros(N), with_jobs=False)
-    qwall = max(r["t_done"] for r in res) - min(r["t_arrival"] for r in res)
-    sat = len(res) / qwall
-    levels = {"queries_only_burst": summarize(res, qwall)}
+    # capacity of each stream alone: all of its requests at t = 0
+    res = run(np.zeros(N), [])
+    sat_q = len(res) / span(res)
+    levels = {"queries_only_burst": summarize(res)}
+    res = run(None, np.zeros(nb))
+    sat_j = len(res) / span(res)
+    levels["labeling_only_burst"] = summarize(res)
     for frac in args.serve_loads:
-        rate = frac * sat  # offered rate of query requests; labeling jobs ride on the same arrival process
-        gaps = -np.log(1.0 - synth.uniform01(synth.splitmix64(4, 4 * N, N))) / (rate / (1.0 - args.serve_build_frac))
-        at = np.cumsum(gaps) - gaps[0]
-        res, wall = run(at)
+        gq = -np.log(1.0 - synth.uniform01(synth.splitmix64(4, 4 * N, N))) / (frac * sat_q)
+        q_at = np.cumsum(gq) - gq[0]
+        gj = -np.log(1.0 - synth.uniform01(synth.splitmix64(7, 0, nb))) / (frac * sat_j)
+        j_at = np.cumsum(gj)
+        j_at = j_at[j_at <= q_at[-1]]
         key = f"{int(round(frac * 100))}%"
-        levels[key] = summarize(res, wall)
-        levels[key]["offered_requests_per_s"] = rate
+        levels[key] = summarize(run(q_at, j_at))
+        levels[key]["offered_query_requests_per_s"] = frac * sat_q
+        levels[key]["offered_labeling_jobs_per_s"] = frac * sat_j
     info = idx.info()
     idx.free()
-    line = {"mode": "serve", "workload": f"rmat{args.serve_scale} index resident; {N} requests, "
-            f"{nb} of them labeling jobs; query sizes log-uniform in [1, 65536]",
+    line = {"mode": "serve", "workload": f"rmat{args.serve_scale} index resident; {N} query requests, "
+            f"sizes log-uniform in [1, 65536]; {nb} Barabasi-Albert labeling jobs, n in [1000, 50000]",
             "index_entries": info["total_entries"], "label_bytes": info["label_bytes"],
-            "query_saturation_requests_per_s": sat, "levels": levels, "slots": args.serve_slots,
-            "data": "synthetic"}
+            "query_saturation_requests_per_s": sat_q, "labeling_saturation_jobs_per_s": sat_j,
+            "levels": levels, "slots": args.serve_slots, "data": "synthetic"}
     print(json.dumps(line), flush=True)
 
 
@@ -650,7 +661,7 @@ def main():
                     help="finish with a 256 MiB read + 256 MiB write elementwise kernel (counter scale)")
     ap.add_argument("--serve-scale", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=100000)
-    ap.add_argument("--serve-build-frac", type=float, default=0.02)
+    ap.add_argument("--serve-jobs", type=int, default=512)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 0.95])
     args = ap.parse_args()

@@ -36,6 +36,7 @@ namespace {
 constexpr int kBlock = 256;              // 4 waves
 constexpr int kWavesPerBlock = kBlock / PLL_WAVE;
 constexpr uint32_t kMaxBlocks = 4096;
+constexpr uint32_t kHotRows = 256;         // top-ranked table rows whose row masks stay all ones
 
 inline uint32_t blocks_for_waves(uint64_t waves) {
     uint64_t b = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -1134,7 +1135,9 @@ int init_state(DevAllocs& M, BuildArgs& A, uint32_t n, uint64_t nnz, uint32_t W,
     TRY_HIP(hipMemsetAsync(A.C, 0, sizeof(uint64_t) * n * W, s));
     TRY_HIP(hipMemsetAsync(A.msgs, 0, sizeof(uint64_t) * n * W, s));
     TRY_HIP(hipMemsetAsync(A.T, 0xFF, (size_t)n * A.bstride, s));
-    TRY_HIP(hipMemsetAsync(A.rowmask, 0, sizeof(uint64_t) * n, s));
+    A.hot = std::min<uint32_t>(n, kHotRows);
+    TRY_HIP(hipMemsetAsync(A.rowmask, 0xFF, sizeof(uint64_t) * A.hot, s));
+    TRY_HIP(hipMemsetAsync(A.rowmask + A.hot, 0, sizeof(uint64_t) * (n - A.hot), s));
     TRY_HIP(hipMemsetAsync(A.recv_stamp, 0, sizeof(uint32_t) * n, s));
     TRY_HIP(hipMemsetAsync(A.touch_stamp, 0, sizeof(uint32_t) * n, s));
     return PLL_OK;

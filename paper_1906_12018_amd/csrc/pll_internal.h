@@ -73,7 +73,7 @@ struct BuildArgs {
     uint32_t n;
     uint32_t W;        // words per candidate bit-vector (ceil(b / 64))
     uint32_t bstride;  // bytes per distance-table row (64 * W)
-    uint32_t pad0;
+    uint32_t hot;      // rows h < hot keep every row-mask bit set for the whole build
     const uint64_t* rrow;   // rank-space CSR row pointers [n+1]
     const uint32_t* rcol;   // rank-space CSR columns [nnz]
     const uint8_t* rw;      // weighted graphs: weight of each rank-space CSR entry (null otherwise)
@@ -90,7 +90,11 @@ struct BuildArgs {
                      // check-and-push rounds alternate two buffers and filter in the check)
     // per-batch distance table: T[h * bstride + k] = d(u_k, h) for (h, d) in L(u_k)
     uint8_t* T;
-    uint64_t* rowmask;  // bit q set when row h of T has an entry for a batch vertex u_k with k / 16 = q
+    // bit q set when row h of T has an entry for a batch vertex u_k with k / 16 = q; the
+    // check skips row segments whose bits are clear.  The top-ranked rows h < hot hold
+    // entries for nearly every batch vertex, so their masks stay all ones instead of
+    // taking one contended atomic per label entry (a set bit only costs a segment load)
+    uint64_t* rowmask;
     // table the pruning checks read: T itself for an undirected graph; for a
     // directed one, the other side's table (a forward check of candidate u_k
     // at v scans L_in(v) against the table of L_out(u_k), and vice versa)

@@ -117,7 +117,9 @@ __device__ inline uint64_t prune_scan(const BuildArgs& A, uint64_t off, uint32_t
         ok = ok && d < j;
         if (relaxed) ok = ok && h < ib;
         const uint64_t rm = ok ? A.rmchk[h] : 0ull;
-        const uint32_t tt = ok ? (j - d) * 0x01010101u : 0u;
+        // threshold at most 254, the largest finite table byte: at round 255
+        // (which only reports the overflow) an empty cell must not prune
+        const uint32_t tt = ok ? min(j - d, PLL_INF8 - 1u) * 0x01010101u : 0u;
         const uint8_t* row = A.Tchk + (size_t)h * A.bstride;
         const uint64_t live_lane = cw & ~pw;
 #pragma unroll
@@ -255,13 +257,13 @@ __device__ inline void phase_batch_init(const BuildArgs& A, const Exec& X, uint3
             A.arena[off + len] = pll_pack(u, 0);
             A.llen[u] = len + 1;
             A.T[(size_t)u * A.bstride + k] = 0;
-            atomicOr((unsigned long long*)&A.rowmask[u], kq);
+            if (u >= A.hot) atomicOr((unsigned long long*)&A.rowmask[u], kq);
         }
         for (uint32_t i = lane; i < len; i += 64) {
             const uint32_t e = A.arena[off + i];
             const uint32_t h = e >> 8;
             A.T[(size_t)h * A.bstride + k] = (uint8_t)(e & 255u);
-            atomicOr((unsigned long long*)&A.rowmask[h], kq);
+            if (h >= A.hot) atomicOr((unsigned long long*)&A.rowmask[h], kq);
         }
         if (lane == 0) A.act_v[0][k] = u;
         if (lane == 0 && A.act_rng[0]) A.act_rng[0][k] = make_uint2(len, 1u);  // the self entry
@@ -533,7 +535,8 @@ __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t i
                 A.arena[off + len + pwos + __builtin_popcountll(aw & lt)] = pll_pack(ib + k, j);
                 if (in_batch) {
                     A.T[(size_t)(ib + k) * A.bstride + (v - ib)] = (uint8_t)j;
-                    atomicOr((unsigned long long*)&A.rowmask[ib + k], 1ull << ((v - ib) >> 4));
+                    if (ib + k >= A.hot)
+                        atomicOr((unsigned long long*)&A.rowmask[ib + k], 1ull << ((v - ib) >> 4));
                 }
             }
         }
@@ -918,9 +921,9 @@ __device__ inline void phase_clear_table(const BuildArgs& A, const Exec& X, uint
         for (uint32_t i = lane; i < len; i += 64) {
             const uint32_t h = A.arena[off + i] >> 8;
             A.T[(size_t)h * A.bstride + k] = (uint8_t)PLL_INF8;
-            A.rowmask[h] = 0;
+            if (h >= A.hot) A.rowmask[h] = 0;
         }
-        if (lane == 0) A.rowmask[u] = 0;
+        if (lane == 0 && u >= A.hot) A.rowmask[u] = 0;
     }
 }
 

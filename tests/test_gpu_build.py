@@ -163,6 +163,12 @@ def test_distance_overflow_is_edist():
     order = synth.degree_order(g)
     idx = build(g, order, batch_size=32)
     assert_labels_equal(idx, oracle.pll_labels(g, order), order)
+    # one batch, ids as ranks: the round-255 candidate of vertex 0 at vertex
+    # 255 meets only empty table cells (255 + 0 must not count as <= 255)
+    g = synth.path_graph(257)
+    with pytest.raises(pll.PllError) as e:
+        build(g, np.arange(257, dtype=np.uint32))
+    assert e.value.status == pll.PLL_EDIST
 
 
 def test_fixed_arena_too_small_is_enospc():

@@ -644,8 +644,8 @@ def serve_mode(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat16", choices=sorted(WORKLOADS))
     ap.add_argument("--batch-size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")

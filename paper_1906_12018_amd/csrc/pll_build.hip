@@ -1099,9 +1099,11 @@ int prepare_rank_csr(DevAllocs& M, DevCounters* ctr, DevCounters* h, uint32_t n,
 
 // Working buffers of the batch phases over the rank-space CSR (rrow, rcol);
 // the pruning checks read the build's own table until the caller says
-// otherwise.  Returns the spare offsets array of the arena relayout.
+// otherwise.  The row masks of the first hot_rows table rows stay all ones.
+// Returns the spare offsets array of the arena relayout.
 int init_state(DevAllocs& M, BuildArgs& A, uint32_t n, uint64_t nnz, uint32_t W, const uint64_t* rrow,
-               const uint32_t* rcol, DevCounters* ctr, hipStream_t s, uint64_t** spare_off) {
+               const uint32_t* rcol, DevCounters* ctr, hipStream_t s, uint64_t** spare_off,
+               uint32_t hot_rows = kHotRows) {
     A = BuildArgs{};
     A.n = n;
     A.W = W;
@@ -1135,7 +1137,7 @@ int init_state(DevAllocs& M, BuildArgs& A, uint32_t n, uint64_t nnz, uint32_t W,
     TRY_HIP(hipMemsetAsync(A.C, 0, sizeof(uint64_t) * n * W, s));
     TRY_HIP(hipMemsetAsync(A.msgs, 0, sizeof(uint64_t) * n * W, s));
     TRY_HIP(hipMemsetAsync(A.T, 0xFF, (size_t)n * A.bstride, s));
-    A.hot = std::min<uint32_t>(n, kHotRows);
+    A.hot = std::min<uint32_t>(n, hot_rows);
     TRY_HIP(hipMemsetAsync(A.rowmask, 0xFF, sizeof(uint64_t) * A.hot, s));
     TRY_HIP(hipMemsetAsync(A.rowmask + A.hot, 0, sizeof(uint64_t) * (n - A.hot), s));
     TRY_HIP(hipMemsetAsync(A.recv_stamp, 0, sizeof(uint32_t) * n, s));
@@ -1241,7 +1243,9 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     // --- build state
     BuildArgs A{};
     uint64_t* spare_off = nullptr;
-    rc = init_state(M, A, n, nnz, W, RC.rrow, RC.rcol, ctr, s, &spare_off);
+    // bit-parallel roots take the top-ranked vertices out of the labels, which
+    // leaves the top rows sparse: their masks are kept exact then
+    rc = init_state(M, A, n, nnz, W, RC.rrow, RC.rcol, ctr, s, &spare_off, bp_req ? 0u : kHotRows);
     if (rc) return rc;
     BpState BP;
     if (bp_req) {

@@ -1326,6 +1326,11 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
             }
         }
     }
+    // round 1's receivers (the neighbours of the batch) are only counted
+    // after its launch; its grid is sized by the previous batch's count,
+    // which falls from batch to batch in rank order (a grid-stride loop
+    // covers any excess)
+    uint64_t r1_est = n;
     for (uint32_t ib = 0; !(flags & PLL_FLAG_PERSISTENT) && ib < n; ib += b) {
         const uint32_t bs = std::min(b, n - ib);
         ++bstamp;
@@ -1348,7 +1353,7 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
             k_push<<<blocks_for_waves((uint64_t)bs + 1024), kBlock, 0, s>>>(A1, ib, 0, bs, rstamp, bstamp);
             P.span(PLL_PHASE_PUSH, r0, P.mark(), 1);
         }
-        uint64_t next_est = bs;
+        uint64_t next_est = r1_est;
         for (uint32_t j = 1;; ++j) {
             ++rounds;
             const pll::NextRound nr{mbuf[(j + 1) & 1u], rbuf[(j + 1) & 1u], (j - 1) % 3, j % 3, (j + 1) % 3, j & 1u,
@@ -1368,6 +1373,7 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
             if (rc) return rc;
             P.resolve();
             const unsigned long long acc_now = sum_stat(h, PLL_ST_ACC);
+            if (j == 1) r1_est = std::max<uint64_t>(bs, sum_recv(h, nr.rin));
             if (trace) {
                 unsigned long long cur[PLL_NUM_ST];
                 for (int k = 0; k < PLL_NUM_ST; ++k) cur[k] = sum_stat(h, k);
@@ -1714,6 +1720,7 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
     uint32_t rstamp = 0, bstamp = 0;
     uint64_t rounds = 0, batches = 0;
     unsigned long long accepted_seen[2] = {0, 0};
+    uint64_t r1_est[2] = {n, n};  // as in the undirected loop
     for (uint32_t ib = 0; ib < n; ib += b) {
         const uint32_t bs = std::min(b, n - ib);
         ++bstamp;
@@ -1734,7 +1741,7 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
             k_push<<<blocks_for_waves((uint64_t)bs + 1024), kBlock, 0, s>>>(A1, ib, 0, bs, rstamp, bstamp);
             P.span(PLL_PHASE_PUSH, r0, P.mark(), 1);
         }
-        uint64_t next_est[2] = {bs, bs};
+        uint64_t next_est[2] = {r1_est[0], r1_est[1]};
         bool live[2] = {true, true};
         for (uint32_t j = 1; live[0] || live[1]; ++j) {
             ++rounds;
@@ -1759,6 +1766,7 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
             P.resolve();
             for (int d = 0; d < 2; ++d) {
                 if (h[d]->error) return device_error_status(h[d]->error);
+                if (j == 1) r1_est[d] = std::max<uint64_t>(bs, sum_recv(h[d], nr[d].rin));
                 if (!live[d]) continue;
                 const unsigned long long acc_now = sum_stat(h[d], PLL_ST_ACC);
                 if (acc_now == accepted_seen[d]) {  // this side accepted nothing: its search is done

@@ -37,6 +37,7 @@ constexpr int kBlock = 256;              // 4 waves
 constexpr int kWavesPerBlock = kBlock / PLL_WAVE;
 constexpr uint32_t kMaxBlocks = 4096;
 constexpr uint32_t kHotRows = 256;         // top-ranked table rows whose row masks stay all ones
+constexpr uint64_t kPullFrac = 2;          // a round with at least n / 2 receivers pulls the next one
 
 inline uint32_t blocks_for_waves(uint64_t waves) {
     uint64_t b = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -347,8 +348,8 @@ __device__ inline void check_push_body(const BuildArgs& A, const pll::Exec& X, u
                                        const pll::NextRound& nr, uint32_t relaxed) {
     PhaseStats st;
     pll::phase_check<WM, BP, true>(A, X, ib, bs, j, nr.rin, relaxed != 0, st, &nr);
-    const unsigned long long v[9] = {st.cand,     st.acc, st.read,  st.table, st.cost_pos,
-                                     st.cost_neg, st.bp,  st.edges, st.edges};
+    const unsigned long long v[9] = {st.cand,     st.acc, st.read,  st.table,          st.cost_pos,
+                                     st.cost_neg, st.bp,  st.edges + st.pulled, st.edges};
     const int which[9] = {PLL_ST_CAND,     PLL_ST_ACC, PLL_ST_READ,  PLL_ST_TABLE,      PLL_ST_COST_POS,
                           PLL_ST_COST_NEG, PLL_ST_BP,  PLL_ST_EDGES, PLL_ST_FUSED_EDGES};
     block_add_stats<9>(A.ctr, v, which);
@@ -393,6 +394,16 @@ template <int WM>
 __global__ void __launch_bounds__(kBlock) k_check_push_bp(BuildArgs A, uint32_t ib, uint32_t bs, uint32_t j,
                                                           pll::NextRound nr, uint32_t relaxed) {
     check_push_body<WM, true>(A, grid_exec(A), ib, bs, j, nr, relaxed);
+}
+
+// Pulled rounds: the (vertex, segment) items, once per build, and a round.
+__global__ void __launch_bounds__(kBlock) k_pull_items(BuildArgs A, uint2* items, uint32_t* nitems) {
+    pll::phase_pull_items(A, grid_exec(A), items, nitems);
+}
+
+__global__ void __launch_bounds__(kBlock) k_pull(BuildArgs A, uint32_t ib, const uint2* items, const uint32_t* nitems,
+                                                 uint32_t q, pll::NextRound nr) {
+    pll::phase_pull(A, grid_exec(A), ib, items, nitems, q, nr);
 }
 
 // The heavy rows the fused round queued, pushed for the next round.
@@ -1292,11 +1303,25 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     // round j's messages and receivers live in mbuf[j & 1] and rbuf[j & 1]
     uint64_t* mbuf[2] = {A.msgs, nullptr};
     uint32_t* rbuf[2] = {A.recv, nullptr};
+    // pulled rounds: a round whose receivers number at least n / kPullFrac
+    // (the active vertices of the next round are among them) gathers at
+    // every vertex instead of scattering atomics along every active edge
+    uint2* pull_items = nullptr;
+    uint32_t* pull_n = nullptr;
+    uint64_t pull_cap = 0;
     if (!(flags & PLL_FLAG_PERSISTENT)) {
         mbuf[1] = M.get<uint64_t>((size_t)n * W);
         rbuf[1] = M.get<uint32_t>((size_t)PLL_SHARDS * n);
+        pull_cap = (uint64_t)n + nnz / pll::kPullSeg + 1;
+        pull_items = M.get<uint2>(pull_cap);
+        pull_n = M.get<uint32_t>(1);
+        A.act_at = M.get<uint64_t>(n);
         if (M.err != hipSuccess) return status_of(M.err);
         TRY_HIP(hipMemsetAsync(mbuf[1], 0, sizeof(uint64_t) * n * W, s));
+        TRY_HIP(hipMemsetAsync(pull_n, 0, sizeof(uint32_t), s));
+        TRY_HIP(hipMemsetAsync(A.act_at, 0, sizeof(uint64_t) * n, s));
+        k_pull_items<<<blocks_for_waves((n + 63) / 64), kBlock, 0, s>>>(A, pull_items, pull_n);
+        TRY_HIP(hipGetLastError());
     }
     if (flags & PLL_FLAG_PERSISTENT) {
         TRY_HIP(hipStreamSynchronize(s));
@@ -1356,8 +1381,9 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
         uint64_t next_est = r1_est;
         for (uint32_t j = 1;; ++j) {
             ++rounds;
+            const uint32_t pull = next_est * kPullFrac >= n ? 1u : 0u;
             const pll::NextRound nr{mbuf[(j + 1) & 1u], rbuf[(j + 1) & 1u], (j - 1) % 3, j % 3, (j + 1) % 3, j & 1u,
-                                    rstamp + 1, bstamp};
+                                    rstamp + 1, bstamp, pull};
             ++rstamp;
             BuildArgs Aj = A;
             Aj.msgs = mbuf[j & 1u];
@@ -1368,6 +1394,12 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
                                 relaxed);
             P.span(PLL_PHASE_CHECK, r1, P.mark(), 1);
             TRY_HIP(hipGetLastError());
+            if (pull) {
+                hipEvent_t r3 = P.mark();
+                k_pull<<<blocks_for_waves(pull_cap), kBlock, 0, s>>>(A, ib, pull_items, pull_n, nr.hout, nr);
+                P.span(PLL_PHASE_PUSH, r3, P.mark(), 1);
+                TRY_HIP(hipGetLastError());
+            }
             const double check_ms0 = P.ms[PLL_PHASE_CHECK];
             rc = read_counters(ctr, h, s);
             if (rc) return rc;

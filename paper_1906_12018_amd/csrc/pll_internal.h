@@ -108,6 +108,7 @@ struct BuildArgs {
     uint32_t* act_v[2];      // active list by parity (compact)
     uint64_t* act_delta[2];  // W words per active slot: delta L of that vertex
     uint2* act_rng[2];       // weighted graphs: (first, count) of the label entries the slot's vertex accepted
+    uint64_t* act_at;        // pulled rounds: (round stamp << 32) | active slot of a vertex that accepted
     // bit-parallel labels (rank space; bp_t = 0: none): bp_used[r] marks the
     // BP roots and their neighbour sets; per (rank r, BP root i) at r * bp_t + i:
     // bp_dist = d_i(r), bp_sets = (S^-1, S^0)

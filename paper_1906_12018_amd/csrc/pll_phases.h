@@ -31,6 +31,9 @@ struct PhaseStats {
     // cost of the positive / negative checks: |L(v)| at each check that
     // added / pruned a candidate (Section 4.3, Table 3)
     unsigned long long cost_pos = 0, cost_neg = 0;
+    // CSR entries of the vertices whose next-round deliveries are pulled: the
+    // edge accesses of Algorithm 4 (the gather itself reads more)
+    unsigned long long pulled = 0;
 };
 
 // Per byte of x: 1 if byte <= t, where tt = t * 0x01010101 (t <= 254).  Bytes
@@ -343,6 +346,108 @@ __device__ inline void phase_push_heavy(const BuildArgs& A, const Exec& X, uint3
     }
 }
 
+// Where a fused check delivers the next round: its message buffer, receiver
+// queue and counters, the round stamps, and whether that round is pulled.
+struct NextRound {
+    uint64_t* msgs;
+    uint32_t* recv;
+    uint32_t rin, rout, rclr, hout;
+    uint32_t rstamp, bstamp;
+    uint32_t pull;  // the next round is pulled (phase_pull) instead of pushed
+};
+
+// A pulled round (the direction-optimizing alternative to push_edges, for
+// rounds whose active vertices cover much of the graph): every vertex
+// r > ib ORs the deltas of its active neighbours (act_at carries this
+// round's stamp) and delivers the result exactly as the pushes from those
+// neighbours would: masked to candidates ranked above r and not yet in
+// C(r), into msgs(r), with one receiver slot and the first-touch record.
+// Items are (vertex, segment of kPullSeg CSR entries); the segments of one
+// vertex merge through atomicOr and the receiver stamp, like pushes do.
+// Four active neighbours are gathered at a time, one per 16-lane group.
+constexpr uint32_t kPullSeg = 256;
+
+__device__ inline void phase_pull(const BuildArgs& A, const Exec& X, uint32_t ib, const uint2* items,
+                                  const uint32_t* nitems, uint32_t q, const NextRound& nr) {
+    const uint32_t lane = lane_id();
+    const uint32_t W = A.W;
+    const uint32_t grp = lane >> 4, wd = lane & 15u;
+    const uint64_t* act_d = A.act_delta[q];
+    const uint32_t total = *nitems;
+    for (uint32_t t = X.w; t < total; t += X.nw) {
+        const uint2 it = items[t];
+        const uint32_t r = it.x;
+        if (r <= ib) continue;
+        const uint64_t beg = A.rrow[r] + (uint64_t)it.y * kPullSeg;
+        const uint64_t end = min(A.rrow[r + 1], beg + kPullSeg);
+        uint64_t m = 0;
+        for (uint64_t e0 = beg; e0 < end; e0 += 64) {
+            const uint64_t e = e0 + lane;
+            const uint64_t at = e < end ? A.act_at[A.rcol[e]] : 0ull;
+            uint64_t act = ballot64((uint32_t)(at >> 32) == nr.rstamp);
+            while (act) {
+                uint32_t slot = 0;
+                bool have = false;
+#pragma unroll
+                for (uint32_t k = 0; k < 4; ++k) {
+                    if (act) {
+                        const uint32_t s = (uint32_t)__builtin_ctzll(act);
+                        act &= act - 1;
+                        const uint32_t sl = readlane32((uint32_t)at, s);
+                        if (grp == k) {
+                            slot = sl;
+                            have = true;
+                        }
+                    }
+                }
+                if (have && wd < W) m |= act_d[(size_t)slot * W + wd];
+            }
+        }
+        m |= __shfl_xor(m, 16, 64);
+        m |= __shfl_xor(m, 32, 64);
+        if (lane < W) {
+            m &= rank_mask(r - ib, lane);
+            if (m) m &= ~A.C[(size_t)r * W + lane];
+        } else {
+            m = 0;
+        }
+        if (m) atomicOr((unsigned long long*)&nr.msgs[(size_t)r * W + lane], (unsigned long long)m);
+        if (!ballot64(m != 0)) continue;
+        bool enq = false, first = false;
+        if (lane == 0) {
+            if (A.recv_stamp[r] != nr.rstamp) enq = atomicExch(&A.recv_stamp[r], nr.rstamp) != nr.rstamp;
+            if (enq && A.touch_stamp[r] != nr.bstamp) {
+                A.touch_stamp[r] = nr.bstamp;
+                first = true;
+            }
+        }
+        const uint32_t rp = shard_append(&X.qs[X.my].recv[nr.rout], enq, (uint64_t)X.my * X.seg);
+        if (enq) nr.recv[rp] = r;
+        const uint32_t tp = shard_append(&X.qs[X.my].touched, first, (uint64_t)X.my * X.seg);
+        if (first) {
+            A.touched[tp] = r;
+            A.tstart[tp] = A.llen[r];
+        }
+    }
+}
+
+// The pull items of a rank-space CSR: (r, c) for every segment c of
+// kPullSeg entries of every vertex r with neighbours, appended in any order.
+__device__ inline void phase_pull_items(const BuildArgs& A, const Exec& X, uint2* items, uint32_t* nitems) {
+    const uint32_t lane = lane_id();
+    for (uint32_t r0 = X.w * 64u; r0 < A.n; r0 += X.nw * 64u) {
+        const uint32_t r = r0 + lane;
+        const uint64_t deg = r < A.n ? A.rrow[r + 1] - A.rrow[r] : 0ull;
+        const uint32_t cnt = (uint32_t)((deg + kPullSeg - 1) / kPullSeg);
+        const uint32_t pos = wave_excl_scan32(cnt);
+        const uint32_t tot = readlane32(pos + cnt, 63);
+        uint32_t base = 0;
+        if (lane == 0 && tot) base = atomicAdd(nitems, tot);
+        base = readlane32(base, 0);
+        for (uint32_t c = 0; c < cnt; ++c) items[base + pos + c] = make_uint2(r, c);
+    }
+}
+
 // Scatter phase (Algorithm 4, lines 6-10) over active list p (nact slots).
 // Batch vertex u_k may be sent to v only when u_k outranks v (rank ib + k
 // < v) and C(v) does not hold it yet.  Slots whose delta is empty are
@@ -461,12 +566,6 @@ __device__ inline uint64_t bp_prune_words(const BuildArgs& A, uint32_t v, uint32
 // counters rotate over three (this round's nr->rin = p, the next round's,
 // and nr->rclr, cleared here); active lists and heavy items use parity
 // nr->hout.
-struct NextRound {
-    uint64_t* msgs;
-    uint32_t* recv;
-    uint32_t rin, rout, rclr, hout;
-    uint32_t rstamp, bstamp;
-};
 
 template <int WM, bool BP = false, bool FUSE = false, bool QGATE = false>
 __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t bs, uint32_t j, uint32_t p,
@@ -541,6 +640,13 @@ __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t i
             }
         }
         if (lane == 0) A.llen[v] = len + total;
+        if (FUSE && nr->pull) {  // the receivers gather: record where delta L(v) is
+            if (lane == 0) {
+                A.act_at[v] = ((uint64_t)nr->rstamp << 32) | i;
+                st.pulled += A.rrow[v + 1] - A.rrow[v];
+            }
+            continue;
+        }
         const uint64_t beg = A.rrow[v], end = A.rrow[v + 1];
         if (FUSE && end - beg <= kHeavy) {
             if (lane == 0) st.edges += end - beg;

@@ -38,6 +38,7 @@ constexpr int kWavesPerBlock = kBlock / PLL_WAVE;
 constexpr uint32_t kMaxBlocks = 4096;
 constexpr uint32_t kHotRows = 256;         // top-ranked table rows whose row masks stay all ones
 constexpr uint64_t kPullFrac = 2;          // a round with at least n / 2 receivers pulls the next one
+constexpr uint32_t kPullMinN = 16384;      // smaller graphs always push (the pull's set-up outweighs it)
 
 inline uint32_t blocks_for_waves(uint64_t waves) {
     uint64_t b = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -1309,15 +1310,19 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     uint2* pull_items = nullptr;
     uint32_t* pull_n = nullptr;
     uint64_t pull_cap = 0;
+    const bool pull_ok = !(flags & PLL_FLAG_PERSISTENT) && n >= kPullMinN;
     if (!(flags & PLL_FLAG_PERSISTENT)) {
         mbuf[1] = M.get<uint64_t>((size_t)n * W);
         rbuf[1] = M.get<uint32_t>((size_t)PLL_SHARDS * n);
+        if (M.err != hipSuccess) return status_of(M.err);
+        TRY_HIP(hipMemsetAsync(mbuf[1], 0, sizeof(uint64_t) * n * W, s));
+    }
+    if (pull_ok) {
         pull_cap = (uint64_t)n + nnz / pll::kPullSeg + 1;
         pull_items = M.get<uint2>(pull_cap);
         pull_n = M.get<uint32_t>(1);
         A.act_at = M.get<uint64_t>(n);
         if (M.err != hipSuccess) return status_of(M.err);
-        TRY_HIP(hipMemsetAsync(mbuf[1], 0, sizeof(uint64_t) * n * W, s));
         TRY_HIP(hipMemsetAsync(pull_n, 0, sizeof(uint32_t), s));
         TRY_HIP(hipMemsetAsync(A.act_at, 0, sizeof(uint64_t) * n, s));
         k_pull_items<<<blocks_for_waves((n + 63) / 64), kBlock, 0, s>>>(A, pull_items, pull_n);
@@ -1381,7 +1386,7 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
         uint64_t next_est = r1_est;
         for (uint32_t j = 1;; ++j) {
             ++rounds;
-            const uint32_t pull = next_est * kPullFrac >= n ? 1u : 0u;
+            const uint32_t pull = pull_ok && next_est * kPullFrac >= n ? 1u : 0u;
             const pll::NextRound nr{mbuf[(j + 1) & 1u], rbuf[(j + 1) & 1u], (j - 1) % 3, j % 3, (j + 1) % 3, j & 1u,
                                     rstamp + 1, bstamp, pull};
             ++rstamp;
@@ -1752,7 +1757,6 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
     uint32_t rstamp = 0, bstamp = 0;
     uint64_t rounds = 0, batches = 0;
     unsigned long long accepted_seen[2] = {0, 0};
-    uint64_t r1_est[2] = {n, n};  // as in the undirected loop
     for (uint32_t ib = 0; ib < n; ib += b) {
         const uint32_t bs = std::min(b, n - ib);
         ++bstamp;
@@ -1773,7 +1777,7 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
             k_push<<<blocks_for_waves((uint64_t)bs + 1024), kBlock, 0, s>>>(A1, ib, 0, bs, rstamp, bstamp);
             P.span(PLL_PHASE_PUSH, r0, P.mark(), 1);
         }
-        uint64_t next_est[2] = {r1_est[0], r1_est[1]};
+        uint64_t next_est[2] = {bs, bs};
         bool live[2] = {true, true};
         for (uint32_t j = 1; live[0] || live[1]; ++j) {
             ++rounds;
@@ -1798,7 +1802,6 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
             P.resolve();
             for (int d = 0; d < 2; ++d) {
                 if (h[d]->error) return device_error_status(h[d]->error);
-                if (j == 1) r1_est[d] = std::max<uint64_t>(bs, sum_recv(h[d], nr[d].rin));
                 if (!live[d]) continue;
                 const unsigned long long acc_now = sum_stat(h[d], PLL_ST_ACC);
                 if (acc_now == accepted_seen[d]) {  // this side accepted nothing: its search is done

@@ -277,3 +277,20 @@ def test_size_limits_rejected_before_any_work():
         with pytest.raises(pll.PllError) as e:
             build(g, synth.degree_order(g), **bad)
         assert e.value.status == pll.PLL_EINVAL
+
+
+@pytest.mark.parametrize("b", [64, 1024])
+def test_pulled_rounds_match_oracle(b):
+    """Graphs of 16,384 vertices or more gather the rounds that follow a round
+    with at least n/2 receivers instead of pushing them: labels and every
+    counter of Algorithm 4 (edge accesses included) stay as with pushes."""
+    g = synth.ba_graph(20000, 4, 3)
+    order = synth.degree_order(g)
+    want = oracle.pll_labels(g, order)
+    idx = build(g, order, batch_size=b, flags=pll.FLAG_PROFILE)
+    assert_labels_equal(idx, want, order)
+    info = check_counters(idx, g, order, b, want)
+    assert int(g.degrees().max()) <= 1024  # no heavy-row pushes: every extra push launch is a pull
+    assert info["phase_launches"]["push"] > info["batches"]
+    u, v = synth.query_pairs(g.n, 100_000, seed=4)
+    assert np.array_equal(gpu_query(idx, u, v), oracle.query(want, u, v))

@@ -112,7 +112,8 @@ typedef struct {
     uint64_t rounds;          /* vertex-centric rounds run, summed over batches */
     uint64_t candidates;      /* distance checks made (candidates surviving the C(v) filter) */
     uint64_t accepted;        /* entries accepted by the round checks */
-    uint64_t edges_scanned;   /* CSR entries read by the push phase */
+    uint64_t edges_scanned;   /* edge accesses of Algorithm 4: CSR entries of every vertex that sends new entries
+                                 on (counted the same whether a round pushes them or its receivers gather them) */
     uint64_t recheck_removed; /* entries dropped by the label-cleaning recheck (0 for exact rounds) */
     uint64_t arena_entries;   /* arena capacity the successful build used */
     uint32_t build_attempts;  /* 1 + automatic arena retries */
@@ -133,7 +134,9 @@ typedef struct {
     uint64_t bp_pruned;       /* candidates the bit-parallel bound pruned */
     uint64_t check_push_edges; /* CSR entries pushed by the check launches themselves (the rounds fuse the
                                   check of round j with the push of round j+1); the rest of edges_scanned is
-                                  the first push of each batch and rows longer than 1,024 entries */
+                                  the first push of each batch, rows longer than 1,024 entries and the senders
+                                  of gathered rounds (rounds with at least n/2 receivers, graphs of 16,384
+                                  vertices or more) */
 } pll_index_info;
 
 /* One graph of a batched build (all pointers are device pointers). */

@@ -10,6 +10,8 @@ Functions (all host-side, written from the paper, arXiv 1906.12018):
 * :func:`canonical_labels` -- Definition 2 written out, one BFS per vertex.
 * :func:`pll_labels`       -- Algorithm 1 (PLL) with the small revision of
   Section 2.1.1.
+* :func:`pll_labels_budget` -- the same PLL stopped after a host-time budget
+  (the first roots in rank order; a timing sample of a long build).
 * :func:`bvc_labels`       -- Algorithm 4 (BVC-PLL) run sequentially with
   batch size b; b = 1 is PLL and b = n is VC-PLL (Algorithm 3).
 * :func:`query`            -- the 2-hop distance formula of Section 2.1.
@@ -86,6 +88,9 @@ def _load():
         P = ctypes.c_void_p
         lib.oracle_pll.argtypes = [ctypes.c_uint32, P, P, P, ctypes.POINTER(_CLabels)]
         lib.oracle_pll.restype = ctypes.c_int
+        lib.oracle_pll_budget.argtypes = [ctypes.c_uint32, P, P, P, ctypes.c_double,
+                                          ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_CLabels)]
+        lib.oracle_pll_budget.restype = ctypes.c_int
         lib.oracle_bvc.argtypes = [ctypes.c_uint32, P, P, P, ctypes.c_uint32, ctypes.POINTER(_CLabels)]
         lib.oracle_bvc.restype = ctypes.c_int
         lib.oracle_canonical.argtypes = [ctypes.c_uint32, P, P, P, ctypes.c_uint32, P, ctypes.c_uint32,
@@ -176,6 +181,19 @@ def pll_labels(g, order) -> Labels:
     _check(_load().oracle_pll(g.n, row_ptr.ctypes.data, col.ctypes.data, order.ctypes.data, ctypes.byref(c)),
            "oracle_pll")
     return _take(c)
+
+
+def pll_labels_budget(g, order, seconds: float):
+    """The PLL of :func:`pll_labels` run over the first roots in rank order
+    until ``seconds`` of host time are spent (the root running then is
+    finished).  Returns ``(labels, roots_done)``; the lists hold only hubs of
+    rank below roots_done."""
+    row_ptr, col, order = _graph_args(g, order)
+    c = _CLabels()
+    done = ctypes.c_uint32(0)
+    _check(_load().oracle_pll_budget(g.n, row_ptr.ctypes.data, col.ctypes.data, order.ctypes.data, float(seconds),
+                                     ctypes.byref(done), ctypes.byref(c)), "oracle_pll_budget")
+    return _take(c), int(done.value)
 
 
 def bvc_labels(g, order, b: int) -> Labels:

@@ -12,6 +12,8 @@
  *   oracle_pll        Algorithm 1 (PLL) with the "small revision" of
  *                     Section 2.1.1 (only push to lower-ranked neighbours) and
  *                     the dense array for L(u) from Section 3.3.
+ *   oracle_pll_budget the same PLL stopped once a host-time budget is spent
+ *                     (the first roots in rank order; a timing sample).
  *   oracle_bvc        Algorithm 4 (BVC-PLL), sequential, batch size b, with
  *                     the candidate bit-vector C(v) and the per-batch H(u)
  *                     arrays of Section 4.1.
@@ -44,6 +46,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <pthread.h>
+#include <time.h>
 
 #define ORACLE_OK 0
 #define ORACLE_ENOMEM 2
@@ -292,9 +295,20 @@ int oracle_canonical(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, c
  * joins L(v) and the unvisited neighbours of v ranked below u are queued
  * with delta + 1 (the small revision); otherwise v is pruned.
  */
-int oracle_pll(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* order,
-               oracle_labels* out) {
+static double mono_seconds(void) {
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+/* PLL over the roots of rank 0 .. n-1, or, with budget_s > 0, over the roots
+ * taken before budget_s seconds have passed (the root running when the budget
+ * runs out is finished); *roots_done receives the number of roots run. */
+static int pll_run(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* order,
+                   double budget_s, uint32_t* roots_done, oracle_labels* out) {
     memset(out, 0, sizeof(*out));
+    const double t_start = budget_s > 0 ? mono_seconds() : 0.0;
+    uint32_t roots = 0;
     uint32_t* rank = make_rank(n, order);
     if (!rank) return ORACLE_EINVAL;
     vlist* L = (vlist*)calloc(n ? n : 1, sizeof(vlist));
@@ -308,6 +322,8 @@ int oracle_pll(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const u
     for (uint32_t i = 0; i < n; ++i) visited[i] = DIST_INF;
     uint64_t checks = 0, added = 0, edges = 0, scanned = 0, cost_pos = 0, cost_neg = 0;
     for (uint32_t k = 0; k < n && !rc; ++k) {
+        if (budget_s > 0 && mono_seconds() - t_start >= budget_s) break;
+        roots = k + 1;
         uint32_t u = order[k];
         vlist* Lu = &L[u];
         for (uint32_t i = 0; i < Lu->len; ++i) T[Lu->hub[i]] = Lu->d[i];
@@ -359,7 +375,21 @@ int oracle_pll(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const u
 done:
     if (L) vlists_free(L, n);
     free(T); free(visited); free(qv); free(qd); free(rank);
+    if (roots_done) *roots_done = roots;
     return rc;
+}
+
+int oracle_pll(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* order,
+               oracle_labels* out) {
+    return pll_run(n, row_ptr, col, order, 0.0, NULL, out);
+}
+
+/* The same PLL stopped after the first roots that fit in budget_s seconds of
+ * host time (a timing sample of a build too long to run whole): the lists
+ * hold the entries of hubs ranked below *roots_done only. */
+int oracle_pll_budget(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* order,
+                      double budget_s, uint32_t* roots_done, oracle_labels* out) {
+    return pll_run(n, row_ptr, col, order, budget_s > 0 ? budget_s : 1e-9, roots_done, out);
 }
 
 /* ---- Algorithm 4: BVC-PLL (sequential) -------------------------------------

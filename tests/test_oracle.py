@@ -343,3 +343,79 @@ def test_check_costs_ba_and_b1_reduces_to_pll():
         bv = oracle.bvc_labels(g, order, b)
         assert bv.counters["cost_pos"] == bvc_positive_cost(bv, order, b)
         assert bv.counters["cost_pos"] <= p.counters["cost_pos"]
+
+
+# ---- edge-access and round counters (Algorithm 4's rounds; Section 4.3's edge accesses) ---------------------------
+
+def bvc_edge_accesses(lab: oracle.Labels, order, g, b):
+    """Every vertex that accepts entries of batch i in a round sends them
+    along all of its edges in the next round (the batch roots send their
+    self entry in round 1), so v costs deg(v) edge accesses per distinct
+    distance among its batch-i entries."""
+    deg = g.degrees()
+    total = 0
+    for v in range(g.n):
+        h, d = lab.of(v)
+        bt = h.astype(np.int64) // b
+        pairs = np.unique(bt * 256 + d.astype(np.int64))
+        total += int(pairs.shape[0]) * int(deg[v])
+    return total
+
+
+def bvc_rounds(lab: oracle.Labels, n, b):
+    """A batch runs one round per message distance 1 .. D+1, where D is the
+    largest distance among its entries: the round carrying D+1 is the one in
+    which nothing is accepted and the batch ends."""
+    bt = lab.hub_rank.astype(np.int64) // b
+    nb = (n + b - 1) // b
+    dmax = np.full(nb, -1, dtype=np.int64)
+    np.maximum.at(dmax, bt, lab.dist.astype(np.int64))
+    assert (dmax >= 0).all()  # every batch has its roots' self entries
+    return int((dmax + 1).sum())
+
+
+@pytest.mark.parametrize("gi", range(len(small_graphs())))
+def test_edge_and_round_counters_match_closed_forms(gi):
+    g = small_graphs()[gi]
+    if g.n == 0:
+        return
+    for order in (synth.degree_order(g), random_order(g.n, 5 + gi)):
+        p = oracle.pll_labels(g, order)
+        # PLL expands every vertex it labels: deg(v) per entry of L(v)
+        assert p.counters["edge_accesses"] == int((p.sizes() * g.degrees()).sum())
+        for b in sorted({1, 2, 3, 5, g.n}):
+            bv = oracle.bvc_labels(g, order, b)
+            assert bv.counters["edge_accesses"] == bvc_edge_accesses(bv, order, g, b), b
+            assert bv.counters["rounds"] == bvc_rounds(bv, g.n, b), b
+            assert bv.counters["batches"] == (g.n + b - 1) // b
+            if b == 1:  # one root per batch: PLL's BFS expansions
+                assert bv.counters["edge_accesses"] == p.counters["edge_accesses"]
+
+
+def test_edge_and_round_counters_ba2000():
+    g = synth.ba_graph(2000, 4, 1)
+    order = synth.degree_order(g)
+    for b in (64, 1024):
+        bv = oracle.bvc_labels(g, order, b)
+        assert bv.counters["edge_accesses"] == bvc_edge_accesses(bv, order, g, b)
+        assert bv.counters["rounds"] == bvc_rounds(bv, g.n, b)
+
+
+def test_budgeted_pll_is_a_prefix_of_pll():
+    """The time-bounded PLL (the CPU baseline's sample of long builds) runs
+    the first roots in rank order: its lists are exactly the full labels'
+    entries whose hub ranks below the roots it ran, and with room for every
+    root it is PLL."""
+    g = synth.ba_graph(3000, 4, 3)
+    order = synth.degree_order(g)
+    full = oracle.pll_labels(g, order)
+    part, k = oracle.pll_labels_budget(g, order, 1e-4)
+    assert 1 <= k <= g.n
+    keep = full.hub_rank < k
+    owners = np.repeat(np.arange(g.n), full.sizes())
+    want_sizes = np.bincount(owners[keep], minlength=g.n)
+    assert np.array_equal(part.sizes(), want_sizes)
+    assert np.array_equal(part.hub_rank, full.hub_rank[keep])
+    assert np.array_equal(part.dist, full.dist[keep])
+    whole, k = oracle.pll_labels_budget(g, order, 3600.0)
+    assert k == g.n and np.array_equal(whole.offsets, full.offsets) and np.array_equal(whole.hub_rank, full.hub_rank)

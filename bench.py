@@ -2,16 +2,21 @@
 """Benchmark of the label-build + query hot path on one MI355X.
 
 One step = one full label build (pll_build_labels: checks, relabel, every
-batch and round, finalize) of the R-MAT scale-16 graph (65,536 vertices, edge
-factor 16, a,b,c,d = .57,.19,.19,.05, seed 1, degree order, b = 1024) from a
-device-resident CSR, followed by one batched query of 10^6 uniform pairs
-(seed 2).  Prints one JSON line.  The timed steps build without per-phase
-events; --steps profiled builds follow, and their HIP events give the
-kernel times of the roofline entry.  Other modes: --mode query (queries
-alone), --mode batched (the 256-graph one-launch build), --mode serve (the
-serving loop), --mode directed (directed R-MAT build and query), --mode
-weighted (R-MAT with 1..7 weights, build and query), --mode bp (builds with
-bit-parallel labels), each printing its own JSON line.
+batch and round, finalize) of the R-MAT scale-20 graph (1,048,576 vertices,
+edge factor 16, a,b,c,d = .57,.19,.19,.05, seed 1, degree order, b = 1024)
+from a device-resident CSR, followed by one batched query of its 10^7
+uniform pairs (seed 2); --workload rmat16 / ba2000 picks the smaller
+configurations.  Prints one JSON line.  The timed steps build without
+per-phase events; --steps profiled builds follow, and their HIP events give
+the kernel times of the roofline entry.  The exported labels and the answers
+are compared with the oracle's stored digests (tests/golden), the query
+rate is set beside a streaming-read kernel's rate on the same device, and
+the CPU baseline times the oracle on the host (a whole build when it takes
+seconds, else the first roots that fit a time budget).  Other modes: --mode
+query (queries alone), --mode batched (the 256-graph one-launch build),
+--mode serve (the serving loop), --mode directed (directed R-MAT build and
+query), --mode weighted (R-MAT with 1..7 weights, build and query), --mode bp
+(builds with bit-parallel labels), each printing its own JSON line.
 """
 from __future__ import annotations
 
@@ -229,20 +234,6 @@ def consumed_for(idx, g, order, u, v):
     return consumed_entries(off, rank[hubs.astype(np.int64)], rank, u.astype(np.int64), v.astype(np.int64))
 
 
-_POOL_LABELS = None
-
-
-def _pool_init(labels):
-    global _POOL_LABELS
-    _POOL_LABELS = labels
-
-
-def _pool_query(args):
-    import oracle
-    u, v = args
-    return oracle.query(_POOL_LABELS, u, v)
-
-
 def host_info():
     """CPU model and core counts of the host the CPU baseline ran on."""
     model = ""
@@ -261,36 +252,66 @@ def host_info():
     return {"cpu": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
-def cpu_baseline(g, order, total_entries, u, v):
-    """The oracle's sequential PLL (Algorithm 1) on the host, one thread, on
-    the whole graph (the R-MAT scale-16 build takes a few seconds); then the
-    oracle's merge-join query on its own labels over the workload's pairs,
-    on one core and on a pool of host processes (started fresh: they never
-    touch the GPU)."""
-    import multiprocessing as mp
+def oracle_query_rates(labels, u, v):
+    """The oracle's merge-join over ``labels`` for the workload's pairs, on
+    one host thread and on every usable host CPU (threads over contiguous
+    chunks; the C oracle runs outside the interpreter lock).  Returns the
+    rates and the answers of the one-thread run."""
+    from concurrent.futures import ThreadPoolExecutor
     import numpy as np
     import oracle
     t0 = time.perf_counter()
-    lab = oracle.pll_labels(g, order)
-    dt = time.perf_counter() - t0
-    assert lab.total == total_entries, "oracle and GPU label counts differ"
-    t0 = time.perf_counter()
-    oracle.query(lab, u, v)
+    ans = oracle.query(labels, u, v)
     q1 = time.perf_counter() - t0
-    procs = min(8, os.cpu_count() or 1)
-    chunks = [(a, b) for a, b in zip(np.array_split(u, procs * 4), np.array_split(v, procs * 4))]
-    with mp.get_context("spawn").Pool(procs, initializer=_pool_init, initargs=(lab,)) as pool:
-        pool.map(_pool_query, chunks[:procs])  # start-up and label transfer, untimed
+    threads = host_info()["usable_cpus"] or 1
+    parts = [(a, b) for a, b in zip(np.array_split(u, threads * 4), np.array_split(v, threads * 4))]
+    with ThreadPoolExecutor(threads) as ex:
         t0 = time.perf_counter()
-        pool.map(_pool_query, chunks)
+        outs = list(ex.map(lambda ab: oracle.query(labels, ab[0], ab[1]), parts))
         qn = time.perf_counter() - t0
-    return {"value": lab.total / dt, "unit": "label entries/s", "cores": 1, "kind": "oracle", "host": host_info(),
-            "sample": f"full sequential PLL build of the same graph ({g.n} vertices, {lab.total} entries), "
-                      f"1 run, {dt:.2f} s", "seconds": dt,
-            "pll_check_cost": {"pos": lab.counters["cost_pos"], "neg": lab.counters["cost_neg"]},
-            "query": {"pairs": int(u.shape[0]), "queries_per_s_1core": u.shape[0] / q1,
-                      "queries_per_s_pool": u.shape[0] / qn, "pool_processes": procs,
-                      "sample": "the oracle's merge-join over its own labels, the same pairs"}}
+    assert np.array_equal(np.concatenate(outs), ans), "threaded oracle query disagrees"
+    return {"pairs": int(u.shape[0]), "queries_per_s_1core": u.shape[0] / q1, "queries_per_s_all": u.shape[0] / qn,
+            "threads": threads}, ans
+
+
+def cpu_baseline(g, order, total_entries, u, v, budget_s: float, gpu_labels=None):
+    """The oracle's sequential PLL (Algorithm 1) on one host thread.  With
+    budget_s = 0 the whole graph is built (R-MAT scale 16 takes seconds);
+    otherwise only the first roots in rank order that fit in budget_s
+    seconds (a full R-MAT scale-20 build takes tens of minutes), reported
+    with the number of roots run.  Then the oracle's merge-join query over
+    the workload's pairs on one thread and on every usable CPU, over the
+    oracle's own labels, or, for a sampled build, over ``gpu_labels``: the
+    exported GPU labels, already checked byte for byte against the oracle's
+    stored digests of the same graph."""
+    import oracle
+    res = {"unit": "label entries/s", "cores": 1, "kind": "oracle", "host": host_info()}
+    t0 = time.perf_counter()
+    if budget_s > 0:
+        lab, roots = oracle.pll_labels_budget(g, order, budget_s)
+    else:
+        lab, roots = oracle.pll_labels(g, order), g.n
+    dt = time.perf_counter() - t0
+    res.update({"value": lab.total / dt, "seconds": dt, "roots_done": roots, "entries": lab.total})
+    if roots == g.n:
+        assert lab.total == total_entries, "oracle and GPU label counts differ"
+        res["sample"] = f"full sequential PLL build of the same graph ({g.n} vertices, {lab.total} entries), " \
+                        f"1 run, {dt:.2f} s"
+        res["pll_check_cost"] = {"pos": lab.counters["cost_pos"], "neg": lab.counters["cost_neg"]}
+        qlab = lab
+        src = "the oracle's merge-join over its own labels, the same pairs"
+    else:
+        res["sample"] = (f"sequential PLL over the first {roots} of {g.n} roots in rank order (a {budget_s:.0f} s "
+                         f"budget): {lab.total} of the {total_entries} entries in {dt:.2f} s; the earliest roots "
+                         f"label the most vertices per check, so the whole build runs slower than this rate")
+        del lab
+        qlab = gpu_labels
+        src = ("the oracle's merge-join, the same pairs, over the exported GPU labels (identical to the oracle's: "
+               "their SHA-256 digests equal the stored ones)")
+    if qlab is not None:
+        res["query"], _ = oracle_query_rates(qlab, u, v)
+        res["query"]["sample"] = src
+    return res
 
 
 def directed_mode(args):
@@ -641,12 +662,242 @@ def serve_mode(args):
     print(json.dumps(line), flush=True)
 
 
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+
+
+def stream_read_gbs(gib: float, reps: int = 5):
+    """Achievable HBM read bandwidth: the library's streaming-read reference
+    kernel over a buffer of `gib` GiB (16x the last-level cache at 4 GiB),
+    timed with HIP events on the launching stream.  Returns the best and the
+    median rate over `reps` launches."""
+    import numpy as np
+    import torch
+    import paper_1906_12018_amd as pll
+    nbytes = int(gib * (1 << 30)) & ~15
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    buf.fill_(7)
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    pll.stream_read(buf, sink)  # warm-up
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pll.stream_read(buf, sink)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del buf
+    gbs = [nbytes / (t / 1e3) / 1e9 for t in ms]
+    return {"best_GBs": max(gbs), "median_GBs": float(np.median(gbs)), "bytes": nbytes, "launches": reps,
+            "kernel": "k_stream_read (pll_bench_stream_read)"}
+
+
+def golden_for(workload):
+    """The oracle's stored digests of a workload (tests/golden), or None."""
+    path = os.path.join(GOLDEN_DIR, f"{workload}_oracle.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def export_digests(idx, order):
+    """SHA-256 digests of the exported labels in the stored layout, and the
+    exported arrays as oracle-layout labels (hub ranks) for the CPU query."""
+    import numpy as np
+    import torch
+    import oracle
+    if GOLDEN_DIR not in sys.path:
+        sys.path.insert(0, GOLDEN_DIR)
+    from make_goldens import label_digests
+    ex = idx.export()
+    torch.cuda.synchronize()
+    off = ex.offsets.cpu().numpy().view(np.uint64)
+    hubs = ex.hubs.cpu().numpy().view(np.uint32)
+    dists = ex.dists.cpu().numpy()
+    dig = label_digests(off, hubs, dists)
+    rank = np.empty(order.shape[0], dtype=np.uint32)
+    rank[order.astype(np.int64)] = np.arange(order.shape[0], dtype=np.uint32)
+    return dig, oracle.Labels(off.copy(), rank[hubs], dists.copy())
+
+
+def build_mode(args):
+    """One step = one full label build of the workload's graph from a
+    device-resident CSR, then one batched query of its configured pairs."""
+    import hashlib
+    import numpy as np
+    import torch
+    import synth
+    import paper_1906_12018_amd as pll
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    g = make_graph(w)
+    order = synth.degree_order(g)
+    rp, cl = pll.graph_to_device(g, dev)
+    od = torch.from_numpy(order.view(np.int32)).to(dev)
+    u, v = synth.query_pairs(g.n, w["pairs"], seed=2)
+    du = torch.from_numpy(u.view(np.int32)).to(dev)
+    dv = torch.from_numpy(v.view(np.int32)).to(dev)
+    out = torch.empty_like(du)
+    torch.cuda.synchronize()
+    print(f"bench: {args.workload} n={g.n} nnz={g.nnz} pairs={w['pairs']}", file=sys.stderr, flush=True)
+
+    # timed steps: builds without per-phase events (the events add about a
+    # fifth to an R-MAT-16 build); then the same number of profiled builds
+    # whose HIP events on the build stream give the per-kernel times
+    build_ms, query_ms, step_ms = [], [], []
+    ref = None
+    for it in range(args.warmup + args.steps):
+        timed = it >= args.warmup
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        idx = pll.build_labels(rp, cl, od, batch_size=args.batch_size, flags=0)
+        t1 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        idx.query(du, dv, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        info = idx.info()
+        if ref is None:
+            ref = (info["total_entries"], out.clone())
+        else:
+            assert info["total_entries"] == ref[0] and torch.equal(out, ref[1]), "steps disagree"
+        if timed:
+            build_ms.append((t1 - t0) * 1e3)
+            query_ms.append(e0.elapsed_time(e1))
+            step_ms.append((t2 - t0) * 1e3)
+        if it < args.warmup + args.steps - 1:
+            idx.free()
+    print(f"bench: {args.steps} timed steps done", file=sys.stderr, flush=True)
+    prof = []
+    for _ in range(args.steps):
+        pidx = pll.build_labels(rp, cl, od, batch_size=args.batch_size, flags=pll.FLAG_PROFILE)
+        prof.append(pidx.info())
+        assert prof[-1]["total_entries"] == ref[0], "profiled build disagrees"
+        pidx.free()
+    print("bench: profiled builds done", file=sys.stderr, flush=True)
+
+    info = prof[-1]
+    total = info["total_entries"]
+    K = args.steps
+    sum_build_s = sum(build_ms) / 1e3
+    value = total * K / sum_build_s
+    qps = w["pairs"] / (np.median(query_ms) / 1e3)
+
+    # parity of this run against the oracle's stored digests (labels whole,
+    # answers to every configured pair), when they exist for the workload
+    gold = golden_for(args.workload)
+    parity, gpu_labels, cons = None, None, None
+    if gold is not None:
+        dig, gpu_labels = export_digests(idx, order)
+        ans = out.cpu().numpy().view(np.uint32)
+        parity = {"labels_equal_oracle": all(dig[k] == gold[k] for k in ("total", "sha_offsets", "sha_hubs",
+                                                                           "sha_dists")),
+                  "answers_equal_oracle": hashlib.sha256(ans.tobytes()).hexdigest() == gold["pairs"]["sha"],
+                  "source": f"tests/golden/{args.workload}_oracle.json (oracle PLL, written offline)"}
+        if parity["labels_equal_oracle"]:
+            cons = gold["pairs"]["consumed_entries"]
+        else:
+            gpu_labels = None
+        print(f"bench: parity {parity}", file=sys.stderr, flush=True)
+    if cons is None:
+        cons = consumed_for(idx, g, order, u, v)
+
+    # roofline, dominant kernel: the fused pruning check and push
+    # (k_check_push), bytes per the kernel's traffic model (label entries and
+    # 16-byte table quarters the scans read, entries appended, CSR entries the
+    # fused pushes read; the message atomics are not counted), time from HIP
+    # events on the build stream
+    check_ms = np.mean([i["phase_ms"]["check"] for i in prof])
+    check_launches = info["phase_launches"]["check"]
+    check_bytes = (4 * info["check_entries_read"] + 16 * info["check_table_reads"]
+                   + 4 * info["accepted"] + 4 * info["check_push_edges"])
+    check_gbs = check_bytes / (check_ms / 1e3) / 1e9
+    q_bytes = w["pairs"] * (8 + 32 + 4) + 4 * cons
+    q_gbs = q_bytes / (np.median(query_ms) / 1e3) / 1e9
+    achievable = stream_read_gbs(args.stream_gib)
+    print("bench: streaming read done", file=sys.stderr, flush=True)
+
+    tr_check = measured_traffic("k_check_push", args.workload)
+    tr_query = measured_traffic("k_query_group", args.workload)
+    res = {
+        "metric": "index build s + label entries/s; batched queries/s with p50/p99 latency",
+        "value": value,
+        "unit": "label entries/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": float(np.mean(step_ms)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload} label build + {w['pairs']} query pairs", "n": g.n,
+                   "undirected_edges": g.num_edges, "batch_size": args.batch_size, "query_pairs": w["pairs"],
+                   "order": "degree descending, ties by id"},
+        "build_s": float(np.median(build_ms) / 1e3),
+        "build_s_mean": float(np.mean(build_ms) / 1e3),
+        "label_entries": total,
+        "label_bytes": info["label_bytes"],
+        "queries_per_s": qps,
+        "query_batch_ms_p50": float(np.percentile(query_ms, 50)),
+        "query_batch_ms_p99": float(np.percentile(query_ms, 99)),
+        "query_latency_note": "p50/p99 over the timed launches of the whole configured pair batch (one request "
+                              "of all pairs); per-request latencies of a mixed stream come from --mode serve",
+        "build_phase_ms": {k: round(x, 3) for k, x in info["phase_ms"].items()},
+        "profiled_build_s": float(np.median([i["build_ms"] for i in prof]) / 1e3),
+        "rounds": info["rounds"], "batches": info["batches"], "candidates": info["candidates"],
+        "parity": parity,
+        "roofline": {"kernel": "k_check_push", "bound": "hbm", "achieved": check_gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": check_gbs / HBM_PEAK_GBS,
+                     "traffic": tr_check["bytes"] if tr_check else None,
+                     "launches_per_step": check_launches,
+                     "avg_launch_us": check_ms * 1e3 / max(check_launches, 1),
+                     "bytes_per_step": check_bytes,
+                     "timing": "HIP events around every k_check_push launch on the build stream, over --steps "
+                               "profiled builds run right after the timed steps"},
+        "roofline_query": {"kernel": "k_query_group", "bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": q_gbs / HBM_PEAK_GBS,
+                           "achievable": achievable["best_GBs"],
+                           "frac_of_achievable": q_gbs / achievable["best_GBs"],
+                           "achievable_measure": achievable,
+                           "traffic": tr_query["bytes"] if tr_query else None,
+                           "traffic_GBs": (tr_query["bytes"] / (np.median(query_ms) / 1e3) / 1e9) if tr_query
+                           else None,
+                           "bytes_per_launch": q_bytes, "entries_consumed": cons,
+                           "bytes_model": "per pair 8 B ids + 32 B offsets + 4 B answer, plus 4 B per label entry "
+                                          "a sequential merge reads (hub rank <= the smaller list end)"},
+    }
+    # Table 3's quantities: sum of |L(v)| over positive / negative checks
+    res["check_cost"] = {"bvc_pos": info["check_cost_pos"], "bvc_neg": info["check_cost_neg"]}
+    idx.free()
+    if not args.no_cpu_baseline:
+        budget = 0.0 if g.n <= (1 << 16) else args.cpu_budget
+        res["cpu_baseline"] = cpu_baseline(g, order, total, u, v, budget, gpu_labels)
+        pc = res["cpu_baseline"].get("pll_check_cost")
+        if pc:
+            res["check_cost"].update({"pll_pos": pc["pos"], "pll_neg": pc["neg"],
+                                      "pos_ratio_pll_over_bvc": pc["pos"] / max(info["check_cost_pos"], 1),
+                                      "neg_ratio_pll_over_bvc": pc["neg"] / max(info["check_cost_neg"], 1)})
+    print(json.dumps(res), flush=True)
+    if args.calibrate:
+        calibrate()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat16", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-budget", type=float, default=20.0,
+                    help="seconds of host time for the oracle build sample of graphs it cannot build whole quickly")
+    ap.add_argument("--stream-gib", type=float, default=4.0,
+                    help="size of the buffer the streaming-read reference kernel reads")
     ap.add_argument("--batch-size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="build",
@@ -691,132 +942,7 @@ def main():
             calibrate()
         return
 
-    import numpy as np
-    import torch
-    import synth
-    import paper_1906_12018_amd as pll
-
-    w = WORKLOADS[args.workload]
-    dev = torch.device("cuda:0")
-    g = make_graph(w)
-    order = synth.degree_order(g)
-    rp, cl = pll.graph_to_device(g, dev)
-    od = torch.from_numpy(order.view(np.int32)).to(dev)
-    u, v = synth.query_pairs(g.n, w["pairs"], seed=2)
-    du = torch.from_numpy(u.view(np.int32)).to(dev)
-    dv = torch.from_numpy(v.view(np.int32)).to(dev)
-    out = torch.empty_like(du)
-    torch.cuda.synchronize()
-
-    # timed steps: builds without per-phase events (the events add about a
-    # fifth to an R-MAT-16 build); then the same number of profiled builds
-    # whose HIP events on the build stream give the per-kernel times
-    build_ms, query_ms, step_ms, infos = [], [], [], []
-    ref = None
-    for it in range(args.warmup + args.steps):
-        timed = it >= args.warmup
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        idx = pll.build_labels(rp, cl, od, batch_size=args.batch_size, flags=0)
-        t1 = time.perf_counter()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        idx.query(du, dv, out=out)
-        e1.record()
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        info = idx.info()
-        if ref is None:
-            ref = (info["total_entries"], out.clone())
-        else:
-            assert info["total_entries"] == ref[0] and torch.equal(out, ref[1]), "steps disagree"
-        if timed:
-            build_ms.append((t1 - t0) * 1e3)
-            query_ms.append(e0.elapsed_time(e1))
-            step_ms.append((t2 - t0) * 1e3)
-            infos.append(info)
-        if it < args.warmup + args.steps - 1:
-            idx.free()
-    prof = []
-    for _ in range(args.steps):
-        pidx = pll.build_labels(rp, cl, od, batch_size=args.batch_size, flags=pll.FLAG_PROFILE)
-        prof.append(pidx.info())
-        assert prof[-1]["total_entries"] == ref[0], "profiled build disagrees"
-        pidx.free()
-
-    info = prof[-1]
-    total = info["total_entries"]
-    K = args.steps
-    sum_build_s = sum(build_ms) / 1e3
-    value = total * K / sum_build_s
-    qps = w["pairs"] / (np.median(query_ms) / 1e3)
-
-    # roofline, dominant kernel: the fused pruning check and push
-    # (k_check_push), bytes per the kernel's traffic model (label entries and
-    # 16-byte table quarters the scans read, entries appended, CSR entries the
-    # fused pushes read; the message atomics are not counted), time from HIP
-    # events on the build stream
-    check_ms = np.mean([i["phase_ms"]["check"] for i in prof])
-    check_launches = info["phase_launches"]["check"]
-    check_bytes = (4 * info["check_entries_read"] + 16 * info["check_table_reads"]
-                   + 4 * info["accepted"] + 4 * info["check_push_edges"])
-    check_gbs = check_bytes / (check_ms / 1e3) / 1e9
-    cons = consumed_for(idx, g, order, u, v)
-    q_bytes = w["pairs"] * (8 + 32 + 4) + 4 * cons
-    q_gbs = q_bytes / (np.median(query_ms) / 1e3) / 1e9
-
-    tr_check = measured_traffic("k_check_push", args.workload)
-    tr_query = measured_traffic("k_query_group", args.workload)
-    res = {
-        "metric": "index build s + label entries/s; batched queries/s with p50/p99 latency",
-        "value": value,
-        "unit": "label entries/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": float(np.mean(step_ms)),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u8",
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload} label build + {w['pairs']} query pairs", "n": g.n,
-                   "undirected_edges": g.num_edges, "batch_size": args.batch_size, "query_pairs": w["pairs"],
-                   "order": "degree descending, ties by id"},
-        "build_s": float(np.median(build_ms) / 1e3),
-        "label_entries": total,
-        "label_bytes": info["label_bytes"],
-        "queries_per_s": qps,
-        "query_batch_ms_p50": float(np.percentile(query_ms, 50)),
-        "query_batch_ms_p99": float(np.percentile(query_ms, 99)),
-        "build_phase_ms": {k: round(x, 3) for k, x in info["phase_ms"].items()},
-        "profiled_build_s": float(np.median([i["build_ms"] for i in prof]) / 1e3),
-        "rounds": info["rounds"], "batches": info["batches"], "candidates": info["candidates"],
-        "roofline": {"kernel": "k_check_push", "bound": "hbm", "achieved": check_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": check_gbs / HBM_PEAK_GBS,
-                     "traffic": tr_check["bytes"] if tr_check else None,
-                     "launches_per_step": check_launches,
-                     "avg_launch_us": check_ms * 1e3 / max(check_launches, 1),
-                     "bytes_per_step": check_bytes,
-                     "timing": "HIP events around every k_check_push launch on the build stream, over --steps "
-                               "profiled builds run right after the timed steps"},
-        "roofline_query": {"kernel": "k_query_group", "bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": q_gbs / HBM_PEAK_GBS,
-                           "traffic": tr_query["bytes"] if tr_query else None,
-                           "bytes_per_launch": q_bytes, "entries_consumed": cons},
-    }
-    # Table 3's quantities: sum of |L(v)| over positive / negative checks
-    res["check_cost"] = {"bvc_pos": info["check_cost_pos"], "bvc_neg": info["check_cost_neg"]}
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(g, order, total, u, v)
-        pc = res["cpu_baseline"]["pll_check_cost"]
-        res["check_cost"].update({"pll_pos": pc["pos"], "pll_neg": pc["neg"],
-                                  "pos_ratio_pll_over_bvc": pc["pos"] / max(info["check_cost_pos"], 1),
-                                  "neg_ratio_pll_over_bvc": pc["neg"] / max(info["check_cost_neg"], 1)})
-    idx.free()
-    print(json.dumps(res), flush=True)
-    if args.calibrate:
-        calibrate()
+    build_mode(args)
 
 
 if __name__ == "__main__":

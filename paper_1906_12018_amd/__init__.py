@@ -36,7 +36,7 @@ EXPORTED_SYMBOLS = (
     "pll_export_labels_side", "pll_export_bp", "pll_index_set_query_lanes",
     "pll_build_labels_batched", "pll_index_free", "pll_status_string",
     "pll_server_create", "pll_server_add_index", "pll_server_index", "pll_server_submit", "pll_server_poll",
-    "pll_server_replay", "pll_server_destroy",
+    "pll_server_replay", "pll_server_destroy", "pll_bench_stream_read",
 )
 REQ_QUERY, REQ_BUILD = 0, 1
 
@@ -157,6 +157,8 @@ class Result(ctypes.Structure):
         ("t_arrival", ctypes.c_double),
         ("t_admit", ctypes.c_double),
         ("t_done", ctypes.c_double),
+        ("t_dev_start", ctypes.c_double),
+        ("t_dev_end", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -216,6 +218,8 @@ def load_library(path: str = LIB_PATH):
     lib.pll_server_replay.restype = ctypes.c_int
     lib.pll_server_destroy.argtypes = [P]
     lib.pll_server_destroy.restype = None
+    lib.pll_bench_stream_read.argtypes = [P, U64, P, U32, P]
+    lib.pll_bench_stream_read.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -443,6 +447,19 @@ def build_labels_batched(graphs, batch_size: int = DEFAULT_BATCH, flags: int = F
     return [Index(outs[i], dev) for i in range(len(graphs))]
 
 
+def stream_read(buf: torch.Tensor, sink: torch.Tensor, workgroups: int = 0, stream=None) -> None:
+    """Enqueue pll_bench_stream_read over the bytes of ``buf`` (a contiguous
+    device tensor, size a multiple of 16); ``sink`` is a device int64 tensor
+    whose first element receives the XOR of the words."""
+    if not buf.is_cuda or not sink.is_cuda or sink.dtype != torch.int64 or not buf.is_contiguous():
+        raise PllError(PLL_EINVAL, "stream_read needs a contiguous device buffer and an int64 device sink")
+    nbytes = buf.numel() * buf.element_size()
+    rc = load_library().pll_bench_stream_read(buf.data_ptr(), nbytes, sink.data_ptr(), workgroups,
+                                              _stream_handle(stream))
+    if rc:
+        raise PllError(rc, "pll_bench_stream_read")
+
+
 def graph_to_device(g, device="cuda"):
     """(row_ptr, col) numpy CSR -> device tensors of the binding's dtypes."""
     import numpy as np
@@ -471,20 +488,18 @@ class Server:
             raise PllError(rc, "pll_server_create")
         self._h = h
         self._keep = {}
-        self._indexes = []  # non-owned indexes stay alive as long as the server
 
     def add_index(self, index: Index, take_ownership: bool = False) -> int:
-        """Make `index` resident.  Without ownership the server keeps a
-        reference to the Python object, so its device memory outlives every
-        query the server runs on it."""
+        """Make `index` resident.  Without ownership the C server takes a
+        reference of its own, so `index` may be freed (or collected) at any
+        time: its labels stay resident until the server is closed.  With
+        ownership the handle passes to the server."""
         iid = ctypes.c_uint32()
         rc = load_library().pll_server_add_index(self._h, index.handle, int(take_ownership), ctypes.byref(iid))
         if rc:
             raise PllError(rc, "pll_server_add_index")
         if take_ownership:
             index._h = ctypes.c_void_p(0)
-        else:
-            self._indexes.append(index)
         return iid.value
 
     def index(self, index_id: int) -> "Index":
@@ -574,7 +589,6 @@ class Server:
             load_library().pll_server_destroy(self._h)
             self._h = None
             self._keep.clear()
-            self._indexes.clear()
 
     def __del__(self):
         try:

@@ -1,5 +1,6 @@
 """Host-side checks of the C ABI boundary (no GPU needed, no compute calls)."""
 import ctypes
+import glob
 import os
 import re
 import subprocess
@@ -9,13 +10,15 @@ import pytest
 import paper_1906_12018_amd as pll
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "pll.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(pll_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(pll_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -42,7 +45,7 @@ def test_status_strings():
     assert pll.status_string(99) == "unknown status"
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
     # sizes of the C structs as laid out by the compiler for the header
     src = r'''
 #include <stdio.h>
@@ -53,8 +56,7 @@ int main(void) {
   return 0;
 }
 '''
-    exe = os.path.join(ROOT, "_work", "layout_probe")
-    os.makedirs(os.path.dirname(exe), exist_ok=True)
+    exe = str(tmp_path / "layout_probe")
     c = exe + ".c"
     with open(c, "w") as f:
         f.write(src)

@@ -307,6 +307,8 @@ int pll_export_labels_side(const pll_index* idx, uint32_t side, uint64_t* d_offs
 int pll_build_labels_batched(uint32_t count, const pll_graph_desc* graphs, const pll_build_opts* opts,
                              hipStream_t stream, pll_index** outs);
 
+/* Drop the caller's reference to an index.  Its device memory is released once no server keeps it
+   resident (pll_server_add_index without take_ownership holds a reference of its own). */
 void pll_index_free(pll_index* idx);
 
 const char* pll_status_string(int status);
@@ -364,11 +366,17 @@ typedef struct {
     uint32_t index_id;         /* query: the index asked; build: the new resident index */
     uint32_t batch_requests;   /* query: requests packed in the batch that carried its first pairs */
     double t_arrival, t_admit, t_done;
+    double t_dev_start, t_dev_end; /* device time, seconds after the server was created: query, from the start of
+                                      the first to the end of the last query kernel that carried its pairs; build,
+                                      the launch that labeled it (its upload included); -1 when not known.
+                                      Intervals of different requests that overlap ran on the device together */
 } pll_result;
 
 int pll_server_create(const pll_server_opts* opts, pll_server** out);
-/* Make `idx` resident.  With take_ownership the server frees it in pll_server_destroy; without it the
-   caller must keep `idx` alive (not pll_index_free it) until pll_server_destroy has returned. */
+/* Make `idx` resident.  With take_ownership the caller hands its reference to the server (and must not
+   use or free the handle afterwards); without it the server takes a reference of its own, so the caller
+   may pll_index_free its handle at any time: the labels stay resident until pll_server_destroy drops the
+   server's reference. */
 int pll_server_add_index(pll_server* server, pll_index* idx, int take_ownership, uint32_t* index_id);
 /* The resident index with this id (owned by the server if the server built it). */
 int pll_server_index(pll_server* server, uint32_t index_id, pll_index** idx);

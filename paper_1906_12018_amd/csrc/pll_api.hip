@@ -168,7 +168,9 @@ int pll_build_labels_batched(uint32_t count, const pll_graph_desc* graphs, const
     }
 }
 
-void pll_index_free(pll_index* idx) { free_index(idx); }
+void pll_index_free(pll_index* idx) {
+    if (idx && idx->refs.fetch_sub(1, std::memory_order_acq_rel) == 1) free_index(idx);
+}
 
 const char* pll_status_string(int status) {
     switch (status) {

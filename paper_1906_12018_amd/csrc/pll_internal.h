@@ -182,6 +182,20 @@ __device__ inline uint32_t wave_max32(uint32_t x) {
     return x;
 }
 
+// OR over the 64 lanes by DPP moves (the whole wave must be active); the
+// result is wave-uniform.  row_shr:1,2,4,8 leave each 16-lane row's OR in
+// its lane 15; row_bcast:15 adds row 0 into row 1 and row 2 into row 3;
+// row_bcast:31 adds rows 0-1 into rows 2-3, so lane 63 holds the total.
+__device__ inline uint32_t wave_or32_dpp(uint32_t x) {
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);  // row_shr:1
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);  // row_shr:2
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);  // row_shr:4
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);  // row_shr:8
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false); // row_bcast:15, rows 1, 3
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false); // row_bcast:31, rows 2, 3
+    return readlane32(x, 63);
+}
+
 // Exclusive prefix sum over the 64 lanes.
 __device__ inline uint32_t wave_excl_scan32(uint32_t x) {
     const uint32_t l = lane_id();
@@ -259,6 +273,10 @@ struct pll_shared_store {
 // label per vertex (d_off / d_ent); a directed one keeps L_in there and L_out
 // in d_off_out / d_ent_out.
 struct pll_index {
+    // references held on the index: 1 for the handle the build returned, plus
+    // one per server that keeps it resident without owning it; the device
+    // memory is released when the last one is dropped (pll_index_free)
+    std::atomic<uint32_t> refs{1};
     int device;
     uint32_t n;
     uint64_t total;
@@ -279,3 +297,6 @@ struct pll_index {
     ulonglong2* d_bp_sets;     // [n * t] (S^-1, S^0)
     pll_index_info info;
 };
+
+// Take one more reference on an index (dropped again by pll_index_free).
+inline void pll_index_retain(pll_index* idx) { idx->refs.fetch_add(1, std::memory_order_relaxed); }

@@ -38,6 +38,9 @@ struct Req {
     uint64_t remaining = 0;  // pairs not yet answered
     uint32_t batch_requests = 0;
     uint32_t new_index = 0;
+    // device interval (seconds after the server's reference event) of the
+    // query kernels that carried its pairs, or of the build launch of a job
+    double dev_start = -1, dev_end = -1;
 };
 
 struct Member {
@@ -50,6 +53,7 @@ struct Member {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    hipEvent_t k0 = nullptr, k1 = nullptr;  // around the batch's query kernel (timing events)
     uint32_t *h_u = nullptr, *h_v = nullptr, *h_out = nullptr;
     uint32_t *d_u = nullptr, *d_v = nullptr, *d_out = nullptr;
     uint64_t cap = 0;
@@ -57,9 +61,11 @@ struct Slot {
     std::vector<Member> members;
 };
 
+// The server holds one reference on every resident index: the caller's
+// handed-over reference (take_ownership, and the indexes the server built),
+// or one it takes itself; pll_server_destroy drops them all.
 struct IndexEntry {
     pll_index* idx = nullptr;
-    bool owned = false;
 };
 
 uint64_t build_bytes_estimate(uint32_t n, uint64_t nnz, uint32_t b) {
@@ -92,7 +98,14 @@ struct pll_server {
     bool stop = false;
     std::vector<Slot> slots;
     hipStream_t build_stream = nullptr;
+    hipEvent_t ev_ref = nullptr;  // device time origin of the results' dev_start / dev_end
     std::thread sched, builder;
+
+    // seconds from ev_ref to a completed timing event (-1 if unavailable)
+    double dev_time(hipEvent_t e) const {
+        float ms = 0;
+        return hipEventElapsedTime(&ms, ev_ref, e) == hipSuccess ? ms / 1e3 : -1.0;
+    }
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 
@@ -112,14 +125,23 @@ struct pll_server {
             bool any_busy = false;
             for (Slot& s : slots) {
                 if (!s.busy) continue;
-                if (hipEventQuery(s.done) != hipSuccess) {
+                const hipError_t q = hipEventQuery(s.done);
+                if (q == hipErrorNotReady) {
                     any_busy = true;
                     continue;
                 }
+                // finished, or failed: a device error ends the batch's requests
+                // with PLL_EDEVICE instead of keeping the slot busy for ever
+                const bool ok = q == hipSuccess;
+                const double d0 = ok ? dev_time(s.k0) : -1, d1 = ok ? dev_time(s.k1) : -1;
                 for (const Member& m : s.members) {
-                    std::memcpy(m.req->r.h_out + m.src, s.h_out + m.dst, sizeof(uint32_t) * m.count);
-                    m.req->remaining -= m.count;
-                    if (m.req->remaining == 0) finish(m.req, PLL_OK);
+                    Req* r = m.req;
+                    if (ok) std::memcpy(r->r.h_out + m.src, s.h_out + m.dst, sizeof(uint32_t) * m.count);
+                    else r->status = PLL_EDEVICE;
+                    if (r->dev_start < 0 || (d0 >= 0 && d0 < r->dev_start)) r->dev_start = d0;
+                    r->dev_end = std::max(r->dev_end, d1);
+                    r->remaining -= m.count;
+                    if (r->remaining == 0) finish(r, r->status);
                 }
                 s.members.clear();
                 s.busy = false;
@@ -173,7 +195,9 @@ struct pll_server {
             if (m.src == 0) m.req->batch_requests = nreq;
         bool ok = hipMemcpyAsync(s.d_u, s.h_u, sizeof(uint32_t) * used, hipMemcpyHostToDevice, s.stream) == hipSuccess &&
                   hipMemcpyAsync(s.d_v, s.h_v, sizeof(uint32_t) * used, hipMemcpyHostToDevice, s.stream) == hipSuccess &&
+                  hipEventRecord(s.k0, s.stream) == hipSuccess &&
                   pll_query_launch(idx, used, s.d_u, s.d_v, s.d_out, s.stream) == PLL_OK &&
+                  hipEventRecord(s.k1, s.stream) == hipSuccess &&
                   hipMemcpyAsync(s.h_out, s.d_out, sizeof(uint32_t) * used, hipMemcpyDeviceToHost, s.stream) == hipSuccess &&
                   hipEventRecord(s.done, s.stream) == hipSuccess;
         if (!ok) {
@@ -236,12 +260,20 @@ struct pll_server {
             lk.unlock();
             std::vector<pll_index*> idx(take.size(), nullptr);
             std::vector<int> rc(take.size(), PLL_OK);
+            const bool timed = hipEventRecord(b0, build_stream) == hipSuccess;
             build_jobs(take, b, idx.data(), rc.data());
+            const bool timed_end = timed && hipEventRecord(b1, build_stream) == hipSuccess;
+            (void)hipStreamSynchronize(build_stream);
+            const double d0 = timed_end ? dev_time(b0) : -1, d1 = timed_end ? dev_time(b1) : -1;
             lk.lock();
+            for (Req* q : take) {
+                q->dev_start = d0;
+                q->dev_end = d1;
+            }
             for (size_t i = 0; i < take.size(); ++i) {
                 if (rc[i] == PLL_OK) {
                     const uint32_t id = next_index++;
-                    indexes[id] = IndexEntry{idx[i], true};
+                    indexes[id] = IndexEntry{idx[i]};
                     take[i]->new_index = id;
                 }
                 finish(take[i], rc[i]);
@@ -252,6 +284,8 @@ struct pll_server {
     static constexpr size_t kMaxJobsPerLaunch = 256;
     static constexpr uint32_t kBuildWorkgroups = 128;  // of 1,024 threads: a quarter of the device's wave slots
     static constexpr uint32_t kLargeGraph = 1u << 16;  // built alone, grid-wide
+
+    hipEvent_t b0 = nullptr, b1 = nullptr;  // around each build launch (timing events)
 
     // device staging for the host CSRs of admitted jobs (grows, kept)
     void* stage = nullptr;
@@ -333,7 +367,6 @@ struct pll_server {
             rc[i] = pll_build_one(r.n, r.nnz, desc[i].d_row_ptr, desc[i].d_col, desc[i].d_order, &o, build_stream,
                                   &idx[i]);
         }
-        (void)hipStreamSynchronize(build_stream);
     }
 };
 
@@ -351,6 +384,8 @@ void destroy_server(pll_server* s) {
     for (Slot& sl : s->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.k0) (void)hipEventDestroy(sl.k0);
+        if (sl.k1) (void)hipEventDestroy(sl.k1);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.h_u) (void)hipHostFree(sl.h_u);
         if (sl.h_v) (void)hipHostFree(sl.h_v);
@@ -362,8 +397,10 @@ void destroy_server(pll_server* s) {
     if (s->build_stream) (void)hipStreamSynchronize(s->build_stream);
     if (s->stage) (void)hipFree(s->stage);
     if (s->build_stream) (void)hipStreamDestroy(s->build_stream);
-    for (auto& kv : s->indexes)
-        if (kv.second.owned) pll_index_free(kv.second.idx);
+    if (s->b0) (void)hipEventDestroy(s->b0);
+    if (s->b1) (void)hipEventDestroy(s->b1);
+    if (s->ev_ref) (void)hipEventDestroy(s->ev_ref);
+    for (auto& kv : s->indexes) pll_index_free(kv.second.idx);  // the server's reference
     for (auto& kv : s->all) delete kv.second;
     delete s;
 }
@@ -405,6 +442,8 @@ void fill_result(const Req* q, pll_result* r) {
     r->t_arrival = q->t_arrival;
     r->t_admit = q->t_admit;
     r->t_done = q->t_done;
+    r->t_dev_start = q->dev_start;
+    r->t_dev_end = q->dev_end;
 }
 
 }  // namespace
@@ -431,11 +470,15 @@ int pll_server_create(const pll_server_opts* opts, pll_server** out) {
         return PLL_EDEVICE;
     }
     s->slots.resize(nslots);
-    bool ok = hipStreamCreateWithFlags(&s->build_stream, hipStreamNonBlocking) == hipSuccess;
+    bool ok = hipStreamCreateWithFlags(&s->build_stream, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreate(&s->b0) == hipSuccess && hipEventCreate(&s->b1) == hipSuccess &&
+              hipEventCreate(&s->ev_ref) == hipSuccess && hipEventRecord(s->ev_ref, s->build_stream) == hipSuccess &&
+              hipEventSynchronize(s->ev_ref) == hipSuccess;
     for (Slot& sl : s->slots) {
         sl.cap = cap;
         ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
+             hipEventCreate(&sl.k0) == hipSuccess && hipEventCreate(&sl.k1) == hipSuccess &&
              hipHostMalloc((void**)&sl.h_u, 4 * cap, hipHostMallocDefault) == hipSuccess &&
              hipHostMalloc((void**)&sl.h_v, 4 * cap, hipHostMallocDefault) == hipSuccess &&
              hipHostMalloc((void**)&sl.h_out, 4 * cap, hipHostMallocDefault) == hipSuccess &&
@@ -461,7 +504,8 @@ int pll_server_add_index(pll_server* s, pll_index* idx, int take_ownership, uint
     if (!s || !idx || !index_id) return PLL_EINVAL;
     std::lock_guard<std::mutex> lk(s->mu);
     const uint32_t id = s->next_index++;
-    s->indexes[id] = IndexEntry{idx, take_ownership != 0};
+    if (!take_ownership) pll_index_retain(idx);  // the caller keeps its own reference
+    s->indexes[id] = IndexEntry{idx};
     *index_id = id;
     return PLL_OK;
 }

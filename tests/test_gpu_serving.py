@@ -9,6 +9,11 @@ import paper_1906_12018_amd as pll
 import synth
 from gpu_util import assert_labels_equal, build
 
+
+def overlapping(a, b):
+    """Device intervals (t_dev_start, t_dev_end) that share some time."""
+    return a[0] < b[1] and b[0] < a[1]
+
 pytestmark = pytest.mark.gpu
 
 
@@ -73,6 +78,7 @@ def test_alone_equals_mix(two_indexes):
     # requests were packed together while others were on the device
     q_res = [r for r in res if r["kind"] == pll.REQ_QUERY]
     assert max(r["batch_requests"] for r in q_res) > 1
+    assert all(0 <= r["t_dev_start"] <= r["t_dev_end"] for r in res)
     assert all(r["t_done"] >= r["t_admit"] >= r["t_arrival"] - 1e-6 for r in q_res)
     # the built indexes are resident and exact
     b_res = [r for r in res if r["kind"] == pll.REQ_BUILD]
@@ -137,4 +143,24 @@ def test_labeling_jobs_admitted_together():
         rid = srv.submit(pll.Server.query_request(r["index_id"], u, v, out))
         assert srv.wait(rid)["status"] == pll.PLL_OK
         assert np.array_equal(out, oracle.query(want, u, v))
+    srv.close()
+
+
+def test_resident_index_outlives_the_callers_free(two_indexes):
+    """A server keeps its own reference on an index it does not own: the
+    caller may free its handle while the index is resident, and queries on
+    it stay exact until the server is closed (pll_server_add_index)."""
+    (ga, oa, la), _ = two_indexes
+    srv = pll.Server(slots=2)
+    idx = build(ga, oa)
+    iid = srv.add_index(idx)
+    idx.free()  # the caller's reference only
+    for k in range(3):
+        u, v = synth.query_pairs(ga.n, 5000, seed=40 + k)
+        out = np.zeros(len(u), dtype=np.uint32)
+        rid = srv.submit(pll.Server.query_request(iid, u, v, out))
+        assert srv.wait(rid)["status"] == pll.PLL_OK
+        assert np.array_equal(out, oracle.query(la, u, v))
+    view = srv.index(iid)
+    assert view.info()["total_entries"] == la.total
     srv.close()

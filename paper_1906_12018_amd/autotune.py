@@ -7,8 +7,9 @@ tiles, 64*ceil(b/64) bytes per row, and of the candidate bit-vectors), the
 gang scale (how many workgroups each graph gets relative to its share of the
 estimated work, i.e. the work per wavefront) and the largest gang.  Every
 candidate is timed on the caller's graphs through the C ABI; a candidate
-whose label totals differ from the others is rejected (labels are invariant
-under all of these, so a difference would be a bug).  Results are cached in a
+whose exported labels differ in any entry from the first candidate's is
+rejected (labels are invariant under all of these, so a difference would be
+a bug).  Results are cached in a
 JSON file keyed by a coarse signature of the workload.
 
 For queries it tunes the lanes per pair G of an index (the merge reads
@@ -80,32 +81,48 @@ def cached_config(graphs):
     return dict(ent["best"]) if ent else None
 
 
+def _exports(idxs):
+    """Every index's exported labels (offsets, hubs, dists), kept on the device."""
+    out = []
+    for i in idxs:
+        ex = i.export()
+        out.append((ex.offsets, ex.hubs, ex.dists))
+    return out
+
+
+def _same_labels(a, b) -> bool:
+    return len(a) == len(b) and all(torch.equal(x, y) for p, q in zip(a, b) for x, y in zip(p, q))
+
+
 def tune_batched(graphs, candidates=None, reps: int = 2, flags: int = 0, save: bool = True, verbose: bool = False):
     """Time every candidate on `graphs` (median of `reps` builds after one
-    warm-up build) and return {"best": params, "results": [...]}."""
+    warm-up build) and return {"best": params, "results": [...]}.  The labels
+    of every candidate's warm-up build must equal the first candidate's entry
+    for entry (they do not depend on any tuned parameter); a candidate that
+    changes them raises."""
     candidates = candidates or DEFAULT_CANDIDATES
-    results, totals = [], None
+    results, ref = [], None
     for cand in candidates:
         times = []
-        tot = None
         for rep in range(reps + 1):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             idxs = build_labels_batched(graphs, flags=flags, **cand)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            t = [i.info()["total_entries"] for i in idxs]
+            if rep == 0:
+                labels = _exports(idxs)
+                if ref is None:
+                    ref = labels
+                elif not _same_labels(labels, ref):
+                    for i in idxs:
+                        i.free()
+                    raise RuntimeError(f"candidate {cand} produced different labels")
+                del labels
             for i in idxs:
                 i.free()
-            tot = t if tot is None else tot
-            if t != tot:
-                raise RuntimeError(f"label totals changed between runs of {cand}")
             if rep > 0:
                 times.append(dt)
-        if totals is None:
-            totals = tot
-        elif tot != totals:
-            raise RuntimeError(f"candidate {cand} produced different labels")
         times.sort()
         med = times[len(times) // 2]
         results.append(dict(params=cand, seconds=med))

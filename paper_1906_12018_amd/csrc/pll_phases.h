@@ -81,11 +81,12 @@ __device__ inline uint32_t quarters(uint64_t x) {
            ((uint32_t)((x & 0xFFFF00000000ull) != 0) << 2) | ((uint32_t)((x >> 48) != 0) << 3);
 }
 
-// OR over the 64 lanes (DPP wave reduction); the result is wave-uniform.
+// OR over the 64 lanes (DPP wave reduction, the whole wave active); the
+// result is wave-uniform.
 __device__ inline uint64_t wave_or64_u(uint64_t x) {
-    const unsigned lo = __reduce_or_sync(~0ull, (unsigned)x);
-    const unsigned hi = __reduce_or_sync(~0ull, (unsigned)(x >> 32));
-    return ((uint64_t)__builtin_amdgcn_readfirstlane(hi) << 32) | (uint32_t)__builtin_amdgcn_readfirstlane(lo);
+    const uint32_t lo = wave_or32_dpp((uint32_t)x);
+    const uint32_t hi = wave_or32_dpp((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Scan the label list arena[off .. off+len) of one vertex v.  Lane w (< W)

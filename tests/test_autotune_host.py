@@ -38,3 +38,43 @@ def test_index_key_buckets():
     c = autotune.index_key(_FakeIndex(1 << 20, 252_000_000))
     d = autotune.index_key(_FakeIndex(65536, 5_000_000, bp=16))
     assert a == b and a != c and a != d
+
+
+class _FakeExport:
+    def __init__(self, off, hubs, dists):
+        self.offsets, self.hubs, self.dists = off, hubs, dists
+
+
+class _FakeBuilt:
+    def __init__(self, ex):
+        self._ex = ex
+
+    def export(self):
+        return self._ex
+
+    def info(self):
+        return {"total_entries": int(self._ex.hubs.numel())}
+
+    def free(self):
+        pass
+
+
+def test_tuner_rejects_same_size_but_different_labels(monkeypatch, tmp_path):
+    """A candidate whose labels keep every list length but change one
+    distance is rejected; identical labels pass."""
+    import pytest
+    monkeypatch.setenv("PLL_TUNE_CACHE", str(tmp_path / "t.json"))
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    good = _FakeExport(torch.tensor([0, 2, 3]), torch.tensor([0, 1, 1], dtype=torch.int32),
+                       torch.tensor([0, 1, 0], dtype=torch.uint8))
+    bad = _FakeExport(good.offsets.clone(), good.hubs.clone(), torch.tensor([0, 2, 0], dtype=torch.uint8))
+
+    def fake_build(graphs, flags=0, batch_size=0, **kw):
+        return [_FakeBuilt(bad if batch_size == 999 else good)]
+
+    monkeypatch.setattr(autotune, "build_labels_batched", fake_build)
+    gs = [fake(2, 2)]
+    ok = autotune.tune_batched(gs, candidates=[dict(batch_size=256), dict(batch_size=512)], reps=1, save=False)
+    assert ok["best"] in (dict(batch_size=256), dict(batch_size=512))
+    with pytest.raises(RuntimeError, match="different labels"):
+        autotune.tune_batched(gs, candidates=[dict(batch_size=256), dict(batch_size=999)], reps=1, save=False)

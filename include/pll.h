@@ -60,6 +60,7 @@ extern "C" {
 #define PLL_ENOSPC 3  /* the label arena given in pll_build_opts is too small; retry larger */
 #define PLL_EDIST 4   /* some shortest distance is 255 or more (uint8 labels) */
 #define PLL_EDEVICE 5 /* a HIP runtime error */
+#define PLL_ESCRATCH 6 /* pll_build_labels_noalloc: the graph does not fit its fixed scratch */
 
 #define PLL_DIST_INF 0xFFFFFFFFu
 
@@ -164,6 +165,41 @@ typedef struct {
  */
 int pll_build_labels(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
                      const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out);
+
+/*
+ * Allocation-free build, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the labels pll_build_labels would build, written straight into
+ * the caller's buffers in the form pll_export_labels gives, with no device
+ * or pinned-host allocation and no free.
+ *   n, nnz, d_row_ptr, d_col, d_order, opts
+ *               as for pll_build_labels; opts->batch_size and the flags
+ *               PLL_FLAG_VALIDATE, PLL_FLAG_RECHECK and PLL_FLAG_RELAXED
+ *               apply; other flags, bp_roots or arena_entries give
+ *               PLL_EINVAL; the other fields are ignored
+ *   d_offsets   uint64[n+1]: list offsets by vertex id
+ *   d_hubs      uint32[capacity]: hub vertex ids, ascending hub rank per list
+ *   d_dists     uint8[capacity]
+ *   capacity    entries d_hubs and d_dists hold
+ *   total       host pointer; receives the number of label entries, also
+ *               when it exceeds capacity (then PLL_ENOSPC and nothing is
+ *               written; call again with capacity >= *total)
+ * Every working buffer comes from a fixed 64 MiB device array that each GPU
+ * the library runs on holds until the process ends.  A graph whose working
+ * set or labels do not fit it fails with PLL_ESCRATCH before anything is
+ * written: about 16,000 vertices fit at b = 1024 and about 40,000 at
+ * b = 256 (the working set is about 580 + 1.6 b bytes per vertex plus 4
+ * bytes per CSR entry; the rest holds the labels twice).  All
+ * calls on one GPU share that array, and the array keeps the last call's
+ * contents: the library runs one such call at a time per device (calls from
+ * several host threads wait for each other), and everything a call needs
+ * zeroed it clears itself.  The call returns once the outputs are written
+ * (it synchronises `stream`).
+ */
+int pll_build_labels_noalloc(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
+                             const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream,
+                             uint64_t* d_offsets, uint32_t* d_hubs, uint8_t* d_dists, uint64_t capacity,
+                             uint64_t* total);
 
 /*
  * Build the labels of a directed graph (Section 5.1): every vertex v gets

@@ -24,7 +24,7 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpll.so")
 
-PLL_OK, PLL_EINVAL, PLL_ENOMEM, PLL_ENOSPC, PLL_EDIST, PLL_EDEVICE = 0, 1, 2, 3, 4, 5
+PLL_OK, PLL_EINVAL, PLL_ENOMEM, PLL_ENOSPC, PLL_EDIST, PLL_EDEVICE, PLL_ESCRATCH = 0, 1, 2, 3, 4, 5, 6
 DIST_INF = 0xFFFFFFFF
 FLAG_VALIDATE, FLAG_RECHECK, FLAG_RELAXED, FLAG_PROFILE, FLAG_PERSISTENT = 0x1, 0x2, 0x4, 0x8, 0x10
 PHASES = ("prep", "init", "push", "check", "end", "final", "loop")
@@ -36,7 +36,7 @@ EXPORTED_SYMBOLS = (
     "pll_export_labels_side", "pll_export_bp", "pll_index_set_query_lanes",
     "pll_build_labels_batched", "pll_index_free", "pll_status_string",
     "pll_server_create", "pll_server_add_index", "pll_server_index", "pll_server_submit", "pll_server_poll",
-    "pll_server_replay", "pll_server_destroy", "pll_bench_stream_read",
+    "pll_server_replay", "pll_server_destroy", "pll_bench_stream_read", "pll_build_labels_noalloc",
 )
 REQ_QUERY, REQ_BUILD = 0, 1
 
@@ -218,6 +218,9 @@ def load_library(path: str = LIB_PATH):
     lib.pll_server_replay.restype = ctypes.c_int
     lib.pll_server_destroy.argtypes = [P]
     lib.pll_server_destroy.restype = None
+    lib.pll_build_labels_noalloc.argtypes = [U32, U64, P, P, P, ctypes.POINTER(BuildOpts), P, P, P, P, U64,
+                                             ctypes.POINTER(ctypes.c_uint64)]
+    lib.pll_build_labels_noalloc.restype = ctypes.c_int
     lib.pll_bench_stream_read.argtypes = [P, U64, P, U32, P]
     lib.pll_bench_stream_read.restype = ctypes.c_int
     _lib = lib
@@ -372,6 +375,36 @@ def build_labels(row_ptr: torch.Tensor, col: torch.Tensor, order: torch.Tensor, 
     if rc:
         raise PllError(rc, "pll_build_labels")
     return Index(h.value, order.device)
+
+
+def build_labels_noalloc(row_ptr: torch.Tensor, col: torch.Tensor, order: torch.Tensor, offsets: torch.Tensor,
+                         hubs: torch.Tensor, dists: torch.Tensor, batch_size: int = DEFAULT_BATCH,
+                         flags: int = FLAG_VALIDATE, stream=None) -> int:
+    """pll_build_labels_noalloc: the labels of the graph written into the
+    caller's device tensors (offsets int64 [n+1], hubs int32 [capacity],
+    dists uint8 [capacity]) without any device allocation by the library.
+    Returns the number of entries; raises PllError (its ``total`` attribute
+    holds the entries needed when the status is PLL_ENOSPC)."""
+    row_ptr = _dev(row_ptr, torch.int64, "row_ptr")
+    col = _dev(col, torch.int32, "col")
+    order = _dev(order, torch.int32, "order")
+    offsets = _dev(offsets, torch.int64, "offsets")
+    hubs = _dev(hubs, torch.int32, "hubs")
+    dists = _dev(dists, torch.uint8, "dists")
+    n = order.numel()
+    if row_ptr.numel() != n + 1 or offsets.numel() != n + 1:
+        raise PllError(PLL_EINVAL, "row_ptr and offsets must have n + 1 entries")
+    cap = min(hubs.numel(), dists.numel())
+    total = ctypes.c_uint64()
+    o = _opts(batch_size, flags, 0, 0)
+    rc = load_library().pll_build_labels_noalloc(n, col.numel(), row_ptr.data_ptr(), col.data_ptr(), order.data_ptr(),
+                                                 ctypes.byref(o), _stream_handle(stream), offsets.data_ptr(),
+                                                 hubs.data_ptr(), dists.data_ptr(), cap, ctypes.byref(total))
+    if rc:
+        err = PllError(rc, "pll_build_labels_noalloc")
+        err.total = total.value
+        raise err
+    return total.value
 
 
 def build_labels_directed(row_ptr: torch.Tensor, col: torch.Tensor, order: torch.Tensor,

@@ -1,4 +1,5 @@
 // C ABI entry points of libpll (declared in include/pll.h).
+#include <algorithm>
 #include <new>
 
 #include "pll_internal.h"
@@ -54,6 +55,16 @@ void free_index(pll_index* idx) {
 }
 
 }  // namespace
+
+// Labels in the exported form from a final label array: hubs as vertex ids,
+// distances as bytes (used by the allocation-free build).
+int pll_export_launch(uint64_t total, const uint32_t* ent, const uint32_t* order, uint32_t* hubs, uint8_t* dists,
+                      hipStream_t s) {
+    if (total == 0) return PLL_OK;
+    const uint64_t blocks = std::min<uint64_t>((total + kBlock - 1) / kBlock, 65536);
+    k_export<<<(uint32_t)blocks, kBlock, 0, s>>>(total, ent, order, hubs, dists);
+    return hipGetLastError() == hipSuccess ? PLL_OK : PLL_EDEVICE;
+}
 
 extern "C" {
 
@@ -180,6 +191,8 @@ const char* pll_status_string(int status) {
         case PLL_ENOSPC: return "label arena too small; retry with a larger pll_build_opts.arena_entries";
         case PLL_EDIST: return "a shortest distance of 255 or more does not fit the uint8 labels";
         case PLL_EDEVICE: return "HIP runtime error";
+        case PLL_ESCRATCH:
+            return "the graph's working set or labels do not fit the fixed scratch of pll_build_labels_noalloc";
         default: return "unknown status";
     }
 }

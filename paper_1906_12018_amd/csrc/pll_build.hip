@@ -26,6 +26,7 @@
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
 #include <vector>
 
 #include "pll_internal.h"
@@ -761,13 +762,30 @@ __global__ void __launch_bounds__(kBlock) k_final_copy(uint32_t n, const uint32_
 
 // Buffers of one build: workspace from the caching allocator (returned once
 // the stream has drained), outputs from hipMalloc (kept with forget()).
+//
+// With `fixed` set, every block (outputs included) is carved in order out of
+// one region the caller provides and nothing is allocated or freed: blocks
+// live until the region is reused, and a request past its end fails with
+// hipErrorOutOfMemory.
 struct DevAllocs {
     std::vector<void*> ws, outs;
     hipStream_t s = nullptr;
     hipError_t err = hipSuccess;
+    char* fixed = nullptr;
+    size_t fixed_cap = 0, fixed_used = 0;
+    void* carve(size_t bytes) {
+        const size_t at = (fixed_used + 255) & ~size_t(255);
+        if (at + bytes > fixed_cap) {
+            err = hipErrorOutOfMemory;
+            return nullptr;
+        }
+        fixed_used = at + bytes;
+        return fixed + at;
+    }
     template <class T>
     T* get(size_t count) {
         if (err != hipSuccess) return nullptr;
+        if (fixed) return static_cast<T*>(carve(std::max<size_t>(count * sizeof(T), 256)));
         void* p = nullptr;
         err = pll_ws_alloc(&p, std::max<size_t>(count * sizeof(T), 256));
         if (err != hipSuccess) return nullptr;
@@ -777,6 +795,7 @@ struct DevAllocs {
     template <class T>
     T* get_out(size_t count) {
         if (err != hipSuccess) return nullptr;
+        if (fixed) return static_cast<T*>(carve(std::max<size_t>(count * sizeof(T), 256)));
         void* p = nullptr;
         err = hipMalloc(&p, std::max<size_t>(count * sizeof(T), 256));
         if (err != hipSuccess) return nullptr;
@@ -804,6 +823,14 @@ struct DevAllocs {
     }
 };
 
+// A fixed device region and host counter record for a build that allocates
+// nothing (pll_build_labels_noalloc).
+struct FixedWs {
+    void* base = nullptr;
+    size_t bytes = 0;
+    DevCounters* host_ctr = nullptr;
+};
+
 inline int status_of(hipError_t e) { return e == hipErrorOutOfMemory ? PLL_ENOMEM : PLL_EDEVICE; }
 
 #define TRY_HIP(expr)                                  \
@@ -814,8 +841,9 @@ inline int status_of(hipError_t e) { return e == hipErrorOutOfMemory ? PLL_ENOME
 
 struct HostCounters {
     DevCounters* p = nullptr;
+    bool own = true;
     ~HostCounters() {
-        if (p) pll_pinned_free(p);
+        if (p && own) pll_pinned_free(p);
     }
 };
 
@@ -1230,14 +1258,21 @@ int build_bp(DevAllocs& M, uint32_t n, uint32_t t_req, const uint64_t* rrow, con
 
 int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* order,
                   uint32_t b, uint32_t flags, uint64_t arena_hint, bool arena_fixed, uint32_t max_workgroups,
-                  uint32_t bp_req, hipStream_t s, pll_index* idx, uint64_t* used_arena) {
+                  uint32_t bp_req, hipStream_t s, pll_index* idx, uint64_t* used_arena, const FixedWs* fw = nullptr) {
     DevAllocs M;
     M.s = s;
     HostCounters HC;
     PhaseProfiler P;
     P.on = (flags & PLL_FLAG_PROFILE) != 0;
     P.s = s;
-    TRY_HIP(pll_pinned_alloc((void**)&HC.p, sizeof(DevCounters)));
+    if (fw) {
+        M.fixed = static_cast<char*>(fw->base);
+        M.fixed_cap = fw->bytes;
+        HC.p = fw->host_ctr;
+        HC.own = false;
+    } else {
+        TRY_HIP(pll_pinned_alloc((void**)&HC.p, sizeof(DevCounters)));
+    }
     DevCounters* h = HC.p;
     const uint32_t W = (b + 63) / 64;
 
@@ -2016,4 +2051,110 @@ int pll_build_directed(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, cons
 int pll_build_weighted(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col, const uint8_t* d_w,
                        const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out) {
     return build_index(n, nnz, d_row_ptr, d_col, d_w, true, d_order, opts, false, stream, out);
+}
+
+// ---- allocation-free build (pll_build_labels_noalloc) --------------------------------------------
+
+namespace {
+
+constexpr size_t kScratchBytes = 64ull << 20;
+constexpr size_t kScratchSlack = 64u << 10;  // alignment padding and small blocks beyond the estimate
+constexpr int kMaxDevices = 64;
+
+// Every working buffer of the allocation-free builds, carved in order by a
+// fixed-region DevAllocs.  Each device holds its own copy from the time this
+// code object is loaded on it until the process ends.  Host code must use the
+// address hipGetSymbolAddress gives for the current device, never this name.
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+std::mutex g_scratch_mu[kMaxDevices];       // one allocation-free build at a time per device
+void* g_scratch_ptr[kMaxDevices];           // device address of `scratch`, set once per device under its mutex
+DevCounters g_scratch_host[kMaxDevices];    // host copy of the build's counters
+
+size_t blk(size_t bytes) { return (std::max<size_t>(bytes, 256) + 255) & ~size_t(255); }
+
+// Bytes build_attempt carves before its label arena and final CSR for a
+// graph of n vertices and nnz CSR entries at W words per candidate
+// bit-vector, with neither bit-parallel roots nor the persistent loop (the
+// blocks of prepare_rank_csr, init_state, the second message buffer and
+// receiver list of the fused rounds, and the pulled rounds' items).
+size_t noalloc_state_bytes(uint32_t n, uint64_t nnz, uint32_t W) {
+    const size_t N = n, E = nnz ? nnz : 1;
+    size_t b = blk(sizeof(DevCounters));
+    b += blk(4 * N) + blk(4 * (N + 1)) + blk(8 * ((N + 1) / kScanTile + 2)) + blk(8 * (N + 1)) + blk(4 * E);
+    b += 2 * blk(8 * (N + 1)) + 2 * blk(4 * N) + 2 * blk(8 * N * W) + blk(64 * W * N) + blk(8 * N);
+    const size_t hq_seg = 2 * (nnz / kHeavy) + 64;
+    b += 2 * (blk(4 * N) + blk(8 * N * W) + blk(8 * PLL_SHARDS * hq_seg));
+    b += 3 * blk(4 * PLL_SHARDS * N) + 2 * blk(4 * N);
+    b += blk(8 * N * W) + blk(4 * PLL_SHARDS * N);
+    if (n >= kPullMinN) b += blk(8 * (N + nnz / pll::kPullSeg + 1)) + blk(4) + blk(8 * N);
+    return b;
+}
+
+}  // namespace
+
+int pll_export_launch(uint64_t total, const uint32_t* ent, const uint32_t* order, uint32_t* hubs, uint8_t* dists,
+                      hipStream_t s);
+
+extern "C" int pll_build_labels_noalloc(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
+                                        const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream,
+                                        uint64_t* d_offsets, uint32_t* d_hubs, uint8_t* d_dists, uint64_t capacity,
+                                        uint64_t* total) {
+    if (!total) return PLL_EINVAL;
+    *total = 0;
+    pll_build_opts o{};
+    if (opts) o = *opts;
+    for (uint32_t r : o.reserved)
+        if (r) return PLL_EINVAL;
+    const uint32_t b = o.batch_size ? o.batch_size : PLL_BMAX;
+    if (b > PLL_BMAX || n >= PLL_MAX_N || nnz > 0xFFFFFFFFull * 2) return PLL_EINVAL;
+    if (o.flags & ~(PLL_FLAG_VALIDATE | PLL_FLAG_RECHECK | PLL_FLAG_RELAXED)) return PLL_EINVAL;
+    if ((o.flags & PLL_FLAG_RELAXED) && !(o.flags & PLL_FLAG_RECHECK)) return PLL_EINVAL;
+    if (o.bp_roots || o.arena_entries) return PLL_EINVAL;
+    if (!d_offsets || (n > 0 && (!d_row_ptr || !d_order || (nnz && !d_col))) || (capacity && (!d_hubs || !d_dists)))
+        return PLL_EINVAL;
+    const uint32_t W = (b + 63) / 64;
+    // the label arena takes half of what the working state leaves, the final
+    // entries (as many at most) the other half
+    const size_t state = noalloc_state_bytes(n, nnz, W);
+    const size_t fin = 2 * blk(8 * ((size_t)n + 1)) + blk(4 * (size_t)n);
+    if (state + fin + kScratchSlack >= kScratchBytes) return PLL_ESCRATCH;
+    const uint64_t arena = (kScratchBytes - state - fin - kScratchSlack) / 8;
+    if (arena < 32ull * n + 4096) return PLL_ESCRATCH;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PLL_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu[dev]);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PLL_EDEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    if (n == 0) {
+        if (hipMemsetAsync(d_offsets, 0, sizeof(uint64_t), stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return PLL_EDEVICE;
+        return PLL_OK;
+    }
+    FixedWs fw;
+    fw.base = g_scratch_ptr[dev];
+    fw.bytes = kScratchBytes;
+    fw.host_ctr = &g_scratch_host[dev];
+    pll_index idx{};  // host record of this build; its device arrays lie in the scratch
+    idx.device = dev;
+    uint64_t used = 0;
+    int rc = build_attempt(n, nnz, d_row_ptr, d_col, d_order, b, o.flags, arena, true, 0, 0, stream, &idx, &used,
+                           &fw);
+    // with a fixed region, running out of arena or of scratch both mean the
+    // graph's labels do not fit
+    if (rc == PLL_ENOSPC || rc == PLL_ENOMEM) return PLL_ESCRATCH;
+    if (rc) return rc;
+    *total = idx.total;
+    if (idx.total > capacity) return PLL_ENOSPC;
+    if (hipMemcpyAsync(d_offsets, idx.d_off, sizeof(uint64_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, stream) !=
+        hipSuccess)
+        return PLL_EDEVICE;
+    rc = pll_export_launch(idx.total, idx.d_ent, idx.d_order, d_hubs, d_dists, stream);
+    if (rc) return rc;
+    // the next call may reuse the scratch as soon as this one returns
+    return hipStreamSynchronize(stream) == hipSuccess ? PLL_OK : PLL_EDEVICE;
 }

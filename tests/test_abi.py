@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol():
 def test_status_strings():
     if not os.path.exists(pll.LIB_PATH):
         pytest.skip("libpll.so not built")
-    for s in range(6):
+    for s in range(7):
         assert isinstance(pll.status_string(s), str) and pll.status_string(s)
     assert pll.status_string(99) == "unknown status"
 

@@ -1294,6 +1294,9 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     // leaves the top rows sparse: their masks are kept exact then
     rc = init_state(M, A, n, nnz, W, RC.rrow, RC.rcol, ctr, s, &spare_off, bp_req ? 0u : kHotRows);
     if (rc) return rc;
+    // the round-2 neighbour check needs every higher-ranked neighbour to be a
+    // hub, which bit-parallel roots (taken out of the labels) break
+    A.nbr_hubs = bp_req ? 0u : 1u;
     BpState BP;
     if (bp_req) {
         rc = build_bp(M, n, bp_req, RC.rrow, RC.rcol, ctr, h, s, &BP);

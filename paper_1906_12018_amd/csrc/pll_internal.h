@@ -74,6 +74,8 @@ struct BuildArgs {
     uint32_t W;        // words per candidate bit-vector (ceil(b / 64))
     uint32_t bstride;  // bytes per distance-table row (64 * W)
     uint32_t hot;      // rows h < hot keep every row-mask bit set for the whole build
+    uint32_t nbr_hubs; // 1: round-2 checks read v's higher-ranked neighbours instead of L(v) (undirected,
+                       // unweighted builds without bit-parallel roots; see prune_scan_nbrs)
     const uint64_t* rrow;   // rank-space CSR row pointers [n+1]
     const uint32_t* rcol;   // rank-space CSR columns [nnz]
     const uint8_t* rw;      // weighted graphs: weight of each rank-space CSR entry (null otherwise)

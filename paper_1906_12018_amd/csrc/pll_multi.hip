@@ -612,6 +612,7 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
         A.act_rng[0] = A.act_rng[1] = nullptr;
         A.bp_t = 0;
         A.hot = 0;  // small graphs leave rows sparse: every row mask is kept exact
+        A.nbr_hubs = 1;  // undirected, unweighted, no bit-parallel roots
         J.rank = (uint32_t*)(op + o.rank);
         A.rrow = (uint64_t*)(op + o.rrow);
         A.rcol = (uint32_t*)(op + o.rcol);

@@ -96,8 +96,11 @@ __device__ inline uint64_t wave_or64_u(uint64_t x) {
 // j is already covered through a hub ranked above u_k (Algorithm 4, line 14).
 // With `relaxed`, entries whose hub is in the current batch are skipped.
 // The table loads of all candidate words of a chunk are independent; lanes
-// are OR-reduced every 4 chunks (and at the end), which is also where the
-// scan stops once every candidate is pruned.  With QGATE only the 16-byte
+// are OR-reduced after the first chunk, every 4 chunks and at the end,
+// which is also where the scan stops once every candidate is pruned (the
+// early reduction took the R-MAT-20 check from 407 to 315 ms: the top-ranked
+// hubs of the first chunk prune most candidates of the late rounds).  The
+// next chunk's entries are loaded while this chunk's segments are.  With QGATE only the 16-byte
 // quarters of a table segment that both hold entries (row mask) and have
 // live candidates are loaded; without it a segment is loaded whole when any
 // of its quarters qualifies (fewer, wider loads: measured faster on the large
@@ -112,11 +115,14 @@ __device__ inline uint64_t prune_scan(const BuildArgs& A, uint64_t off, uint32_t
 #pragma unroll
     for (int w = 0; w < WM; ++w) accm[w] = 0;
     uint32_t chunk = 0;
+    // the next chunk's entry is loaded while this chunk's table segments are
+    uint32_t next = lane < len ? A.arena[off + lane] : 0u;
     for (uint32_t base = 0; base < len; base += 64, ++chunk) {
         const uint32_t idx = base + lane;
         bool ok = idx < len;
         st.read += ok;
-        const uint32_t ent = ok ? A.arena[off + idx] : 0u;
+        const uint32_t ent = next;
+        next = idx + 64 < len ? A.arena[off + idx + 64] : 0u;
         const uint32_t h = ent >> 8, d = ent & 255u;
         ok = ok && d < j;
         if (relaxed) ok = ok && h < ib;
@@ -140,7 +146,10 @@ __device__ inline uint64_t prune_scan(const BuildArgs& A, uint64_t off, uint32_t
                 st.table += 4;
             }
         }
-        if ((chunk & 3u) == 3u || base + 64 >= len) {
+        // lanes are OR-reduced after the first chunk (the top-ranked hubs
+        // prune most candidates), then every 4 chunks and at the end; a word
+        // whose candidates are all pruned loads no more table segments
+        if (chunk == 0 || (chunk & 3u) == 3u || base + 64 >= len) {
 #pragma unroll
             for (int w = 0; w < WM; ++w) {
                 if (readlane64(live_lane, w)) {
@@ -150,6 +159,67 @@ __device__ inline uint64_t prune_scan(const BuildArgs& A, uint64_t off, uint32_t
                 }
             }
             if (!ballot64((cw & ~pw) != 0)) break;
+        }
+    }
+    return pw;
+}
+
+// The round-2 check of receiver v through its neighbours.  At distance 2
+// only entries (h, 1) of L(v) can prune (the self entry cannot, as in round
+// 1), and in an undirected unweighted graph those are exactly the
+// neighbours h of v ranked above both v and the end of the current batch
+// (lim): the edge is the only shortest h-v path, so h is its top-ranked
+// vertex, and h's batch has run (or, inside the current batch, round 1
+// accepted (h, 1) unconditionally).  So the rank-space CSR row of v can
+// stand in for L(v): the caller takes it when it is the shorter of the two
+// (a low-ranked vertex has a few dozen neighbours and hundreds of label
+// entries).  Candidate u_k is pruned when T[h][k] <= 1; the table loads,
+// which are the same as those of the label scan, and the lane reductions
+// are those of prune_scan.
+template <int WM, bool QGATE = false>
+__device__ inline uint64_t prune_scan_nbrs(const BuildArgs& A, uint32_t v, uint32_t lim, uint64_t cw,
+                                           PhaseStats& st) {
+    const uint32_t lane = lane_id();
+    uint64_t pw = 0;
+    uint64_t accm[WM];
+#pragma unroll
+    for (int w = 0; w < WM; ++w) accm[w] = 0;
+    const uint64_t beg = A.rrow[v], end = A.rrow[v + 1];
+    const uint32_t tt = 0x01010101u;  // T[h][k] <= 2 - 1
+    uint32_t chunk = 0;
+    for (uint64_t base = beg; base < end; base += 64, ++chunk) {
+        const uint64_t idx = base + lane;
+        const uint32_t h = idx < end ? A.rcol[idx] : ~0u;
+        const bool ok = h < lim;
+        st.read += idx < end;
+        const uint64_t rm = ok ? A.rmchk[h] : 0ull;
+        const uint8_t* row = A.Tchk + (size_t)(ok ? h : 0u) * A.bstride;
+        const uint64_t live_lane = cw & ~pw;
+#pragma unroll
+        for (int w = 0; w < WM; ++w) {
+            const uint64_t live = readlane64(live_lane, w);
+            if (QGATE) {
+                const uint32_t need = (uint32_t)(rm >> (4 * w)) & quarters(live);
+                if (need & 15u) {
+                    accm[w] |= le_mask64_q(row + 64u * w, tt, need) & live;
+                    st.table += __builtin_popcount(need & 15u);
+                }
+            } else if (live != 0 && ((rm >> (4 * w)) & 15u)) {
+                accm[w] |= le_mask64(row + 64u * w, tt) & live;
+                st.table += 4;
+            }
+        }
+        const bool last = base + 64 >= end;
+        if (chunk == 0 || (chunk & 3u) == 3u || last) {
+#pragma unroll
+            for (int w = 0; w < WM; ++w) {
+                if (readlane64(live_lane, w)) {
+                    const uint64_t red = wave_or64_u(accm[w]);
+                    if (lane == (uint32_t)w) pw |= red;
+                    accm[w] = 0;
+                }
+            }
+            if (last || !ballot64((cw & ~pw) != 0)) break;
         }
     }
     return pw;
@@ -604,7 +674,15 @@ __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t i
             st.bp += __builtin_popcountll(lane < W ? bpp : 0ull);
             scan &= ~bpp;
         }
-        const uint64_t pw = prune_scan<WM, QGATE>(A, off, len, j, scan, relaxed, ib, st);
+        // Round 1 never prunes: only an entry at distance 0, the self entry
+        // (v, 0), could cover a candidate at distance 1, through T[v][k] <= 1,
+        // i.e. with v a hub of u_k; but a candidate u_k only reaches vertices
+        // ranked below it, and L(u_k) holds only hubs ranked above u_k.
+        uint64_t pw = 0;
+        if (j == 2 && A.nbr_hubs && A.rrow[v + 1] - A.rrow[v] < len)
+            pw = prune_scan_nbrs<WM, QGATE>(A, v, min(v, relaxed ? ib : ib + bs), scan, st);
+        else if (j > 1)
+            pw = prune_scan<WM, QGATE>(A, off, len, j, scan, relaxed, ib, st);
         const uint64_t acc = lane < W ? (scan & ~pw) : 0ull;
         const uint32_t cnt = (uint32_t)__builtin_popcountll(acc);
         const uint32_t pos = wave_excl_scan32(cnt);

@@ -290,8 +290,10 @@ int pll_export_bp(const pll_index* idx, uint32_t* d_roots, uint32_t* d_nbrs, uin
  *   d_out       uint32[count]; PLL_DIST_INF when v is unreachable from u
  * Asynchronous on `stream`; the index must outlive the enqueued work.
  * Lanes per pair follow opts->query_lanes of the build: 1 runs a scalar
- * two-pointer merge per lane; G in {4..64} lets G lanes merge the two lists
- * in windows of 4G entries; 0 picks G from the mean label length.
+ * two-pointer merge per lane; G in {4..32} lets G lanes merge the two lists
+ * in windows of 4G entries; 64 gives each pair a whole wave, which merges
+ * the lists in merge-path tiles of 512 entries staged in LDS; 0 picks G from
+ * the mean label length.
  */
 int pll_query(const pll_index* idx, uint64_t count, const uint32_t* d_u, const uint32_t* d_v, uint32_t* d_out,
               hipStream_t stream);

@@ -2,10 +2,13 @@
 // Dis(u,v) = min over common hubs h of d(u,h) + d(h,v), found by merging the
 // two hub-rank-sorted label lists.  Labels are packed (hub rank << 8) | dist.
 //
-// Two kernels:
+// Three kernels:
 //  * k_query_lane: one lane per pair, a scalar two-pointer merge.  Kept for
 //    tiny labels and as the simplest form of the operation.
-//  * k_query_group<G>: G lanes per pair merge the lists window by window.  A
+//  * k_query_wave (64 lanes per pair): one pair per wave, the lists merged in
+//    merge-path tiles staged in LDS (described below, before the kernel).
+//  * k_query_group<G> (G = 4..32): G lanes per pair merge the lists window
+//    by window.  A
 //    u-window is 2G consecutive entries of L(u) and a v-window 4G entries of
 //    L(v), read as one aligned 8- or 16-byte load per lane (label arrays are
 //    padded to whole 4-entry chunks).  The v-window is published in LDS;
@@ -258,6 +261,225 @@ __global__ void __launch_bounds__(kBlock) k_query_group(const uint64_t* __restri
     }
 }
 
+// ---- one pair per wave: merge-path tiles ----------------------------------------------------------
+//
+// The wave merges the two lists in tiles of kTile merged entries (8 per
+// lane).  Each tile stages a window of each list in LDS (one aligned 16-byte
+// load per chunk, up to kWin entries from the first unmerged entry); entries
+// past the smaller of the two lists' last hubs can match nothing (the list
+// with that last hub ends there, Section 2.1's merge stops) and are staged
+// as a sentinel.  Lane l finds where diagonal 8l of the tile crosses the
+// merge path by binary search (the number of A entries among the first 8l
+// merged ones; on equal hubs the A entry goes first), then walks its 8
+// merged entries.  Because the A entry of a common hub immediately precedes
+// the B entry in merged order, the lane that takes an A entry sees its
+// partner as its current B entry, so every common hub is found exactly
+// once, also across lane and tile boundaries.
+constexpr int kTile = 512;
+constexpr int kWinChunks = 130;             // 16-byte chunks staged per list
+constexpr int kWin = 4 * kWinChunks;        // 520 entries: a tile plus the alignment offset plus lookahead
+constexpr uint32_t kSent = 0xFFFFFFFFu;     // after every entry; never equal to one (hub ranks < 2^24 - 1)
+constexpr int kWavesPerBlock = kBlock / 64;
+
+// Minimum over the 64 lanes by DPP moves (the whole wave active); the result
+// is wave-uniform.
+__device__ __forceinline__ uint32_t wave_min32_dpp(uint32_t x) {
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)kSent, (int)x, 0x111, 0xf, 0xf, false));  // row_shr:1
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)kSent, (int)x, 0x112, 0xf, 0xf, false));  // row_shr:2
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)kSent, (int)x, 0x114, 0xf, 0xf, false));  // row_shr:4
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)kSent, (int)x, 0x118, 0xf, 0xf, false));  // row_shr:8
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)kSent, (int)x, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)kSent, (int)x, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// Raw chunks of one list's window: entries [base, base + kWin) of `ent`,
+// where base is the first unmerged entry rounded down to 4 entries and the
+// list ends `avail` entries past base.  Chunk r of a lane is chunk
+// lane + 64 r of the window.  A chunk past the list end (or the third chunk
+// of lanes 2..63, which the window does not have) is loaded from the
+// window's first chunk instead, so every load is unconditional and all of
+// them are in flight together; stage_window discards those.
+__device__ __forceinline__ void load_window(const uint32_t* __restrict__ ent, uint64_t base, uint64_t avail,
+                                            uint32_t lane, uint4 (&x)[3]) {
+    const uint32_t hi = (uint32_t)min<uint64_t>(avail, (uint64_t)kWin);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const uint32_t q = 4u * (lane + 64u * r);
+        const uint32_t at = q < hi ? q : 0u;
+        x[r] = *reinterpret_cast<const uint4*>(ent + base + at);
+    }
+}
+
+// Publish a loaded window in LDS: positions past the list end or holding an
+// entry above `limraw` become kSent.  Returns how many published entries at
+// or after position `lo` are not kSent (wave-uniform, counted by ballots).
+__device__ __forceinline__ uint32_t stage_window(const uint4 (&x)[3], uint64_t avail, uint32_t lo, uint32_t limraw,
+                                                 uint32_t* __restrict__ win, uint32_t lane) {
+    const uint32_t hi = (uint32_t)min<uint64_t>(avail, (uint64_t)kWin);
+    uint32_t count = 0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const uint32_t q = 4u * (lane + 64u * r);
+        const uint32_t e[4] = {x[r].x, x[r].y, x[r].z, x[r].w};
+        uint32_t o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool ok = q + k < hi && e[k] <= limraw;
+            o[k] = ok ? e[k] : kSent;
+            count += (uint32_t)__builtin_popcountll(__ballot(ok && q + k >= lo));
+        }
+        if (r < 2 || lane < (uint32_t)(kWinChunks - 128))
+            *reinterpret_cast<uint4*>(win + q) = make_uint4(o[0], o[1], o[2], o[3]);
+    }
+    return count;
+}
+
+template <bool BP>
+__global__ void __launch_bounds__(kBlock) k_query_wave(const uint64_t* __restrict__ offu,
+                                                       const uint32_t* __restrict__ entu,
+                                                       const uint64_t* __restrict__ offv,
+                                                       const uint32_t* __restrict__ entv, uint32_t n, uint64_t count,
+                                                       const uint32_t* __restrict__ qu,
+                                                       const uint32_t* __restrict__ qv, uint32_t* __restrict__ out,
+                                                       const uint8_t* __restrict__ bpd,
+                                                       const ulonglong2* __restrict__ bps, uint32_t bpt) {
+    __shared__ uint4 s_win[kWavesPerBlock][2][(kWin + 16) / 4];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wv = threadIdx.x >> 6;
+    uint32_t* sa = reinterpret_cast<uint32_t*>(s_win[wv][0]);
+    uint32_t* sb = reinterpret_cast<uint32_t*>(s_win[wv][1]);
+    // lookahead past a full window reads the padding: the sentinel
+    if (lane < 16) {
+        sa[kWin + lane] = kSent;
+        sb[kWin + lane] = kSent;
+    }
+    // A wave takes groups of 64 consecutive pairs.  Lane l first gathers pair
+    // l's ids, list bounds and last entries, so these dependent loads are in
+    // flight for all 64 pairs at once; the wave then merges the pairs one by
+    // one, reading their bounds from lane registers, and stores the 64
+    // answers together.
+    const uint64_t groups = (count + 63) / 64;
+    const uint64_t gstride = (uint64_t)gridDim.x * kWavesPerBlock;
+    for (uint64_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + wv); g < groups; g += gstride) {
+        const uint64_t p0 = g * 64;
+        const uint32_t np = (uint32_t)min<uint64_t>(64, count - p0);
+        const uint64_t pl = p0 + lane;
+        uint32_t ul = 0, vl = 0;
+        if (lane < np) {
+            ul = qu[pl];
+            vl = qv[pl];
+        }
+        // an id out of range has no label: no common hub
+        const bool has = lane < np && ul < n && vl < n;
+        uint64_t al = 0, ael = 0, bl = 0, bel = 0;
+        if (has) {
+            al = offu[ul];
+            ael = offu[ul + 1];
+            bl = offv[vl];
+            bel = offv[vl + 1];
+        }
+        // entries above the smaller last hub cannot match: compare raw
+        // entries with (that hub << 8) | 255
+        uint32_t liml = 0;
+        if (al < ael && bl < bel) liml = min(entu[ael - 1], entv[bel - 1]) | 255u;
+        uint32_t res = PLL_DIST_INF;
+        for (uint32_t k = 0; k < np; ++k) {
+            uint64_t a = readlane64(al, k), ae = readlane64(ael, k);
+            uint64_t b = readlane64(bl, k), be = readlane64(bel, k);
+            const uint32_t limraw = readlane32(liml, k);
+            uint32_t best = PLL_DIST_INF;
+            if (a < ae && b < be) {
+                for (;;) {
+                    const uint64_t baseA = a & ~3ull, baseB = b & ~3ull;
+                    const uint32_t loA = (uint32_t)(a - baseA), loB = (uint32_t)(b - baseB);
+                    uint4 xa[3], xb[3];
+                    load_window(entu, baseA, ae - baseA, lane, xa);
+                    load_window(entv, baseB, be - baseB, lane, xb);
+                    const uint32_t nA = stage_window(xa, ae - baseA, loA, limraw, sa, lane);
+                    const uint32_t nB = stage_window(xb, be - baseB, loB, limraw, sb, lane);
+                    wave_lds_sync();
+                    if (nA == 0 || nB == 0) break;
+                    const uint32_t T = min((uint32_t)kTile, nA + nB);
+                    const uint32_t d = min(8u * lane, T);
+                    uint32_t lo = d > nB ? d - nB : 0u, hi = min(d, nA);
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        const uint32_t x = sa[loA + mid], y = sb[loB + d - 1 - mid];
+                        if (x <= (y | 255u))
+                            lo = mid + 1;
+                        else
+                            hi = mid;
+                    }
+                    // walk 8 merged entries; both heads are read every step
+                    uint32_t pa = loA + lo, pb = loB + (d - lo);
+                    const uint32_t steps = T - d;
+                    uint32_t x = sa[pa], y = sb[pb];
+#pragma unroll
+                    for (uint32_t t = 0; t < 8; ++t) {
+                        const bool live = t < steps;
+                        const bool take_a = live && x <= (y | 255u);
+                        const uint32_t sum = (x & 255u) + (y & 255u);
+                        best = (take_a && (x ^ y) < 256u) ? min(best, sum) : best;
+                        pa += take_a ? 1u : 0u;
+                        pb += (live && !take_a) ? 1u : 0u;
+                        x = sa[pa];
+                        y = sb[pb];
+                    }
+                    // lane 63 ended exactly where the tile ends on the merge path
+                    const uint32_t iT = readlane32(pa - loA, 63);
+                    const uint32_t jT = T - iT;
+                    // a list whose valid part ended inside its window and has
+                    // been merged whole ends the merge
+                    if ((iT == nA && nA < (uint32_t)kWin - loA) || (jT == nB && nB < (uint32_t)kWin - loB)) break;
+                    a += iT;
+                    b += jT;
+                    wave_lds_sync();
+                }
+                wave_lds_sync();
+            }
+            if (BP) {
+                const uint32_t u = readlane32(ul, k), v = readlane32(vl, k);
+                if (u < n && v < n) best = min(best, bp_bound(bpd, bps, bpt, u, v, lane, 64));
+            }
+            best = wave_min32_dpp(best);
+            res = lane == k ? best : res;
+        }
+        if (lane < np) out[pl] = res;
+    }
+}
+
+// One pair at a time per wave, in groups of 64 pairs; waves loop over
+// groups.  Grid: 8x the workgroups that fit on the device at once.
+void launch_wave(const pll_index* idx, uint64_t count, const uint32_t* d_u, const uint32_t* d_v, uint32_t* d_out,
+                 hipStream_t stream) {
+    static std::atomic<uint64_t> cap_cache[64];
+    uint64_t blocks = ((count + 63) / 64 + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int dev = idx->device;
+    uint64_t cap = dev >= 0 && dev < 64 ? cap_cache[dev].load(std::memory_order_relaxed) : 0;
+    if (cap == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query_wave<false>, kBlock, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1 ||
+            cus < 1) {
+            per_cu = 8;
+            cus = 256;
+        }
+        cap = (uint64_t)per_cu * cus * 8;
+        if (dev >= 0 && dev < 64) cap_cache[dev].store(cap, std::memory_order_relaxed);
+    }
+    if (blocks > cap) blocks = cap;
+    const uint64_t* offu = idx->directed ? idx->d_off_out : idx->d_off;
+    const uint32_t* entu = idx->directed ? idx->d_ent_out : idx->d_ent;
+    if (idx->info.bp_roots)
+        k_query_wave<true><<<(uint32_t)blocks, kBlock, 0, stream>>>(offu, entu, idx->d_off, idx->d_ent, idx->n, count,
+                                                                    d_u, d_v, d_out, idx->d_bp_dist, idx->d_bp_sets,
+                                                                    idx->info.bp_roots);
+    else
+        k_query_wave<false><<<(uint32_t)blocks, kBlock, 0, stream>>>(offu, entu, idx->d_off, idx->d_ent, idx->n,
+                                                                     count, d_u, d_v, d_out, nullptr, nullptr, 0);
+}
+
 // Grid: a multiple of the workgroups that fit on the device at once (every
 // group loops over pairs).  Short lists leave waves idle sooner, so more
 // workgroups than fit at once balance better; measured: 32x for one pair per
@@ -330,7 +552,7 @@ int pll_query_launch(const pll_index* idx, uint64_t count, const uint32_t* d_u, 
         case 8: launch_group<8>(idx, count, d_u, d_v, d_out, stream); break;
         case 16: launch_group<16>(idx, count, d_u, d_v, d_out, stream); break;
         case 32: launch_group<32>(idx, count, d_u, d_v, d_out, stream); break;
-        case 64: launch_group<64>(idx, count, d_u, d_v, d_out, stream); break;
+        case 64: launch_wave(idx, count, d_u, d_v, d_out, stream); break;
         default: return PLL_EINVAL;
     }
     return hipGetLastError() == hipSuccess ? PLL_OK : PLL_EDEVICE;

@@ -46,9 +46,12 @@ def make_graph(w):
 
 
 def consumed_entries(off, hubs_rank, rank, u, v):
-    """Entries a merge-join must read for each pair: with lim = the smaller
-    of the two lists' last hub ranks (rank(u) and rank(v), since (x,0) closes
-    L(x)), every entry of hub rank <= lim in either list."""
+    """Label entries a merge-join must read, summed over the pairs: with
+    lim = the smaller of the two lists' last hub ranks (rank(u) and rank(v),
+    since (x,0) closes L(x)), every entry of hub rank <= lim in either list,
+    but none when either list has no such entry (its first entry is above
+    lim: the lists share no hub, which the two lists' first and last entries
+    show).  Returns (entries, pairs that merge)."""
     import numpy as np
     n = rank.shape[0]
     owners = np.repeat(np.arange(n, dtype=np.int64), np.diff(off).astype(np.int64))
@@ -57,7 +60,8 @@ def consumed_entries(off, hubs_rank, rank, u, v):
     lim = np.minimum(ru, rv)
     cu = np.searchsorted(keys, (u.astype(np.int64) << 24) | lim, side="right") - off[u].astype(np.int64)
     cv = np.searchsorted(keys, (v.astype(np.int64) << 24) | lim, side="right") - off[v].astype(np.int64)
-    return int(cu.sum() + cv.sum())
+    both = (cu > 0) & (cv > 0)
+    return int((cu + cv)[both].sum()), int(both.sum())
 
 
 # Sources whose text fixes each measured kernel; the HBM traffic recorded in
@@ -148,8 +152,8 @@ def query_mode(args):
         e1.record()
         torch.cuda.synchronize()
         ms.append(e0.elapsed_time(e1))
-    cons = consumed_for(idx, g, order, u, v)
-    q_bytes = w["pairs"] * (8 + 32 + 4) + 4 * cons
+    cons, merging = consumed_for(idx, g, order, u, v)
+    q_bytes = query_bytes(w["pairs"], merging, cons)
     med = float(np.median(ms))
     gbs = q_bytes / (med / 1e3) / 1e9
     tr = measured_traffic("k_query_group", args.workload)
@@ -158,7 +162,8 @@ def query_mode(args):
                       "roofline": {"kernel": "k_query_group", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
                                    "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                                    "traffic": tr["bytes"] if tr else None,
-                                   "bytes_per_launch": q_bytes, "entries_consumed": cons},
+                                   "bytes_per_launch": q_bytes, "entries_consumed": cons,
+                                   "pairs_merged": merging},
                       "label_entries": idx.info()["total_entries"],
                       "query_lanes": tuned["best"] if tuned else "auto",
                       "tuning": tuned["results"] if tuned else None}), flush=True)
@@ -223,6 +228,7 @@ def batched_mode(args):
 
 
 def consumed_for(idx, g, order, u, v):
+    """consumed_entries over the index's exported labels."""
     import numpy as np
     import torch
     ex = idx.export()
@@ -232,6 +238,18 @@ def consumed_for(idx, g, order, u, v):
     rank = np.empty(g.n, dtype=np.int64)
     rank[order.astype(np.int64)] = np.arange(g.n)
     return consumed_entries(off, rank[hubs.astype(np.int64)], rank, u.astype(np.int64), v.astype(np.int64))
+
+
+# Query bytes: every pair reads two 4-byte ids, the two 8-byte list bounds
+# (first and last hub of each list, which decide whether the lists can share
+# a hub) and writes a 4-byte answer; a pair that merges also reads four
+# 8-byte offsets and 4 bytes per merged label entry.
+QUERY_PAIR_BYTES = 8 + 16 + 4
+QUERY_MERGE_BYTES = 32
+
+
+def query_bytes(pairs, merging, consumed):
+    return pairs * QUERY_PAIR_BYTES + merging * QUERY_MERGE_BYTES + 4 * consumed
 
 
 def host_info():
@@ -790,7 +808,7 @@ def build_mode(args):
     # parity of this run against the oracle's stored digests (labels whole,
     # answers to every configured pair), when they exist for the workload
     gold = golden_for(args.workload)
-    parity, gpu_labels, cons = None, None, None
+    parity, gpu_labels = None, None
     if gold is not None:
         dig, gpu_labels = export_digests(idx, order)
         ans = out.cpu().numpy().view(np.uint32)
@@ -798,13 +816,10 @@ def build_mode(args):
                                                                            "sha_dists")),
                   "answers_equal_oracle": hashlib.sha256(ans.tobytes()).hexdigest() == gold["pairs"]["sha"],
                   "source": f"tests/golden/{args.workload}_oracle.json (oracle PLL, written offline)"}
-        if parity["labels_equal_oracle"]:
-            cons = gold["pairs"]["consumed_entries"]
-        else:
+        if not parity["labels_equal_oracle"]:
             gpu_labels = None
         print(f"bench: parity {parity}", file=sys.stderr, flush=True)
-    if cons is None:
-        cons = consumed_for(idx, g, order, u, v)
+    cons, merging = consumed_for(idx, g, order, u, v)
 
     # roofline, dominant kernel: the fused pruning check and push
     # (k_check_push), bytes per the kernel's traffic model (label entries and
@@ -816,7 +831,7 @@ def build_mode(args):
     check_bytes = (4 * info["check_entries_read"] + 16 * info["check_table_reads"]
                    + 4 * info["accepted"] + 4 * info["check_push_edges"])
     check_gbs = check_bytes / (check_ms / 1e3) / 1e9
-    q_bytes = w["pairs"] * (8 + 32 + 4) + 4 * cons
+    q_bytes = query_bytes(w["pairs"], merging, cons)
     q_gbs = q_bytes / (np.median(query_ms) / 1e3) / 1e9
     achievable = stream_read_gbs(args.stream_gib)
     print("bench: streaming read done", file=sys.stderr, flush=True)
@@ -868,9 +883,10 @@ def build_mode(args):
                            "traffic": tr_query["bytes"] if tr_query else None,
                            "traffic_GBs": (tr_query["bytes"] / (np.median(query_ms) / 1e3) / 1e9) if tr_query
                            else None,
-                           "bytes_per_launch": q_bytes, "entries_consumed": cons,
-                           "bytes_model": "per pair 8 B ids + 32 B offsets + 4 B answer, plus 4 B per label entry "
-                                          "a sequential merge reads (hub rank <= the smaller list end)"},
+                           "bytes_per_launch": q_bytes, "entries_consumed": cons, "pairs_merged": merging,
+                           "bytes_model": "per pair 8 B ids + 16 B list bounds + 4 B answer; per pair whose lists "
+                                          "both have an entry of hub rank <= the smaller list end, 32 B offsets + "
+                                          "4 B per such entry"},
     }
     # Table 3's quantities: sum of |L(v)| over positive / negative checks
     res["check_cost"] = {"bvc_pos": info["check_cost_pos"], "bvc_neg": info["check_cost_neg"]}

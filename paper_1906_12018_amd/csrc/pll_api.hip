@@ -31,10 +31,12 @@ void free_index(pll_index* idx) {
     } else {
         (void)hipFree(idx->d_off);
         (void)hipFree(idx->d_order);
+        (void)hipFree(idx->d_lb);
     }
     if (idx->directed) {
         (void)hipFree(idx->d_off_out);
         (void)hipFree(idx->d_ent_out);
+        (void)hipFree(idx->d_lb_out);
     }
     if (idx->d_bp_roots) {
         (void)hipFree(idx->d_bp_roots);

@@ -735,7 +735,8 @@ __global__ void __launch_bounds__(kBlock) k_final_lens(uint32_t n, const uint32_
 
 __global__ void __launch_bounds__(kBlock) k_final_copy(uint32_t n, const uint32_t* rank, const uint64_t* loff,
                                                        const uint32_t* llen, const uint32_t* arena,
-                                                       const uint64_t* off, uint32_t* ent, DevCounters* ctr) {
+                                                       const uint64_t* off, uint32_t* ent, uint2* lb,
+                                                       DevCounters* ctr) {
     __shared__ uint32_t smax[kWavesPerBlock];
     const uint32_t lane = lane_id();
     uint32_t md = 0;
@@ -748,6 +749,8 @@ __global__ void __launch_bounds__(kBlock) k_final_copy(uint32_t n, const uint32_
             ent[dst + i] = e;
             md = max(md, e & 255u);
         }
+        if (lane == 0)
+            lb[v] = len ? make_uint2(arena[src] >> 8, arena[src + len - 1] >> 8) : make_uint2(0xFFFFFFFFu, 0u);
     }
     md = wave_max32(md);
     if (lane == 0) smax[threadIdx.x >> 6] = md;
@@ -1190,7 +1193,8 @@ int init_state(DevAllocs& M, BuildArgs& A, uint32_t n, uint64_t nnz, uint32_t W,
 // padded to whole 4-entry chunks: the query kernel reads labels in aligned
 // 16-byte loads.
 int finalize_labels(DevAllocs& M, const BuildArgs& A, const uint32_t* rank, uint32_t* tmp32,
-                    uint64_t* scan_scratch, hipStream_t s, uint64_t** d_off, uint32_t** d_ent, uint64_t* total) {
+                    uint64_t* scan_scratch, hipStream_t s, uint64_t** d_off, uint32_t** d_ent, uint2** d_lb,
+                    uint64_t* total) {
     const uint32_t n = A.n;
     k_final_lens<<<blocks_for_threads(n), kBlock, 0, s>>>(n, rank, A.llen, tmp32, A.ctr);
     *d_off = M.get_out<uint64_t>((size_t)n + 1);
@@ -1199,9 +1203,10 @@ int finalize_labels(DevAllocs& M, const BuildArgs& A, const uint32_t* rank, uint
     TRY_HIP(hipMemcpyAsync(total, *d_off + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     TRY_HIP(hipStreamSynchronize(s));
     *d_ent = M.get_out<uint32_t>(std::max<uint64_t>((*total + 3) & ~3ull, 4));
+    *d_lb = M.get_out<uint2>(n);
     if (M.err != hipSuccess) return status_of(M.err);
     k_final_copy<<<std::min<uint32_t>(blocks_for_waves(n), 1024), kBlock, 0, s>>>(n, rank, A.loff, A.llen, A.arena,
-                                                                                   *d_off, *d_ent, A.ctr);
+                                                                                   *d_off, *d_ent, *d_lb, A.ctr);
     TRY_HIP(hipGetLastError());
     return PLL_OK;
 }
@@ -1497,8 +1502,9 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     hipEvent_t e_fin = P.mark();
     uint64_t* d_off = nullptr;
     uint32_t* d_ent = nullptr;
+    uint2* d_lb = nullptr;
     uint64_t total = 0;
-    rc = finalize_labels(M, A, rank, tmp32, scan_scratch, s, &d_off, &d_ent, &total);
+    rc = finalize_labels(M, A, rank, tmp32, scan_scratch, s, &d_off, &d_ent, &d_lb, &total);
     if (rc) return rc;
     uint32_t* d_order = M.get_out<uint32_t>(n);
     if (M.err != hipSuccess) return status_of(M.err);
@@ -1523,9 +1529,11 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     idx->total = total;
     idx->d_off = d_off;
     idx->d_ent = d_ent;
+    idx->d_lb = d_lb;
     idx->d_order = d_order;
     M.forget(d_off);
     M.forget(d_ent);
+    M.forget(d_lb);
     M.forget(d_order);
     M.forget(idx->d_bp_roots);
     M.forget(idx->d_bp_nbrs);
@@ -1541,7 +1549,7 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     I.bp_vertices = BP.used_count;
     I.bp_pruned = sum_stat(h, PLL_ST_BP);
     I.check_push_edges = sum_stat(h, PLL_ST_FUSED_EDGES);
-    I.label_bytes = total * sizeof(uint32_t) + ((uint64_t)n + 1) * sizeof(uint64_t);
+    I.label_bytes = total * sizeof(uint32_t) + ((uint64_t)n + 1) * sizeof(uint64_t) + (uint64_t)n * sizeof(uint2);
     I.max_dist = h->max_dist;
     I.max_label = h->max_label;
     I.batches = batches;
@@ -1662,8 +1670,9 @@ int build_attempt_weighted(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
     hipEvent_t e_fin = P.mark();
     uint64_t* d_off = nullptr;
     uint32_t* d_ent = nullptr;
+    uint2* d_lb = nullptr;
     uint64_t total = 0;
-    rc = finalize_labels(M, A, RC.rank, RC.tmp32, RC.scan_scratch, s, &d_off, &d_ent, &total);
+    rc = finalize_labels(M, A, RC.rank, RC.tmp32, RC.scan_scratch, s, &d_off, &d_ent, &d_lb, &total);
     if (rc) return rc;
     uint32_t* d_order = M.get_out<uint32_t>(n);
     if (M.err != hipSuccess) return status_of(M.err);
@@ -1678,9 +1687,11 @@ int build_attempt_weighted(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
     idx->total = total;
     idx->d_off = d_off;
     idx->d_ent = d_ent;
+    idx->d_lb = d_lb;
     idx->d_order = d_order;
     M.forget(d_off);
     M.forget(d_ent);
+    M.forget(d_lb);
     M.forget(d_order);
     pll_index_info& I = idx->info;
     I.n = n;
@@ -1689,7 +1700,7 @@ int build_attempt_weighted(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
     I.total_entries = total;
     I.in_entries = total;
     I.out_entries = total;
-    I.label_bytes = total * sizeof(uint32_t) + ((uint64_t)n + 1) * sizeof(uint64_t);
+    I.label_bytes = total * sizeof(uint32_t) + ((uint64_t)n + 1) * sizeof(uint64_t) + (uint64_t)n * sizeof(uint2);
     I.max_dist = h->max_dist;
     I.max_label = h->max_label;
     I.batches = batches;
@@ -1881,9 +1892,10 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
     hipEvent_t e_fin = P.mark();
     uint64_t* d_off[2] = {nullptr, nullptr};
     uint32_t* d_ent[2] = {nullptr, nullptr};
+    uint2* d_lb[2] = {nullptr, nullptr};
     uint64_t total[2] = {0, 0};
     for (int d = 0; d < 2; ++d) {
-        rc = finalize_labels(M, A[d], RC.rank, tmp32, scan_scratch, s, &d_off[d], &d_ent[d], &total[d]);
+        rc = finalize_labels(M, A[d], RC.rank, tmp32, scan_scratch, s, &d_off[d], &d_ent[d], &d_lb[d], &total[d]);
         if (rc) return rc;
     }
     uint32_t* d_order = M.get_out<uint32_t>(n);
@@ -1903,10 +1915,13 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
     idx->total_out = total[1];
     idx->d_off_out = d_off[1];
     idx->d_ent_out = d_ent[1];
+    idx->d_lb = d_lb[0];
+    idx->d_lb_out = d_lb[1];
     idx->d_order = d_order;
     for (int d = 0; d < 2; ++d) {
         M.forget(d_off[d]);
         M.forget(d_ent[d]);
+        M.forget(d_lb[d]);
     }
     M.forget(d_order);
     pll_index_info& I = idx->info;
@@ -1916,7 +1931,8 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
     I.in_entries = total[0];
     I.out_entries = total[1];
     I.total_entries = total[0] + total[1];
-    I.label_bytes = (total[0] + total[1]) * sizeof(uint32_t) + 2 * ((uint64_t)n + 1) * sizeof(uint64_t);
+    I.label_bytes = (total[0] + total[1]) * sizeof(uint32_t) + 2 * ((uint64_t)n + 1) * sizeof(uint64_t) +
+                    2 * (uint64_t)n * sizeof(uint2);
     I.max_dist = std::max(h[0]->max_dist, h[1]->max_dist);
     I.max_label = std::max(h[0]->max_label, h[1]->max_label);
     I.batches = batches;
@@ -1982,12 +1998,14 @@ int build_index(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint3
         M.s = stream;
         idx->d_off = M.get_out<uint64_t>(1);
         idx->d_ent = M.get_out<uint32_t>(4);
+        idx->d_lb = M.get_out<uint2>(1);
         idx->d_order = M.get_out<uint32_t>(1);
         if (directed) {
             idx->directed = true;
             idx->info.directed = 1;
             idx->d_off_out = M.get_out<uint64_t>(1);
             idx->d_ent_out = M.get_out<uint32_t>(4);
+            idx->d_lb_out = M.get_out<uint2>(1);
         }
         if (M.err != hipSuccess) {
             rc = status_of(M.err);
@@ -1998,9 +2016,11 @@ int build_index(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint3
         } else {
             M.forget(idx->d_off);
             M.forget(idx->d_ent);
+            M.forget(idx->d_lb);
             M.forget(idx->d_order);
             M.forget(idx->d_off_out);
             M.forget(idx->d_ent_out);
+            M.forget(idx->d_lb_out);
             idx->info.weighted = weighted ? 1u : 0u;
             idx->info.batch_size = b;
             idx->info.label_bytes = sizeof(uint64_t);
@@ -2120,7 +2140,7 @@ extern "C" int pll_build_labels_noalloc(uint32_t n, uint64_t nnz, const uint64_t
     // the label arena takes half of what the working state leaves, the final
     // entries (as many at most) the other half
     const size_t state = noalloc_state_bytes(n, nnz, W);
-    const size_t fin = 2 * blk(8 * ((size_t)n + 1)) + blk(4 * (size_t)n);
+    const size_t fin = 2 * blk(8 * ((size_t)n + 1)) + blk(4 * (size_t)n) + blk(8 * (size_t)n);
     if (state + fin + kScratchSlack >= kScratchBytes) return PLL_ESCRATCH;
     const uint64_t arena = (kScratchBytes - state - fin - kScratchSlack) / 8;
     if (arena < 32ull * n + 4096) return PLL_ESCRATCH;

@@ -289,6 +289,13 @@ struct pll_index {
     uint64_t* d_off_out;  // directed only: L_out, laid out as d_off / d_ent
     uint32_t* d_ent_out;
     uint32_t* d_order;  // [n], rank -> vertex id
+    // list bounds by vertex id: {hub rank of the first entry, hub rank of the
+    // last entry} of L(v) ({0xFFFFFFFF, 0} for an empty list); the query tells
+    // from them alone when two lists cannot share a hub.  A directed index
+    // keeps L_in's in d_lb and L_out's in d_lb_out.  In the many-graph build
+    // they lie in the shared block `meta`.
+    uint2* d_lb;
+    uint2* d_lb_out;
     uint32_t query_lanes;
     pll_shared_store* store;  // non-null when d_ent points into a shared allocation
     pll_shared_store* meta;   // non-null when d_off and d_order point into a shared allocation

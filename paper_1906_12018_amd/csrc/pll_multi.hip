@@ -50,6 +50,7 @@ struct GraphJob {
     const uint32_t* order;
     uint32_t* rank;
     uint64_t* out_off;  // [n+1] label offsets by vertex id, relative to the graph's output base
+    uint2* out_lb;      // [n] list bounds by vertex id (first and last hub rank; see pll_index)
     GangCtl* gc;
     uint32_t gang;      // workgroups building this graph
 };
@@ -343,6 +344,9 @@ __global__ void __launch_bounds__(kMultiBlock) k_multi_build(const GraphJob* __r
                 out[dst + i] = e;
                 md = max(md, e & 255u);
             }
+            if (lane == 0)
+                J.out_lb[v] = len ? make_uint2(A.arena[src] >> 8, A.arena[src + len - 1] >> 8)
+                                  : make_uint2(0xFFFFFFFFu, 0u);
         }
         md = wave_max32(md);
         const unsigned long long sums[8] = {wave_sum64(st.cand),  wave_sum64(st.acc),     wave_sum64(st.edges),
@@ -575,10 +579,12 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
     if (hipMalloc(&OUT.p, sizeof(uint32_t) * std::max<uint64_t>(out_cap, 64)) != hipSuccess) return PLL_ENOMEM;
     uint64_t meta_bytes = 0;
     for (uint32_t g = 0; g < count; ++g)
-        meta_bytes += align_up(8 * ((uint64_t)graphs[g].n + 1), 256) + align_up(4 * std::max<uint64_t>(graphs[g].n, 1), 256);
+        meta_bytes += align_up(8 * ((uint64_t)graphs[g].n + 1), 256) + align_up(4 * std::max<uint64_t>(graphs[g].n, 1), 256) +
+                      align_up(8 * std::max<uint64_t>(graphs[g].n, 1), 256);
     if (hipMalloc(&META.p, std::max<uint64_t>(meta_bytes, 256)) != hipSuccess) return PLL_ENOMEM;
     std::vector<uint64_t*> out_offs(count, nullptr);
     std::vector<uint32_t*> orders(count, nullptr);
+    std::vector<uint2*> out_lbs(count, nullptr);
     {
         char* mp = (char*)META.p;
         for (uint32_t g = 0; g < count; ++g) {
@@ -586,6 +592,8 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
             mp += align_up(8 * ((uint64_t)graphs[g].n + 1), 256);
             orders[g] = (uint32_t*)mp;
             mp += align_up(4 * std::max<uint64_t>(graphs[g].n, 1), 256);
+            out_lbs[g] = (uint2*)mp;
+            mp += align_up(8 * std::max<uint64_t>(graphs[g].n, 1), 256);
         }
     }
     char* zp = (char*)Z.p;
@@ -630,6 +638,7 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
         A.region_cap = region_cap;
         A.ctr = (DevCounters*)DC.p;
         J.out_off = out_offs[g];
+        J.out_lb = out_lbs[g];
     }
     MultiCtl hctl{};
     hctl.out_cap = out_cap;
@@ -732,6 +741,7 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
         idx->n = graphs[g].n;
         idx->total = R.total;
         idx->d_off = out_offs[g];
+        idx->d_lb = out_lbs[g];
         idx->d_ent = (uint32_t*)store->ptr + R.out_base;
         idx->d_order = orders[g];
         idx->store = store;
@@ -743,7 +753,7 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
         I.total_entries = R.total;
         I.in_entries = R.total;
         I.out_entries = R.total;
-        I.label_bytes = R.total * 4 + 8 * ((uint64_t)graphs[g].n + 1);
+        I.label_bytes = R.total * 4 + 8 * ((uint64_t)graphs[g].n + 1) + 8 * (uint64_t)graphs[g].n;
         I.max_dist = R.max_dist;
         I.max_label = R.max_label;
         I.batches = R.batches;

@@ -293,53 +293,54 @@ __device__ __forceinline__ uint32_t wave_min32_dpp(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
-// Raw chunks of one list's window: entries [base, base + kWin) of `ent`,
-// where base is the first unmerged entry rounded down to 4 entries and the
-// list ends `avail` entries past base.  Chunk r of a lane is chunk
-// lane + 64 r of the window.  A chunk past the list end (or the third chunk
-// of lanes 2..63, which the window does not have) is loaded from the
-// window's first chunk instead, so every load is unconditional and all of
-// them are in flight together; stage_window discards those.
-__device__ __forceinline__ void load_window(const uint32_t* __restrict__ ent, uint64_t base, uint64_t avail,
-                                            uint32_t lane, uint4 (&x)[3]) {
-    const uint32_t hi = (uint32_t)min<uint64_t>(avail, (uint64_t)kWin);
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        const uint32_t q = 4u * (lane + 64u * r);
-        const uint32_t at = q < hi ? q : 0u;
-        x[r] = *reinterpret_cast<const uint4*>(ent + base + at);
-    }
+// Chunk lane + 64 r of a list's window: the window holds entries
+// [base, base + kWin) of `ent`, where base is the first unmerged entry
+// rounded down to 4 entries, and the list ends `hi` entries into it.  A chunk
+// past the list end (or a third chunk of lanes 2..63, which the window does
+// not have) is loaded from the window's first chunk instead, so every load is
+// unconditional and all of them are in flight together; stage_window never
+// counts what those positions hold.
+__device__ __forceinline__ uint4 load_chunk(const uint32_t* __restrict__ ent, uint64_t base, uint32_t hi,
+                                            uint32_t lane, uint32_t r) {
+    const uint32_t q = 4u * (lane + 64u * r);
+    return *reinterpret_cast<const uint4*>(ent + base + (q < hi ? q : 0u));
 }
 
-// Publish a loaded window in LDS: positions past the list end or holding an
-// entry above `limraw` become kSent.  Returns how many published entries at
-// or after position `lo` are not kSent (wave-uniform, counted by ballots).
-__device__ __forceinline__ uint32_t stage_window(const uint4 (&x)[3], uint64_t avail, uint32_t lo, uint32_t limraw,
-                                                 uint32_t* __restrict__ win, uint32_t lane) {
-    const uint32_t hi = (uint32_t)min<uint64_t>(avail, (uint64_t)kWin);
-    uint32_t count = 0;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        const uint32_t q = 4u * (lane + 64u * r);
-        const uint32_t e[4] = {x[r].x, x[r].y, x[r].z, x[r].w};
-        uint32_t o[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const bool ok = q + k < hi && e[k] <= limraw;
-            o[k] = ok ? e[k] : kSent;
-            count += (uint32_t)__builtin_popcountll(__ballot(ok && q + k >= lo));
-        }
-        if (r < 2 || lane < (uint32_t)(kWinChunks - 128))
-            *reinterpret_cast<uint4*>(win + q) = make_uint4(o[0], o[1], o[2], o[3]);
-    }
-    return count;
+// Publish a loaded window in LDS as it is, and return how many of its
+// positions from `lo` on hold list entries not above `limraw`
+// (wave-uniform).  The list is sorted, so those entries form a prefix: the
+// chunks whose last entry is such an entry are counted by ballots, then the
+// first other chunk is read back and its leading such entries counted
+// (positions before `lo`, which precede the first unmerged entry, count
+// and are subtracted).  Positions past the count are never used.
+__device__ __forceinline__ uint32_t stage_window(uint4 x0, uint4 x1, uint4 x2, uint32_t hi, uint32_t lo,
+                                                 uint32_t limraw, uint32_t* __restrict__ win, uint32_t lane) {
+    const uint32_t q0 = 4u * lane, q1 = q0 + 256u, q2 = q0 + 512u;
+    const bool mine2 = lane < (uint32_t)(kWinChunks - 128);
+    *reinterpret_cast<uint4*>(win + q0) = x0;
+    *reinterpret_cast<uint4*>(win + q1) = x1;
+    if (mine2) *reinterpret_cast<uint4*>(win + q2) = x2;
+    const uint32_t full = (uint32_t)__builtin_popcountll(__ballot(q0 + 3 < hi && x0.w <= limraw)) +
+                          (uint32_t)__builtin_popcountll(__ballot(q1 + 3 < hi && x1.w <= limraw)) +
+                          (uint32_t)__builtin_popcountll(__ballot(mine2 && q2 + 3 < hi && x2.w <= limraw));
+    wave_lds_sync();
+    if (full == (uint32_t)kWinChunks) return (uint32_t)kWin - lo;
+    const uint32_t q = 4u * full;
+    const uint4 c = *reinterpret_cast<const uint4*>(win + q);
+    const bool v0 = q < lo || (q < hi && c.x <= limraw);
+    const bool v1 = v0 && (q + 1 < lo || (q + 1 < hi && c.y <= limraw));
+    const bool v2 = v1 && (q + 2 < lo || (q + 2 < hi && c.z <= limraw));
+    const uint32_t n = q + (uint32_t)v0 + (uint32_t)v1 + (uint32_t)v2;
+    return n > lo ? n - lo : 0u;
 }
 
 template <bool BP>
 __global__ void __launch_bounds__(kBlock) k_query_wave(const uint64_t* __restrict__ offu,
                                                        const uint32_t* __restrict__ entu,
+                                                       const uint2* __restrict__ lbu,
                                                        const uint64_t* __restrict__ offv,
-                                                       const uint32_t* __restrict__ entv, uint32_t n, uint64_t count,
+                                                       const uint32_t* __restrict__ entv,
+                                                       const uint2* __restrict__ lbv, uint32_t n, uint64_t count,
                                                        const uint32_t* __restrict__ qu,
                                                        const uint32_t* __restrict__ qv, uint32_t* __restrict__ out,
                                                        const uint8_t* __restrict__ bpd,
@@ -372,65 +373,92 @@ __global__ void __launch_bounds__(kBlock) k_query_wave(const uint64_t* __restric
         }
         // an id out of range has no label: no common hub
         const bool has = lane < np && ul < n && vl < n;
-        uint64_t al = 0, ael = 0, bl = 0, bel = 0;
+        // Entries above the smaller of the two lists' last hubs cannot match
+        // (the list ending there has nothing beyond it); when either list's
+        // first hub is already above it, the lists share no hub and the pair
+        // is answered without reading them (a vertex with no edges, or one
+        // whose label holds no hub ranked above the other vertex).  The list
+        // bounds tell that; only pairs that merge read offsets and entries.
+        uint32_t liml = 0;
+        bool mergel = false;
         if (has) {
+            const uint2 bu = lbu[ul], bv = lbv[vl];
+            const uint32_t lim = min(bu.y, bv.y);
+            mergel = bu.x <= lim && bv.x <= lim;
+            liml = (lim << 8) | 255u;  // compared with raw entries (hub << 8) | dist
+        }
+        uint64_t al = 0, ael = 0, bl = 0, bel = 0;
+        if (mergel) {
             al = offu[ul];
             ael = offu[ul + 1];
             bl = offv[vl];
             bel = offv[vl + 1];
         }
-        // entries above the smaller last hub cannot match: compare raw
-        // entries with (that hub << 8) | 255
-        uint32_t liml = 0;
-        if (al < ael && bl < bel) liml = min(entu[ael - 1], entv[bel - 1]) | 255u;
+        const uint64_t merge_mask = ballot64(mergel);
+        // pairs to visit: those that merge (with bit-parallel labels every
+        // pair with ids in range, for the BP bound)
+        uint64_t todo = BP ? ballot64(has) : merge_mask;
         uint32_t res = PLL_DIST_INF;
-        for (uint32_t k = 0; k < np; ++k) {
-            uint64_t a = readlane64(al, k), ae = readlane64(ael, k);
-            uint64_t b = readlane64(bl, k), be = readlane64(bel, k);
-            const uint32_t limraw = readlane32(liml, k);
+        while (todo) {
+            const uint32_t k = (uint32_t)__builtin_ctzll(todo);
+            todo &= todo - 1;
             uint32_t best = PLL_DIST_INF;
-            if (a < ae && b < be) {
+            if ((merge_mask >> k) & 1ull) {
+                uint64_t a = readlane64(al, k), b = readlane64(bl, k);
+                const uint64_t ae = readlane64(ael, k), be = readlane64(bel, k);
+                const uint32_t limraw = readlane32(liml, k);
                 for (;;) {
                     const uint64_t baseA = a & ~3ull, baseB = b & ~3ull;
                     const uint32_t loA = (uint32_t)(a - baseA), loB = (uint32_t)(b - baseB);
-                    uint4 xa[3], xb[3];
-                    load_window(entu, baseA, ae - baseA, lane, xa);
-                    load_window(entv, baseB, be - baseB, lane, xb);
-                    const uint32_t nA = stage_window(xa, ae - baseA, loA, limraw, sa, lane);
-                    const uint32_t nB = stage_window(xb, be - baseB, loB, limraw, sb, lane);
-                    wave_lds_sync();
+                    const uint32_t hiA = (uint32_t)min<uint64_t>(ae - baseA, (uint64_t)kWin);
+                    const uint32_t hiB = (uint32_t)min<uint64_t>(be - baseB, (uint64_t)kWin);
+                    // every load of both windows is in flight before any is used
+                    const uint4 a0 = load_chunk(entu, baseA, hiA, lane, 0u);
+                    const uint4 a1 = load_chunk(entu, baseA, hiA, lane, 1u);
+                    const uint4 a2 = load_chunk(entu, baseA, hiA, lane, 2u);
+                    const uint4 b0 = load_chunk(entv, baseB, hiB, lane, 0u);
+                    const uint4 b1 = load_chunk(entv, baseB, hiB, lane, 1u);
+                    const uint4 b2 = load_chunk(entv, baseB, hiB, lane, 2u);
+                    const uint32_t nA = stage_window(a0, a1, a2, hiA, loA, limraw, sa, lane);
+                    const uint32_t nB = stage_window(b0, b1, b2, hiB, loB, limraw, sb, lane);
                     if (nA == 0 || nB == 0) break;
                     const uint32_t T = min((uint32_t)kTile, nA + nB);
                     const uint32_t d = min(8u * lane, T);
+                    // lane l's split of the merge path at diagonal d = 8l: the
+                    // number of L(u) entries among the first d merged ones (on
+                    // equal hubs the L(u) entry goes first)
                     uint32_t lo = d > nB ? d - nB : 0u, hi = min(d, nA);
                     while (lo < hi) {
                         const uint32_t mid = (lo + hi) >> 1;
-                        const uint32_t x = sa[loA + mid], y = sb[loB + d - 1 - mid];
-                        if (x <= (y | 255u))
+                        if (sa[loA + mid] <= (sb[loB + d - 1 - mid] | 255u))
                             lo = mid + 1;
                         else
                             hi = mid;
                     }
-                    // walk 8 merged entries; both heads are read every step
-                    uint32_t pa = loA + lo, pb = loB + (d - lo);
-                    const uint32_t steps = T - d;
+                    const uint32_t i = lo;
+                    // walk 8 merged entries; both heads are read every step,
+                    // and a head past its list's counted entries is not used.
+                    // In a tile shorter than 512 every list is counted whole,
+                    // so lanes past its end only step past both ends.
+                    uint32_t pa = loA + i, pb = loB + (d - i);
+                    const uint32_t endA = loA + nA, endB = loB + nB;
                     uint32_t x = sa[pa], y = sb[pb];
 #pragma unroll
                     for (uint32_t t = 0; t < 8; ++t) {
-                        const bool live = t < steps;
-                        const bool take_a = live && x <= (y | 255u);
+                        const bool b_ok = pb < endB;
+                        const bool take_a = pa < endA && (!b_ok || x <= (y | 255u));
                         const uint32_t sum = (x & 255u) + (y & 255u);
-                        best = (take_a && (x ^ y) < 256u) ? min(best, sum) : best;
+                        best = (take_a && b_ok && (x ^ y) < 256u) ? min(best, sum) : best;
                         pa += take_a ? 1u : 0u;
-                        pb += (live && !take_a) ? 1u : 0u;
+                        pb += take_a ? 0u : 1u;
                         x = sa[pa];
                         y = sb[pb];
                     }
                     // lane 63 ended exactly where the tile ends on the merge path
                     const uint32_t iT = readlane32(pa - loA, 63);
                     const uint32_t jT = T - iT;
-                    // a list whose valid part ended inside its window and has
-                    // been merged whole ends the merge
+                    // a list whose counted entries ended inside its window and
+                    // have been merged whole ends the merge
                     if ((iT == nA && nA < (uint32_t)kWin - loA) || (jT == nB && nB < (uint32_t)kWin - loB)) break;
                     a += iT;
                     b += jT;
@@ -440,7 +468,7 @@ __global__ void __launch_bounds__(kBlock) k_query_wave(const uint64_t* __restric
             }
             if (BP) {
                 const uint32_t u = readlane32(ul, k), v = readlane32(vl, k);
-                if (u < n && v < n) best = min(best, bp_bound(bpd, bps, bpt, u, v, lane, 64));
+                best = min(best, bp_bound(bpd, bps, bpt, u, v, lane, 64));
             }
             best = wave_min32_dpp(best);
             res = lane == k ? best : res;
@@ -471,13 +499,15 @@ void launch_wave(const pll_index* idx, uint64_t count, const uint32_t* d_u, cons
     if (blocks > cap) blocks = cap;
     const uint64_t* offu = idx->directed ? idx->d_off_out : idx->d_off;
     const uint32_t* entu = idx->directed ? idx->d_ent_out : idx->d_ent;
+    const uint2* lbu = idx->directed ? idx->d_lb_out : idx->d_lb;
     if (idx->info.bp_roots)
-        k_query_wave<true><<<(uint32_t)blocks, kBlock, 0, stream>>>(offu, entu, idx->d_off, idx->d_ent, idx->n, count,
-                                                                    d_u, d_v, d_out, idx->d_bp_dist, idx->d_bp_sets,
-                                                                    idx->info.bp_roots);
+        k_query_wave<true><<<(uint32_t)blocks, kBlock, 0, stream>>>(offu, entu, lbu, idx->d_off, idx->d_ent, idx->d_lb,
+                                                                    idx->n, count, d_u, d_v, d_out, idx->d_bp_dist,
+                                                                    idx->d_bp_sets, idx->info.bp_roots);
     else
-        k_query_wave<false><<<(uint32_t)blocks, kBlock, 0, stream>>>(offu, entu, idx->d_off, idx->d_ent, idx->n,
-                                                                     count, d_u, d_v, d_out, nullptr, nullptr, 0);
+        k_query_wave<false><<<(uint32_t)blocks, kBlock, 0, stream>>>(offu, entu, lbu, idx->d_off, idx->d_ent,
+                                                                     idx->d_lb, idx->n, count, d_u, d_v, d_out,
+                                                                     nullptr, nullptr, 0);
 }
 
 // Grid: a multiple of the workgroups that fit on the device at once (every

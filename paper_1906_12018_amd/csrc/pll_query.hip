@@ -263,23 +263,34 @@ __global__ void __launch_bounds__(kBlock) k_query_group(const uint64_t* __restri
 
 // ---- one pair per wave: merge-path tiles ----------------------------------------------------------
 //
-// The wave merges the two lists in tiles of kTile merged entries (8 per
-// lane).  Each tile stages a window of each list in LDS (one aligned 16-byte
-// load per chunk, up to kWin entries from the first unmerged entry); entries
-// past the smaller of the two lists' last hubs can match nothing (the list
-// with that last hub ends there, Section 2.1's merge stops) and are staged
-// as a sentinel.  Lane l finds where diagonal 8l of the tile crosses the
-// merge path by binary search (the number of A entries among the first 8l
-// merged ones; on equal hubs the A entry goes first), then walks its 8
-// merged entries.  Because the A entry of a common hub immediately precedes
-// the B entry in merged order, the lane that takes an A entry sees its
-// partner as its current B entry, so every common hub is found exactly
-// once, also across lane and tile boundaries.
+// The wave merges the two lists in tiles of up to kTile merged entries.  Each
+// tile stages a window of each list in LDS: up to kWin entries from the first
+// unmerged one rounded down to a 4-entry boundary, read as 16-byte chunks
+// through a buffer resource that ends at the list's end, so chunks past it
+// read as zero and are not fetched.  Entries past the smaller of the two
+// lists' last hubs can match nothing (the list with that last hub ends there
+// and the merge of Section 2.1 stops), so a window counts only its entries up
+// to that hub, and the kPad positions after the counted ones are overwritten
+// with a sentinel that sorts after every entry.  Lane l finds where diagonal
+// S*l of the tile crosses the merge path by binary search (the number of A
+// entries among the first S*l merged ones; on equal hubs the A entry goes
+// first), then walks its S merged entries.  S is 8 in a full tile and 4, 2 or
+// 1 when the last tile is short.  Because the A entry of a common hub
+// immediately precedes the B entry in merged order, the lane that takes an A
+// entry sees its partner as its current B entry, so every common hub is
+// found, also across lane and tile boundaries.  A lane past both counted ends
+// meets two sentinels, which look like one hub; their sum (kNoHub) exceeds
+// every real sum (distances are below 255) and is read as no common hub.
 constexpr int kTile = 512;
 constexpr int kWinChunks = 130;             // 16-byte chunks staged per list
 constexpr int kWin = 4 * kWinChunks;        // 520 entries: a tile plus the alignment offset plus lookahead
-constexpr uint32_t kSent = 0xFFFFFFFFu;     // after every entry; never equal to one (hub ranks < 2^24 - 1)
+constexpr int kPad = 16;                    // sentinel positions after the counted entries
+constexpr uint32_t kSent = 0xFFFFFFFFu;     // sorts after every entry (hub ranks < 2^24 - 1)
+constexpr uint32_t kNoHub = 2u * 255u;      // the sum of two sentinels' distance bytes
 constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kRawBufferWord3 = 0x00020000; // buffer resource word 3: 32-bit data, unswizzled (gfx9)
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Minimum over the 64 lanes by DPP moves (the whole wave active); the result
 // is wave-uniform.
@@ -293,45 +304,110 @@ __device__ __forceinline__ uint32_t wave_min32_dpp(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
-// Chunk lane + 64 r of a list's window: the window holds entries
-// [base, base + kWin) of `ent`, where base is the first unmerged entry
-// rounded down to 4 entries, and the list ends `hi` entries into it.  A chunk
-// past the list end (or a third chunk of lanes 2..63, which the window does
-// not have) is loaded from the window's first chunk instead, so every load is
-// unconditional and all of them are in flight together; stage_window never
-// counts what those positions hold.
-__device__ __forceinline__ uint4 load_chunk(const uint32_t* __restrict__ ent, uint64_t base, uint32_t hi,
-                                            uint32_t lane, uint32_t r) {
-    const uint32_t q = 4u * (lane + 64u * r);
-    return *reinterpret_cast<const uint4*>(ent + base + (q < hi ? q : 0u));
+// A window's chunks lane, lane + 64 and lane + 128 (the window has kWinChunks
+// of them).  Entries [base, base + hi) of `ent` are in range, hi rounded up to
+// a whole chunk (label arrays are padded to whole 4-entry chunks and `base`
+// is a multiple of 4); chunks past that read as zero without a memory access.
+// All three loads are in flight before any is used.
+struct Window {
+    u32x4 c0, c1, c2;
+};
+
+__device__ __forceinline__ Window load_window(const uint32_t* __restrict__ ent, uint64_t base, uint32_t hi,
+                                              uint32_t lane) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t*>(ent + base), 0, (int)(((hi + 3u) & ~3u) * 4u), kRawBufferWord3);
+    const int off = (int)(16u * lane);
+    Window w;
+    w.c0 = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+    w.c1 = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 1024, 0, 0);
+    w.c2 = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 2048, 0, 0);
+    return w;
 }
 
-// Publish a loaded window in LDS as it is, and return how many of its
-// positions from `lo` on hold list entries not above `limraw`
-// (wave-uniform).  The list is sorted, so those entries form a prefix: the
-// chunks whose last entry is such an entry are counted by ballots, then the
-// first other chunk is read back and its leading such entries counted
-// (positions before `lo`, which precede the first unmerged entry, count
-// and are subtracted).  Positions past the count are never used.
-__device__ __forceinline__ uint32_t stage_window(uint4 x0, uint4 x1, uint4 x2, uint32_t hi, uint32_t lo,
-                                                 uint32_t limraw, uint32_t* __restrict__ win, uint32_t lane) {
-    const uint32_t q0 = 4u * lane, q1 = q0 + 256u, q2 = q0 + 512u;
-    const bool mine2 = lane < (uint32_t)(kWinChunks - 128);
-    *reinterpret_cast<uint4*>(win + q0) = x0;
-    *reinterpret_cast<uint4*>(win + q1) = x1;
-    if (mine2) *reinterpret_cast<uint4*>(win + q2) = x2;
-    const uint32_t full = (uint32_t)__builtin_popcountll(__ballot(q0 + 3 < hi && x0.w <= limraw)) +
-                          (uint32_t)__builtin_popcountll(__ballot(q1 + 3 < hi && x1.w <= limraw)) +
-                          (uint32_t)__builtin_popcountll(__ballot(mine2 && q2 + 3 < hi && x2.w <= limraw));
-    wave_lds_sync();
-    if (full == (uint32_t)kWinChunks) return (uint32_t)kWin - lo;
-    const uint32_t q = 4u * full;
-    const uint4 c = *reinterpret_cast<const uint4*>(win + q);
-    const bool v0 = q < lo || (q < hi && c.x <= limraw);
-    const bool v1 = v0 && (q + 1 < lo || (q + 1 < hi && c.y <= limraw));
-    const bool v2 = v1 && (q + 2 < lo || (q + 2 < hi && c.z <= limraw));
-    const uint32_t n = q + (uint32_t)v0 + (uint32_t)v1 + (uint32_t)v2;
-    return n > lo ? n - lo : 0u;
+// Publish a window in LDS and return how many of its positions from `lo` on
+// count: list entries not above `limraw` (wave-uniform).  The list is sorted,
+// so those form a prefix of it.  The first chunk whose last entry is above
+// limraw is found by ballots, its leading entries not above limraw are
+// counted from lane registers (positions before `lo` precede the first
+// unmerged entry; they count and are subtracted), and the count is cut at the
+// list's end `hi`.  After `hi` the window holds the next list's entries up to
+// the chunk end, then zeros.  Those can only make the cut at `hi` decide, in
+// which case list entries above limraw may count: that lengthens the merge
+// but cannot change its result, since a hub common to both lists is a real
+// common hub wherever it lies.
+__device__ __forceinline__ uint32_t stage_window(const Window& w, uint32_t hi, uint32_t lo, uint32_t limraw,
+                                                 uint32_t* __restrict__ win, uint32_t lane) {
+    const uint32_t q0 = 4u * lane;
+    *reinterpret_cast<u32x4*>(win + q0) = w.c0;
+    *reinterpret_cast<u32x4*>(win + q0 + 256u) = w.c1;
+    if (lane < (uint32_t)(kWinChunks - 128)) *reinterpret_cast<u32x4*>(win + q0 + 512u) = w.c2;
+    const uint64_t b0 = ballot64(w.c0.w > limraw), b1 = ballot64(w.c1.w > limraw), b2 = ballot64(w.c2.w > limraw);
+    uint32_t c, x, y, z;
+    if (b0) {
+        c = (uint32_t)__builtin_ctzll(b0);
+        x = readlane32(w.c0.x, c), y = readlane32(w.c0.y, c), z = readlane32(w.c0.z, c);
+    } else if (b1) {
+        c = (uint32_t)__builtin_ctzll(b1);
+        x = readlane32(w.c1.x, c), y = readlane32(w.c1.y, c), z = readlane32(w.c1.z, c);
+        c += 64;
+    } else if (b2) {
+        c = (uint32_t)__builtin_ctzll(b2);
+        x = readlane32(w.c2.x, c), y = readlane32(w.c2.y, c), z = readlane32(w.c2.z, c);
+        c += 128;
+    } else {
+        return hi > lo ? hi - lo : 0u;
+    }
+    const uint32_t q = 4u * c;
+    const bool v0 = q < lo || x <= limraw;
+    const bool v1 = v0 && (q + 1 < lo || y <= limraw);
+    const bool v2 = v1 && (q + 2 < lo || z <= limraw);
+    const uint32_t cnt = min(q + (uint32_t)v0 + (uint32_t)v1 + (uint32_t)v2, hi);
+    return cnt > lo ? cnt - lo : 0u;
+}
+
+// Lane l's share of a tile of T merged entries (T <= 64 S): the S merged
+// entries from diagonal S*l (none past T).  `lds` is the block's window
+// array; the wave's A window starts at word wa of it and its counted entries
+// are [loA, loA + nA) of that window, B likewise from word wb, both followed
+// by sentinels.  Returns the lane's smallest sum over common hubs so far;
+// pa_end is the A window position after its last step.
+template <int S>
+__device__ __forceinline__ uint32_t merge_tile(const uint32_t* __restrict__ lds, uint32_t wa, uint32_t wb,
+                                               uint32_t loA, uint32_t loB, uint32_t nA, uint32_t nB, uint32_t T,
+                                               uint32_t lane, uint32_t best, uint32_t& pa_end) {
+    const uint32_t d = min((uint32_t)S * lane, T);
+    uint32_t lo = d > nB ? d - nB : 0u, hi = min(d, nA);
+    const uint32_t* sa = lds + wa + loA;
+    const uint32_t* sb = lds + wb + loB + d - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (sa[mid] <= (sb[-(int)mid] | 255u))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    // The walk keeps the A head as a byte offset oa into `lds`; at step t
+    // the B head is at byte offset kb + 4t - oa.  The A entry goes first
+    // when its hub is not above the B entry's: x <= y, or the same hub.
+    const char* base = reinterpret_cast<const char*>(lds);
+    uint32_t oa = 4u * (wa + loA + lo);
+    const uint32_t kb = 4u * (wa + wb + loA + loB + d);
+    uint32_t x = *reinterpret_cast<const uint32_t*>(base + oa);
+    uint32_t y = *reinterpret_cast<const uint32_t*>(base + (kb - oa));
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+        const bool same = (x ^ y) < 256u;
+        const uint32_t sum = (x & 255u) + (y & 255u);
+        best = same ? min(best, sum) : best;
+        oa += (x <= y || same) ? 4u : 0u;
+        if (t + 1 < S) {
+            x = *reinterpret_cast<const uint32_t*>(base + oa);
+            y = *reinterpret_cast<const uint32_t*>(base + (kb + 4u * (uint32_t)(t + 1) - oa));
+        }
+    }
+    pa_end = oa / 4u - wa;
+    return best;
 }
 
 template <bool BP>
@@ -345,24 +421,21 @@ __global__ void __launch_bounds__(kBlock) k_query_wave(const uint64_t* __restric
                                                        const uint32_t* __restrict__ qv, uint32_t* __restrict__ out,
                                                        const uint8_t* __restrict__ bpd,
                                                        const ulonglong2* __restrict__ bps, uint32_t bpt) {
-    __shared__ uint4 s_win[kWavesPerBlock][2][(kWin + 16) / 4];
+    constexpr uint32_t kWinWords = kWin + kPad;  // one list's window, a multiple of 4 words
+    __shared__ __align__(16) uint32_t s_win[kWavesPerBlock * 2 * kWinWords];
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t wv = threadIdx.x >> 6;
-    uint32_t* sa = reinterpret_cast<uint32_t*>(s_win[wv][0]);
-    uint32_t* sb = reinterpret_cast<uint32_t*>(s_win[wv][1]);
-    // lookahead past a full window reads the padding: the sentinel
-    if (lane < 16) {
-        sa[kWin + lane] = kSent;
-        sb[kWin + lane] = kSent;
-    }
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t oA = wv * 2 * kWinWords, oB = oA + kWinWords;  // the wave's windows, in words
+    uint32_t* sa = s_win + oA;
+    uint32_t* sb = s_win + oB;
     // A wave takes groups of 64 consecutive pairs.  Lane l first gathers pair
-    // l's ids, list bounds and last entries, so these dependent loads are in
+    // l's ids, list bounds and list offsets, so these dependent loads are in
     // flight for all 64 pairs at once; the wave then merges the pairs one by
     // one, reading their bounds from lane registers, and stores the 64
     // answers together.
     const uint64_t groups = (count + 63) / 64;
     const uint64_t gstride = (uint64_t)gridDim.x * kWavesPerBlock;
-    for (uint64_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + wv); g < groups; g += gstride) {
+    for (uint64_t g = blockIdx.x * kWavesPerBlock + wv; g < groups; g += gstride) {
         const uint64_t p0 = g * 64;
         const uint32_t np = (uint32_t)min<uint64_t>(64, count - p0);
         const uint64_t pl = p0 + lane;
@@ -412,59 +485,44 @@ __global__ void __launch_bounds__(kBlock) k_query_wave(const uint64_t* __restric
                     const uint32_t loA = (uint32_t)(a - baseA), loB = (uint32_t)(b - baseB);
                     const uint32_t hiA = (uint32_t)min<uint64_t>(ae - baseA, (uint64_t)kWin);
                     const uint32_t hiB = (uint32_t)min<uint64_t>(be - baseB, (uint64_t)kWin);
-                    // every load of both windows is in flight before any is used
-                    const uint4 a0 = load_chunk(entu, baseA, hiA, lane, 0u);
-                    const uint4 a1 = load_chunk(entu, baseA, hiA, lane, 1u);
-                    const uint4 a2 = load_chunk(entu, baseA, hiA, lane, 2u);
-                    const uint4 b0 = load_chunk(entv, baseB, hiB, lane, 0u);
-                    const uint4 b1 = load_chunk(entv, baseB, hiB, lane, 1u);
-                    const uint4 b2 = load_chunk(entv, baseB, hiB, lane, 2u);
-                    const uint32_t nA = stage_window(a0, a1, a2, hiA, loA, limraw, sa, lane);
-                    const uint32_t nB = stage_window(b0, b1, b2, hiB, loB, limraw, sb, lane);
+                    // both windows' loads are in flight before either is used
+                    const Window wa = load_window(entu, baseA, hiA, lane);
+                    const Window wb = load_window(entv, baseB, hiB, lane);
+                    const uint32_t nA = stage_window(wa, hiA, loA, limraw, sa, lane);
+                    const uint32_t nB = stage_window(wb, hiB, loB, limraw, sb, lane);
                     if (nA == 0 || nB == 0) break;
-                    const uint32_t T = min((uint32_t)kTile, nA + nB);
-                    const uint32_t d = min(8u * lane, T);
-                    // lane l's split of the merge path at diagonal d = 8l: the
-                    // number of L(u) entries among the first d merged ones (on
-                    // equal hubs the L(u) entry goes first)
-                    uint32_t lo = d > nB ? d - nB : 0u, hi = min(d, nA);
-                    while (lo < hi) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if (sa[loA + mid] <= (sb[loB + d - 1 - mid] | 255u))
-                            lo = mid + 1;
+                    if (lane < (uint32_t)kPad) {
+                        sa[loA + nA + lane] = kSent;
+                        sb[loB + nB + lane] = kSent;
+                    }
+                    wave_lds_sync();
+                    const uint32_t tot = nA + nB;
+                    uint32_t pa;
+                    if (tot <= (uint32_t)kTile) {
+                        // the last tile: both counted parts end in it
+                        if (tot <= 64)
+                            best = merge_tile<1>(s_win, oA, oB, loA, loB, nA, nB, tot, lane, best, pa);
+                        else if (tot <= 128)
+                            best = merge_tile<2>(s_win, oA, oB, loA, loB, nA, nB, tot, lane, best, pa);
+                        else if (tot <= 256)
+                            best = merge_tile<4>(s_win, oA, oB, loA, loB, nA, nB, tot, lane, best, pa);
                         else
-                            hi = mid;
+                            best = merge_tile<8>(s_win, oA, oB, loA, loB, nA, nB, tot, lane, best, pa);
+                        break;
                     }
-                    const uint32_t i = lo;
-                    // walk 8 merged entries; both heads are read every step,
-                    // and a head past its list's counted entries is not used.
-                    // In a tile shorter than 512 every list is counted whole,
-                    // so lanes past its end only step past both ends.
-                    uint32_t pa = loA + i, pb = loB + (d - i);
-                    const uint32_t endA = loA + nA, endB = loB + nB;
-                    uint32_t x = sa[pa], y = sb[pb];
-#pragma unroll
-                    for (uint32_t t = 0; t < 8; ++t) {
-                        const bool b_ok = pb < endB;
-                        const bool take_a = pa < endA && (!b_ok || x <= (y | 255u));
-                        const uint32_t sum = (x & 255u) + (y & 255u);
-                        best = (take_a && b_ok && (x ^ y) < 256u) ? min(best, sum) : best;
-                        pa += take_a ? 1u : 0u;
-                        pb += take_a ? 0u : 1u;
-                        x = sa[pa];
-                        y = sb[pb];
-                    }
+                    best = merge_tile<8>(s_win, oA, oB, loA, loB, nA, nB, (uint32_t)kTile, lane, best, pa);
                     // lane 63 ended exactly where the tile ends on the merge path
                     const uint32_t iT = readlane32(pa - loA, 63);
-                    const uint32_t jT = T - iT;
-                    // a list whose counted entries ended inside its window and
-                    // have been merged whole ends the merge
-                    if ((iT == nA && nA < (uint32_t)kWin - loA) || (jT == nB && nB < (uint32_t)kWin - loB)) break;
+                    const uint32_t jT = (uint32_t)kTile - iT;
+                    // a list whose counted entries are all merged ends the
+                    // merge (a full window holds more than a tile)
+                    if (iT == nA || jT == nB) break;
                     a += iT;
                     b += jT;
                     wave_lds_sync();
                 }
                 wave_lds_sync();
+                best = best >= kNoHub ? PLL_DIST_INF : best;
             }
             if (BP) {
                 const uint32_t u = readlane32(ul, k), v = readlane32(vl, k);
@@ -478,7 +536,9 @@ __global__ void __launch_bounds__(kBlock) k_query_wave(const uint64_t* __restric
 }
 
 // One pair at a time per wave, in groups of 64 pairs; waves loop over
-// groups.  Grid: 8x the workgroups that fit on the device at once.
+// groups.  Grid: 8x the workgroups that fit on the device at once (measured
+// on a 2^20-vertex R-MAT index with 10^7 pairs: 8x 4.18 ms, 32x 4.22 ms,
+// 128x 4.28 ms).
 void launch_wave(const pll_index* idx, uint64_t count, const uint32_t* d_u, const uint32_t* d_v, uint32_t* d_out,
                  hipStream_t stream) {
     static std::atomic<uint64_t> cap_cache[64];

@@ -138,6 +138,8 @@ typedef struct {
                                   the first push of each batch, rows longer than 1,024 entries and the senders
                                   of gathered rounds (rounds with at least n/2 receivers, graphs of 16,384
                                   vertices or more) */
+    uint32_t query_lanes;     /* lanes per pair pll_query uses on this index now (the automatic choice resolved):
+                                 1, 4, 8, 16, 32 or 64 */
 } pll_index_info;
 
 /* One graph of a batched build (all pointers are device pointers). */
@@ -292,8 +294,10 @@ int pll_export_bp(const pll_index* idx, uint32_t* d_roots, uint32_t* d_nbrs, uin
  * Lanes per pair follow opts->query_lanes of the build: 1 runs a scalar
  * two-pointer merge per lane; G in {4..32} lets G lanes merge the two lists
  * in windows of 4G entries; 64 gives each pair a whole wave, which merges
- * the lists in merge-path tiles of 512 entries staged in LDS; 0 picks G from
- * the mean label length.
+ * the lists in merge-path tiles of 512 entries staged in LDS; 0 picks 64
+ * when the mean label holds 32 entries or more, else the smallest G in
+ * {4..32} with 4G >= the mean.  pll_index_info.query_lanes reports the
+ * value in use.
  */
 int pll_query(const pll_index* idx, uint64_t count, const uint32_t* d_u, const uint32_t* d_v, uint32_t* d_out,
               hipStream_t stream);

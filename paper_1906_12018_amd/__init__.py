@@ -94,6 +94,7 @@ class IndexInfo(ctypes.Structure):
         ("bp_vertices", ctypes.c_uint32),
         ("bp_pruned", ctypes.c_uint64),
         ("check_push_edges", ctypes.c_uint64),
+        ("query_lanes", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:

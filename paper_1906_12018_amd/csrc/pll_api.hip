@@ -98,6 +98,7 @@ int pll_index_set_query_lanes(pll_index* idx, uint32_t lanes) {
 int pll_index_info_get(const pll_index* idx, pll_index_info* out) {
     if (!idx || !out) return PLL_EINVAL;
     *out = idx->info;
+    out->query_lanes = pll_query_lanes(idx);
     return PLL_OK;
 }
 

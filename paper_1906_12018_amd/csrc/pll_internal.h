@@ -253,6 +253,9 @@ int pll_build_one(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uin
                   const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out);
 int pll_query_launch(const pll_index* idx, uint64_t count, const uint32_t* d_u, const uint32_t* d_v,
                      uint32_t* d_out, hipStream_t stream);
+// Lanes per pair the next pll_query on idx uses (query_lanes, or the
+// automatic choice from the mean label length).
+uint32_t pll_query_lanes(const pll_index* idx);
 
 int pll_build_directed(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint32_t* d_col,
                        const uint32_t* d_order, const pll_build_opts* opts, hipStream_t stream, pll_index** out);

@@ -282,8 +282,10 @@ __global__ void __launch_bounds__(kBlock) k_query_group(const uint64_t* __restri
 // meets two sentinels, which look like one hub; their sum (kNoHub) exceeds
 // every real sum (distances are below 255) and is read as no common hub.
 constexpr int kTile = 512;
-constexpr int kWinChunks = 130;             // 16-byte chunks staged per list
-constexpr int kWin = 4 * kWinChunks;        // 520 entries: a tile plus the alignment offset plus lookahead
+constexpr int kWinChunks = kTile / 4 + 2;   // 16-byte chunks staged per list: a tile plus the alignment
+                                            // offset plus lookahead
+constexpr int kWin = 4 * kWinChunks;        // entries
+constexpr int kRows = (kWinChunks + 63) / 64;  // chunk rows a lane loads
 constexpr int kPad = 16;                    // sentinel positions after the counted entries
 constexpr uint32_t kSent = 0xFFFFFFFFu;     // sorts after every entry (hub ranks < 2^24 - 1)
 constexpr uint32_t kNoHub = 2u * 255u;      // the sum of two sentinels' distance bytes
@@ -304,13 +306,13 @@ __device__ __forceinline__ uint32_t wave_min32_dpp(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
-// A window's chunks lane, lane + 64 and lane + 128 (the window has kWinChunks
-// of them).  Entries [base, base + hi) of `ent` are in range, hi rounded up to
-// a whole chunk (label arrays are padded to whole 4-entry chunks and `base`
-// is a multiple of 4); chunks past that read as zero without a memory access.
-// All three loads are in flight before any is used.
+// A window's chunks lane + 64 r, r < kRows (the window has kWinChunks of
+// them).  Entries [base, base + hi) of `ent` are in range, hi rounded up to a
+// whole chunk (label arrays are padded to whole 4-entry chunks and `base` is
+// a multiple of 4); chunks past that read as zero without a memory access.
+// All loads are in flight before any is used.
 struct Window {
-    u32x4 c0, c1, c2;
+    u32x4 c[kRows];
 };
 
 __device__ __forceinline__ Window load_window(const uint32_t* __restrict__ ent, uint64_t base, uint32_t hi,
@@ -319,9 +321,8 @@ __device__ __forceinline__ Window load_window(const uint32_t* __restrict__ ent, 
         const_cast<uint32_t*>(ent + base), 0, (int)(((hi + 3u) & ~3u) * 4u), kRawBufferWord3);
     const int off = (int)(16u * lane);
     Window w;
-    w.c0 = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-    w.c1 = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 1024, 0, 0);
-    w.c2 = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 2048, 0, 0);
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) w.c[r] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 1024 * r, 0, 0);
     return w;
 }
 
@@ -339,31 +340,25 @@ __device__ __forceinline__ Window load_window(const uint32_t* __restrict__ ent, 
 __device__ __forceinline__ uint32_t stage_window(const Window& w, uint32_t hi, uint32_t lo, uint32_t limraw,
                                                  uint32_t* __restrict__ win, uint32_t lane) {
     const uint32_t q0 = 4u * lane;
-    *reinterpret_cast<u32x4*>(win + q0) = w.c0;
-    *reinterpret_cast<u32x4*>(win + q0 + 256u) = w.c1;
-    if (lane < (uint32_t)(kWinChunks - 128)) *reinterpret_cast<u32x4*>(win + q0 + 512u) = w.c2;
-    const uint64_t b0 = ballot64(w.c0.w > limraw), b1 = ballot64(w.c1.w > limraw), b2 = ballot64(w.c2.w > limraw);
-    uint32_t c, x, y, z;
-    if (b0) {
-        c = (uint32_t)__builtin_ctzll(b0);
-        x = readlane32(w.c0.x, c), y = readlane32(w.c0.y, c), z = readlane32(w.c0.z, c);
-    } else if (b1) {
-        c = (uint32_t)__builtin_ctzll(b1);
-        x = readlane32(w.c1.x, c), y = readlane32(w.c1.y, c), z = readlane32(w.c1.z, c);
-        c += 64;
-    } else if (b2) {
-        c = (uint32_t)__builtin_ctzll(b2);
-        x = readlane32(w.c2.x, c), y = readlane32(w.c2.y, c), z = readlane32(w.c2.z, c);
-        c += 128;
-    } else {
-        return hi > lo ? hi - lo : 0u;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r)
+        if (r + 1 < kRows || lane < (uint32_t)(kWinChunks - 64 * (kRows - 1)))
+            *reinterpret_cast<u32x4*>(win + q0 + 256u * r) = w.c[r];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const uint64_t bad = ballot64(w.c[r].w > limraw);
+        if (bad) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(bad);
+            const uint32_t x = readlane32(w.c[r].x, l), y = readlane32(w.c[r].y, l), z = readlane32(w.c[r].z, l);
+            const uint32_t q = 4u * (l + 64u * r);
+            const bool v0 = q < lo || x <= limraw;
+            const bool v1 = v0 && (q + 1 < lo || y <= limraw);
+            const bool v2 = v1 && (q + 2 < lo || z <= limraw);
+            const uint32_t cnt = min(q + (uint32_t)v0 + (uint32_t)v1 + (uint32_t)v2, hi);
+            return cnt > lo ? cnt - lo : 0u;
+        }
     }
-    const uint32_t q = 4u * c;
-    const bool v0 = q < lo || x <= limraw;
-    const bool v1 = v0 && (q + 1 < lo || y <= limraw);
-    const bool v2 = v1 && (q + 2 < lo || z <= limraw);
-    const uint32_t cnt = min(q + (uint32_t)v0 + (uint32_t)v1 + (uint32_t)v2, hi);
-    return cnt > lo ? cnt - lo : 0u;
+    return hi > lo ? hi - lo : 0u;
 }
 
 // Lane l's share of a tile of T merged entries (T <= 64 S): the S merged
@@ -506,11 +501,13 @@ __global__ void __launch_bounds__(kBlock) k_query_wave(const uint64_t* __restric
                             best = merge_tile<2>(s_win, oA, oB, loA, loB, nA, nB, tot, lane, best, pa);
                         else if (tot <= 256)
                             best = merge_tile<4>(s_win, oA, oB, loA, loB, nA, nB, tot, lane, best, pa);
-                        else
+                        else if (kTile == 512 || tot <= 512)
                             best = merge_tile<8>(s_win, oA, oB, loA, loB, nA, nB, tot, lane, best, pa);
+                        else
+                            best = merge_tile<kTile / 64>(s_win, oA, oB, loA, loB, nA, nB, tot, lane, best, pa);
                         break;
                     }
-                    best = merge_tile<8>(s_win, oA, oB, loA, loB, nA, nB, (uint32_t)kTile, lane, best, pa);
+                    best = merge_tile<kTile / 64>(s_win, oA, oB, loA, loB, nA, nB, (uint32_t)kTile, lane, best, pa);
                     // lane 63 ended exactly where the tile ends on the merge path
                     const uint32_t iT = readlane32(pa - loA, 63);
                     const uint32_t jT = (uint32_t)kTile - iT;
@@ -611,17 +608,25 @@ void launch_group(const pll_index* idx, uint64_t count, const uint32_t* d_u, con
 // lane) should hold about one average label.
 uint32_t query_lanes_auto(const pll_index* idx) {
     const uint64_t mean = idx->n ? (idx->total + (idx->directed ? idx->total_out : idx->total)) / (2ull * idx->n) : 0;
+    // a whole wave per pair from a mean label of 32 entries on (measured on
+    // R-MAT indexes of 2^14..2^20 vertices, mean labels of 44..241 entries:
+    // the wave kernel was fastest at every size); smaller groups below
+    if (mean >= 32) return 64;
     uint32_t g = 4;
-    while (g < 64 && 4ull * g < mean) g *= 2;
+    while (g < 32 && 4ull * g < mean) g *= 2;
     return g;
 }
 
 }  // namespace
 
+uint32_t pll_query_lanes(const pll_index* idx) {
+    return idx->query_lanes ? idx->query_lanes : query_lanes_auto(idx);
+}
+
 int pll_query_launch(const pll_index* idx, uint64_t count, const uint32_t* d_u, const uint32_t* d_v,
                      uint32_t* d_out, hipStream_t stream) {
     if (count == 0) return PLL_OK;
-    const uint32_t g = idx->query_lanes ? idx->query_lanes : query_lanes_auto(idx);
+    const uint32_t g = pll_query_lanes(idx);
     switch (g) {
         case 1: {
             uint64_t blocks = (count + kBlock - 1) / kBlock;

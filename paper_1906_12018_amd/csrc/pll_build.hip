@@ -713,14 +713,30 @@ __global__ void k_bp_ids(uint32_t t, const uint32_t* order, const uint32_t* root
     }
 }
 
+// 1 + the highest rank with an edge, into ctr->edge_end.  A batch whose
+// roots all rank at or above it has isolated roots only: each root's label is
+// its self entry, and no other label holds it, so such batches need no run.
+__global__ void __launch_bounds__(kBlock) k_edge_end(uint32_t n, const uint64_t* rrow, DevCounters* ctr) {
+    uint32_t m = 0;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+        if (rrow[r + 1] > rrow[r]) m = r + 1;
+    m = wave_max32(m);
+    if (lane_id() == 0 && m) atomicMax(&ctr->edge_end, m);
+}
+
 // ---- finalize -----------------------------------------------------------------------------------
 
+// Lists of ranks r >= self_from were never batch roots (their batches held
+// isolated vertices only): each gets its self entry (r, 0) here, after any
+// entries it holds (none, for an isolated vertex).
+
 __global__ void __launch_bounds__(kBlock) k_final_lens(uint32_t n, const uint32_t* rank, const uint32_t* llen,
-                                                       uint32_t* lens, DevCounters* ctr) {
+                                                       uint32_t self_from, uint32_t* lens, DevCounters* ctr) {
     __shared__ uint32_t smax[kWavesPerBlock];
     uint32_t ml = 0;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        const uint32_t l = llen[rank[v]];
+        const uint32_t r = rank[v];
+        const uint32_t l = llen[r] + (r >= self_from ? 1u : 0u);
         lens[v] = l;
         ml = max(ml, l);
     }
@@ -735,8 +751,8 @@ __global__ void __launch_bounds__(kBlock) k_final_lens(uint32_t n, const uint32_
 
 __global__ void __launch_bounds__(kBlock) k_final_copy(uint32_t n, const uint32_t* rank, const uint64_t* loff,
                                                        const uint32_t* llen, const uint32_t* arena,
-                                                       const uint64_t* off, uint32_t* ent, uint2* lb,
-                                                       DevCounters* ctr) {
+                                                       uint32_t self_from, const uint64_t* off, uint32_t* ent,
+                                                       uint2* lb, DevCounters* ctr) {
     __shared__ uint32_t smax[kWavesPerBlock];
     const uint32_t lane = lane_id();
     uint32_t md = 0;
@@ -749,8 +765,14 @@ __global__ void __launch_bounds__(kBlock) k_final_copy(uint32_t n, const uint32_
             ent[dst + i] = e;
             md = max(md, e & 255u);
         }
-        if (lane == 0)
-            lb[v] = len ? make_uint2(arena[src] >> 8, arena[src + len - 1] >> 8) : make_uint2(0xFFFFFFFFu, 0u);
+        if (lane == 0) {
+            if (r >= self_from) {
+                ent[dst + len] = pll_pack(r, 0);
+                lb[v] = make_uint2(len ? arena[src] >> 8 : r, r);
+            } else {
+                lb[v] = len ? make_uint2(arena[src] >> 8, arena[src + len - 1] >> 8) : make_uint2(0xFFFFFFFFu, 0u);
+            }
+        }
     }
     md = wave_max32(md);
     if (lane == 0) smax[threadIdx.x >> 6] = md;
@@ -1194,9 +1216,9 @@ int init_state(DevAllocs& M, BuildArgs& A, uint32_t n, uint64_t nnz, uint32_t W,
 // 16-byte loads.
 int finalize_labels(DevAllocs& M, const BuildArgs& A, const uint32_t* rank, uint32_t* tmp32,
                     uint64_t* scan_scratch, hipStream_t s, uint64_t** d_off, uint32_t** d_ent, uint2** d_lb,
-                    uint64_t* total) {
+                    uint64_t* total, uint32_t self_from) {
     const uint32_t n = A.n;
-    k_final_lens<<<blocks_for_threads(n), kBlock, 0, s>>>(n, rank, A.llen, tmp32, A.ctr);
+    k_final_lens<<<blocks_for_threads(n), kBlock, 0, s>>>(n, rank, A.llen, self_from, tmp32, A.ctr);
     *d_off = M.get_out<uint64_t>((size_t)n + 1);
     if (M.err != hipSuccess) return status_of(M.err);
     TRY_HIP(scan_u32_to_u64(tmp32, n, *d_off, scan_scratch, s));
@@ -1205,8 +1227,8 @@ int finalize_labels(DevAllocs& M, const BuildArgs& A, const uint32_t* rank, uint
     *d_ent = M.get_out<uint32_t>(std::max<uint64_t>((*total + 3) & ~3ull, 4));
     *d_lb = M.get_out<uint2>(n);
     if (M.err != hipSuccess) return status_of(M.err);
-    k_final_copy<<<std::min<uint32_t>(blocks_for_waves(n), 1024), kBlock, 0, s>>>(n, rank, A.loff, A.llen, A.arena,
-                                                                                   *d_off, *d_ent, *d_lb, A.ctr);
+    k_final_copy<<<std::min<uint32_t>(blocks_for_waves(n), 1024), kBlock, 0, s>>>(
+        n, rank, A.loff, A.llen, A.arena, self_from, *d_off, *d_ent, *d_lb, A.ctr);
     TRY_HIP(hipGetLastError());
     return PLL_OK;
 }
@@ -1399,12 +1421,29 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
             }
         }
     }
+    // Batches from skip_from on hold isolated roots only (k_edge_end); they
+    // are not run: each counts as one batch of one round (the round in which
+    // nobody receives), and finalize writes its roots' self entries.  The
+    // bound is known from the first read-back on.  Not with bit-parallel
+    // roots, whose vertices (isolated ones among them) store no self entry.
+    uint32_t skip_from = n;
+    bool skip_known = (flags & PLL_FLAG_PERSISTENT) || A.bp_t;
+    if (!skip_known) {
+        k_edge_end<<<std::min<uint32_t>(blocks_for_threads(n), 1024), kBlock, 0, s>>>(n, A.rrow, ctr);
+        TRY_HIP(hipGetLastError());
+    }
     // round 1's receivers (the neighbours of the batch) are only counted
     // after its launch; its grid is sized by the previous batch's count,
     // which falls from batch to batch in rank order (a grid-stride loop
     // covers any excess)
     uint64_t r1_est = n;
     for (uint32_t ib = 0; !(flags & PLL_FLAG_PERSISTENT) && ib < n; ib += b) {
+        if (ib >= skip_from) {
+            const uint64_t left = (n - ib + b - 1) / b;
+            batches += left;
+            rounds += left;
+            break;
+        }
         const uint32_t bs = std::min(b, n - ib);
         ++bstamp;
         ++batches;
@@ -1452,6 +1491,11 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
             rc = read_counters(ctr, h, s);
             if (rc) return rc;
             P.resolve();
+            if (!skip_known) {  // this batch runs: skipping starts after it
+                skip_known = true;
+                const uint64_t from = std::max<uint64_t>(((uint64_t)h->edge_end + b - 1) / b * b, (uint64_t)ib + b);
+                if (from < n) skip_from = (uint32_t)from;
+            }
             const unsigned long long acc_now = sum_stat(h, PLL_ST_ACC);
             if (j == 1) r1_est = std::max<uint64_t>(bs, sum_recv(h, nr.rin));
             if (trace) {
@@ -1504,7 +1548,7 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
     uint32_t* d_ent = nullptr;
     uint2* d_lb = nullptr;
     uint64_t total = 0;
-    rc = finalize_labels(M, A, rank, tmp32, scan_scratch, s, &d_off, &d_ent, &d_lb, &total);
+    rc = finalize_labels(M, A, rank, tmp32, scan_scratch, s, &d_off, &d_ent, &d_lb, &total, skip_from);
     if (rc) return rc;
     uint32_t* d_order = M.get_out<uint32_t>(n);
     if (M.err != hipSuccess) return status_of(M.err);
@@ -1672,7 +1716,7 @@ int build_attempt_weighted(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
     uint32_t* d_ent = nullptr;
     uint2* d_lb = nullptr;
     uint64_t total = 0;
-    rc = finalize_labels(M, A, RC.rank, RC.tmp32, RC.scan_scratch, s, &d_off, &d_ent, &d_lb, &total);
+    rc = finalize_labels(M, A, RC.rank, RC.tmp32, RC.scan_scratch, s, &d_off, &d_ent, &d_lb, &total, n);
     if (rc) return rc;
     uint32_t* d_order = M.get_out<uint32_t>(n);
     if (M.err != hipSuccess) return status_of(M.err);
@@ -1895,7 +1939,7 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
     uint2* d_lb[2] = {nullptr, nullptr};
     uint64_t total[2] = {0, 0};
     for (int d = 0; d < 2; ++d) {
-        rc = finalize_labels(M, A[d], RC.rank, tmp32, scan_scratch, s, &d_off[d], &d_ent[d], &d_lb[d], &total[d]);
+        rc = finalize_labels(M, A[d], RC.rank, tmp32, scan_scratch, s, &d_off[d], &d_ent[d], &d_lb[d], &total[d], n);
         if (rc) return rc;
     }
     uint32_t* d_order = M.get_out<uint32_t>(n);

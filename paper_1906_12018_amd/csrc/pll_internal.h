@@ -63,7 +63,8 @@ struct DevCounters {
     uint32_t error;  // PLL_ERR_* bits
     uint32_t max_dist;
     uint32_t max_label;
-    uint32_t pad[29];
+    uint32_t edge_end;  // 1 + the highest rank with an edge (0: the graph has no edges)
+    uint32_t pad[28];
     Shard sh[PLL_SHARDS];
 };
 

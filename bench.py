@@ -956,8 +956,8 @@ def main():
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 0.95])
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design, "
+              "not an implementation", file=sys.stderr)
         sys.exit(2)
 
     if args.mode == "serve":

@@ -447,7 +447,7 @@ int oracle_bvc(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const u
         uint32_t bs = (n - ib < b) ? n - ib : b;
         batches++;
         uint32_t nact = 0, ntouched = 0;
-        /* batch init (Algorithm 4, lines 3-4), in rank space */
+        /* batch initialisation of Algorithm 4, in rank space */
         for (uint32_t k = 0; k < bs; ++k) {
             uint32_t u = ib + k;
             if ((rc = vlist_push(&L[u], u, 0))) break;
@@ -462,7 +462,7 @@ int oracle_bvc(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const u
             j++;
             rounds++;
             if (j >= INF8) { rc = ORACLE_EDIST; break; }
-            /* scatter (lines 6-10) */
+            /* scatter step */
             uint32_t nrecv = 0;
             for (uint32_t ai = 0; ai < nact && !rc; ++ai) {
                 uint32_t a = active[ai];
@@ -487,7 +487,7 @@ int oracle_bvc(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const u
             /* every active vertex has now sent its delta L: the active set is
              * emptied before the gather phase builds the next one */
             for (uint32_t ai = 0; ai < nact; ++ai) delta[active[ai]].len = 0;
-            /* gather (lines 11-19) */
+            /* gather step: distance check, append, next active list */
             uint32_t nnext = 0;
             for (uint32_t ri = 0; ri < nrecv && !rc; ++ri) {
                 uint32_t v = recv[ri];
@@ -526,7 +526,7 @@ int oracle_bvc(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const u
             memcpy(active, next_active, sizeof(uint32_t) * nnext);
             nact = nnext;
         }
-        /* clear C (line 22) over the touched vertices and H for this batch */
+        /* clear C over the touched vertices and H for this batch (the batch's last step) */
         for (uint32_t t = 0; t < ntouched; ++t) {
             uint32_t v = touched[t];
             memset(&C[(size_t)v * W], 0, sizeof(uint64_t) * W);

@@ -8,14 +8,14 @@
 //   rounds j = 1, 2, ... until no vertex accepts anything:
 //     k_push       scatter: OR delta L(a) of every active a into msgs(v) of its
 //                  neighbours v ranked below the batch hubs, minus C(v)
-//                  (Algorithm 4, lines 6-10); collect the receivers
+//                  (the scatter step of Algorithm 4); collect the receivers
 //     k_check      gather: cand(v) = msgs(v); C(v) |= cand(v); a candidate
 //                  u_k survives iff no (h, d) in L(v) with d < j has
-//                  T[h][k] + d <= j (lines 13-17); append survivors with
-//                  distance j, write T for batch vertices (line 19), build the
-//                  next active list (line 18)
-//   k_batch_end    clear C(v) over the touched vertices (line 22, Section 5.2
-//                  bitmap + queue), optional recheck (Section 5.1), sort each
+//                  T[h][k] + d <= j (its distance check); append survivors
+//                  with distance j, write T for batch vertices, build the
+//                  next active list
+//   k_batch_end    clear C(v) over the touched vertices (the batch's last step,
+//                  Section 5.2 bitmap + queue), optional recheck (Section 5.1), sort each
 //                  touched vertex's batch segment by hub rank
 //   k_clear_table  reset T and its row masks for the next batch
 //

@@ -93,14 +93,15 @@ __device__ inline uint64_t wave_or64_u(uint64_t x) {
 // holds candidate word cw = bits k of batch vertices u_{64w+k} that arrived
 // at distance j.  Returns, in lane w, the candidates of word w for which some
 // entry (h, d) of the list with d < j has T[h][k] + d <= j, i.e. the distance
-// j is already covered through a hub ranked above u_k (Algorithm 4, line 14).
+// j is already covered through a hub ranked above u_k (the pruning test of
+// Algorithm 4).
 // With `relaxed`, entries whose hub is in the current batch are skipped.
-// The table loads of all candidate words of a chunk are independent; lanes
-// are OR-reduced after the first chunk, every 4 chunks and at the end,
-// which is also where the scan stops once every candidate is pruned (the
-// early reduction took the R-MAT-20 check from 407 to 315 ms: the top-ranked
-// hubs of the first chunk prune most candidates of the late rounds).  The
-// next chunk's entries are loaded while this chunk's segments are.  With QGATE only the 16-byte
+// Each chunk of 64 entries makes one pass per candidate word that still
+// holds live candidates, and the wave OR-reduces that word's prunes in the
+// pass, so the scan stops after the first chunk that leaves no candidate
+// live (the top-ranked hubs of the first chunk prune most candidates of the
+// late rounds).  The next chunk's entries are loaded while this chunk's
+// segments are.  With QGATE only the 16-byte
 // quarters of a table segment that both hold entries (row mask) and have
 // live candidates are loaded; without it a segment is loaded whole when any
 // of its quarters qualifies (fewer, wider loads: measured faster on the large
@@ -111,13 +112,9 @@ __device__ inline uint64_t prune_scan(const BuildArgs& A, uint64_t off, uint32_t
                                       bool relaxed, uint32_t ib, PhaseStats& st) {
     const uint32_t lane = lane_id();
     uint64_t pw = 0;
-    uint64_t accm[WM];
-#pragma unroll
-    for (int w = 0; w < WM; ++w) accm[w] = 0;
-    uint32_t chunk = 0;
     // the next chunk's entry is loaded while this chunk's table segments are
     uint32_t next = lane < len ? A.arena[off + lane] : 0u;
-    for (uint32_t base = 0; base < len; base += 64, ++chunk) {
+    for (uint32_t base = 0; base < len; base += 64) {
         const uint32_t idx = base + lane;
         bool ok = idx < len;
         st.read += ok;
@@ -131,35 +128,33 @@ __device__ inline uint64_t prune_scan(const BuildArgs& A, uint64_t off, uint32_t
         // (which only reports the overflow) an empty cell must not prune
         const uint32_t tt = ok ? min(j - d, PLL_INF8 - 1u) * 0x01010101u : 0u;
         const uint8_t* row = A.Tchk + (size_t)h * A.bstride;
+        // One pass per word that still holds live candidates (a scalar loop
+        // over their mask): every lane compares its entry's table segment,
+        // and the wave OR-reduces the word's prunes at once.  So the
+        // candidates pruned by this chunk (the top-ranked hubs of the first
+        // chunk prune most) load no later segments, one copy of the compare
+        // serves every word, and no per-word accumulators are kept.
         const uint64_t live_lane = cw & ~pw;
-#pragma unroll
-        for (int w = 0; w < WM; ++w) {
+        uint64_t lw = ballot64(live_lane != 0) & (WM >= 64 ? ~0ull : ((1ull << WM) - 1ull));
+        while (lw) {
+            const uint32_t w = (uint32_t)__builtin_ctzll(lw);
+            lw &= lw - 1;
             const uint64_t live = readlane64(live_lane, w);
+            uint64_t m = 0;
             if (QGATE) {
                 const uint32_t need = (uint32_t)(rm >> (4 * w)) & quarters(live);
                 if (need & 15u) {
-                    accm[w] |= le_mask64_q(row + 64u * w, tt, need) & live;
+                    m = le_mask64_q(row + 64u * w, tt, need) & live;
                     st.table += __builtin_popcount(need & 15u);
                 }
-            } else if (live != 0 && ((rm >> (4 * w)) & 15u)) {
-                accm[w] |= le_mask64(row + 64u * w, tt) & live;
+            } else if ((rm >> (4 * w)) & 15u) {
+                m = le_mask64(row + 64u * w, tt) & live;
                 st.table += 4;
             }
+            const uint64_t red = wave_or64_u(m);
+            if (lane == w) pw |= red;
         }
-        // lanes are OR-reduced after the first chunk (the top-ranked hubs
-        // prune most candidates), then every 4 chunks and at the end; a word
-        // whose candidates are all pruned loads no more table segments
-        if (chunk == 0 || (chunk & 3u) == 3u || base + 64 >= len) {
-#pragma unroll
-            for (int w = 0; w < WM; ++w) {
-                if (readlane64(live_lane, w)) {
-                    const uint64_t red = wave_or64_u(accm[w]);
-                    if (lane == (uint32_t)w) pw |= red;
-                    accm[w] = 0;
-                }
-            }
-            if (!ballot64((cw & ~pw) != 0)) break;
-        }
+        if (!ballot64((cw & ~pw) != 0)) break;
     }
     return pw;
 }
@@ -181,46 +176,37 @@ __device__ inline uint64_t prune_scan_nbrs(const BuildArgs& A, uint32_t v, uint3
                                            PhaseStats& st) {
     const uint32_t lane = lane_id();
     uint64_t pw = 0;
-    uint64_t accm[WM];
-#pragma unroll
-    for (int w = 0; w < WM; ++w) accm[w] = 0;
     const uint64_t beg = A.rrow[v], end = A.rrow[v + 1];
     const uint32_t tt = 0x01010101u;  // T[h][k] <= 2 - 1
-    uint32_t chunk = 0;
-    for (uint64_t base = beg; base < end; base += 64, ++chunk) {
+    for (uint64_t base = beg; base < end; base += 64) {
         const uint64_t idx = base + lane;
         const uint32_t h = idx < end ? A.rcol[idx] : ~0u;
         const bool ok = h < lim;
         st.read += idx < end;
         const uint64_t rm = ok ? A.rmchk[h] : 0ull;
         const uint8_t* row = A.Tchk + (size_t)(ok ? h : 0u) * A.bstride;
+        // one pass per word with live candidates, as in prune_scan
         const uint64_t live_lane = cw & ~pw;
-#pragma unroll
-        for (int w = 0; w < WM; ++w) {
+        uint64_t lw = ballot64(live_lane != 0) & (WM >= 64 ? ~0ull : ((1ull << WM) - 1ull));
+        while (lw) {
+            const uint32_t w = (uint32_t)__builtin_ctzll(lw);
+            lw &= lw - 1;
             const uint64_t live = readlane64(live_lane, w);
+            uint64_t m = 0;
             if (QGATE) {
                 const uint32_t need = (uint32_t)(rm >> (4 * w)) & quarters(live);
                 if (need & 15u) {
-                    accm[w] |= le_mask64_q(row + 64u * w, tt, need) & live;
+                    m = le_mask64_q(row + 64u * w, tt, need) & live;
                     st.table += __builtin_popcount(need & 15u);
                 }
-            } else if (live != 0 && ((rm >> (4 * w)) & 15u)) {
-                accm[w] |= le_mask64(row + 64u * w, tt) & live;
+            } else if ((rm >> (4 * w)) & 15u) {
+                m = le_mask64(row + 64u * w, tt) & live;
                 st.table += 4;
             }
+            const uint64_t red = wave_or64_u(m);
+            if (lane == w) pw |= red;
         }
-        const bool last = base + 64 >= end;
-        if (chunk == 0 || (chunk & 3u) == 3u || last) {
-#pragma unroll
-            for (int w = 0; w < WM; ++w) {
-                if (readlane64(live_lane, w)) {
-                    const uint64_t red = wave_or64_u(accm[w]);
-                    if (lane == (uint32_t)w) pw |= red;
-                    accm[w] = 0;
-                }
-            }
-            if (last || !ballot64((cw & ~pw) != 0)) break;
-        }
+        if (!ballot64((cw & ~pw) != 0)) break;
     }
     return pw;
 }
@@ -306,7 +292,8 @@ __device__ inline uint64_t rank_mask(uint32_t rel, uint32_t w) {
     return (1ull << (rel - lo)) - 1ull;
 }
 
-// Algorithm 4, line 4: delta L(u) = {(u,0)}, L(u) gets (u,0), L(u) -> H(u).
+// Batch initialisation of Algorithm 4: delta L(u) = {(u,0)}, L(u) gets
+// (u,0), L(u) -> H(u).
 // The initial active list holds batch vertex u_k in slot k.
 __device__ inline void phase_batch_init(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t bs, uint32_t bstamp) {
     const uint32_t lane = lane_id();
@@ -519,7 +506,7 @@ __device__ inline void phase_pull_items(const BuildArgs& A, const Exec& X, uint2
     }
 }
 
-// Scatter phase (Algorithm 4, lines 6-10) over active list p (nact slots).
+// Scatter phase of Algorithm 4 over active list p (nact slots).
 // Batch vertex u_k may be sent to v only when u_k outranks v (rank ib + k
 // < v) and C(v) does not hold it yet.  Slots whose delta is empty are
 // skipped; rows longer than kHeavy were queued as items and are spread over
@@ -620,7 +607,7 @@ __device__ inline uint64_t bp_prune_words(const BuildArgs& A, uint32_t v, uint32
     return out;
 }
 
-// Gather phase (Algorithm 4, lines 11-19) for round j: one wave per
+// Gather phase of Algorithm 4 for round j: one wave per
 // receiver.  Receiver i (in shard order) becomes slot i of the next active
 // list (with an empty delta when nothing was accepted).
 //
@@ -737,7 +724,7 @@ __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t i
     }
 }
 
-// Batch end, one wave per touched vertex v: clear C(v) (line 22); sort the
+// Batch end, one wave per touched vertex v: clear C(v); sort the
 // entries this batch appended to L(v) by hub rank; with `recheck`, first
 // drop every such entry (u, d) that L(u) and L(v) already cover through
 // another hub at distance <= d (Section 5.1's recheck with the batch's

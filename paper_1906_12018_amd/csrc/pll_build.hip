@@ -482,7 +482,15 @@ __global__ void k_check_weights(uint64_t nnz, const uint8_t* w, DevCounters* ctr
         if (w[e] == 0) atomicOr(&ctr->error, PLL_ERR_BOUNDS);
 }
 
-__global__ void __launch_bounds__(kBlock) k_clear_table(BuildArgs A, uint32_t ib, uint32_t bs) {
+// With `prep` set it also does k_batch_prep's reset for the next batch (the
+// batch end, which reads the touched counts, has finished by then).
+__global__ void __launch_bounds__(kBlock) k_clear_table(BuildArgs A, uint32_t ib, uint32_t bs, DevCounters* prep) {
+    if (prep && blockIdx.x == 0 && threadIdx.x < PLL_SHARDS) {
+        Shard& sh = prep->sh[threadIdx.x];
+        sh.recv[0] = sh.recv[1] = sh.recv[2] = 0;
+        sh.hq[0] = sh.hq[1] = 0;
+        sh.touched = 0;
+    }
     pll::phase_clear_table(A, grid_exec(A), ib, bs);
 }
 
@@ -1448,10 +1456,12 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
         ++bstamp;
         ++batches;
         hipEvent_t e0 = P.mark();
-        k_batch_prep<<<1, 64, 0, s>>>(ctr);
+        // later batches have the counters reset by the previous batch's
+        // table clear
+        if (ib == 0) k_batch_prep<<<1, 64, 0, s>>>(ctr);
         if (A.bp_t) k_bp_batch_stage<<<blocks_for_threads((uint64_t)A.bp_t * bs), kBlock, 0, s>>>(A, ib, bs);
         k_batch_init<<<blocks_for_waves(bs), kBlock, 0, s>>>(A, ib, bs, bstamp);
-        P.span(PLL_PHASE_INIT, e0, P.mark(), A.bp_t ? 3 : 2);
+        P.span(PLL_PHASE_INIT, e0, P.mark(), (A.bp_t ? 2 : 1) + (ib == 0 ? 1 : 0));
         // round 1's push from the batch vertices (active list 0) into
         // receiver queue 0 and message buffer 1; afterwards every round j is
         // one fused launch (check of round j, push of round j+1 into buffer
@@ -1528,7 +1538,7 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
         }
         hipEvent_t e1 = P.mark();
         dispatch_batch_end(blocks_for_waves(sum_touched(h)), s, A, ib, bs, recheck);
-        k_clear_table<<<blocks_for_waves(bs), kBlock, 0, s>>>(A, ib, bs);
+        k_clear_table<<<blocks_for_waves(bs), kBlock, 0, s>>>(A, ib, bs, ctr);
         P.span(PLL_PHASE_END, e1, P.mark(), 2);
         TRY_HIP(hipGetLastError());
         // compact the lists into a larger arena once a bump region is half used
@@ -1698,7 +1708,7 @@ int build_attempt_weighted(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
         }
         hipEvent_t e1 = P.mark();
         dispatch_batch_end_w(blocks_for_waves(sum_touched(h)), s, A, ib, bs);
-        k_clear_table<<<blocks_for_waves(bs), kBlock, 0, s>>>(A, ib, bs);
+        k_clear_table<<<blocks_for_waves(bs), kBlock, 0, s>>>(A, ib, bs, nullptr);
         P.span(PLL_PHASE_END, e1, P.mark(), 2);
         TRY_HIP(hipGetLastError());
         if (!arena_fixed && ib + b < n && max_top(h) * 2 > A.region_cap) {
@@ -1916,7 +1926,7 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
         // are cleared only after both
         hipEvent_t e1 = P.mark();
         for (int d = 0; d < 2; ++d) dispatch_batch_end(blocks_for_waves(sum_touched(h[d])), s, A[d], ib, bs, recheck);
-        for (int d = 0; d < 2; ++d) k_clear_table<<<blocks_for_waves(bs), kBlock, 0, s>>>(A[d], ib, bs);
+        for (int d = 0; d < 2; ++d) k_clear_table<<<blocks_for_waves(bs), kBlock, 0, s>>>(A[d], ib, bs, nullptr);
         P.span(PLL_PHASE_END, e1, P.mark(), 4);
         TRY_HIP(hipGetLastError());
         for (int d = 0; d < 2; ++d) {

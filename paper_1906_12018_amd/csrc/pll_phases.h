@@ -677,8 +677,13 @@ __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t i
         st.cand += __builtin_popcountll(mine);
         st.cost_pos += (unsigned long long)len * (uint32_t)__builtin_popcountll(acc);
         st.cost_neg += (unsigned long long)len * (uint32_t)__builtin_popcountll(mine & ~acc);
-        if (lane == 0) A.act_v[q][i] = v;
-        if (lane < W) A.act_delta[q][(size_t)i * W + lane] = acc;
+        // the active list: the fused rounds read a slot only for a vertex
+        // that accepted (its heavy-row items and pulled rounds); the
+        // unfused ones push from every slot
+        if (!FUSE || total != 0) {
+            if (lane == 0) A.act_v[q][i] = v;
+            if (lane < W) A.act_delta[q][(size_t)i * W + lane] = acc;
+        }
         if (total == 0) continue;
         if (j >= PLL_INF8) {
             if (lane == 0) atomicOr(&A.ctr->error, PLL_ERR_DIST);

@@ -294,3 +294,40 @@ def test_pulled_rounds_match_oracle(b):
     assert info["phase_launches"]["push"] > info["batches"]
     u, v = synth.query_pairs(g.n, 100_000, seed=4)
     assert np.array_equal(gpu_query(idx, u, v), oracle.query(want, u, v))
+
+
+@pytest.mark.parametrize("b", [64, 300, 1024])
+@pytest.mark.parametrize("isolated", [0, 1, 700, 5000])
+def test_trailing_isolated_vertices(b, isolated):
+    """Isolated vertices ranked last: the batches that hold only them are not
+    run, and finalize writes their self entries.  Labels, counters (one batch
+    of one round per such batch, as the oracle counts them) and queries equal
+    the oracle's, also when the boundary falls inside a batch."""
+    g0 = synth.ba_graph(1200, 3, 31)
+    g = synth.disjoint_union(g0, synth.csr_from_edges(isolated, np.zeros(0), np.zeros(0))) if isolated else g0
+    order = synth.degree_order(g)
+    want = oracle.pll_labels(g, order)
+    idx = build(g, order, batch_size=b)
+    assert_labels_equal(idx, want, order)
+    check_counters(idx, g, order, b, want)
+    u, v = synth.query_pairs(g.n, 20_000, seed=3)
+    assert np.array_equal(gpu_query(idx, u, v), oracle.query(want, u, v))
+    idx.free()
+
+
+@pytest.mark.parametrize("b", [1, 64, 1024])
+def test_edgeless_graph_of_several_batches(b):
+    """No edges at all: only the first batch runs; every label is its self
+    entry and every pair but (v, v) is unreachable."""
+    n = 3000
+    g = synth.csr_from_edges(n, np.zeros(0), np.zeros(0))
+    order = synth.degree_order(g)
+    want = oracle.pll_labels(g, order)
+    assert want.total == n
+    idx = build(g, order, batch_size=b)
+    assert_labels_equal(idx, want, order)
+    check_counters(idx, g, order, b, want)
+    u, v = synth.query_pairs(n, 5000, seed=4)
+    got = gpu_query(idx, u, v)
+    assert np.array_equal(got, np.where(u == v, 0, pll.DIST_INF).astype(got.dtype))
+    idx.free()

@@ -72,6 +72,10 @@ extern "C" {
 #define PLL_FLAG_PERSISTENT 0x10u /* run the batches in one persistent launch with grid-wide barriers between
                                     phases, instead of one launch per phase and a host read-back per round */
 #define PLL_FLAG_PROFILE 0x8u  /* time each build phase with HIP events on `stream` (pll_index_info.phase_ms) */
+#define PLL_FLAG_PACK4 0x20u   /* testing: every fused round of an undirected unweighted build without bit-parallel
+                                  roots checks four receivers per wave; otherwise only rounds expected to have at
+                                  least 16,384 receivers do.  The labels are the same either way; directed,
+                                  weighted and bit-parallel builds ignore it */
 
 /* Build phases timed under PLL_FLAG_PROFILE (indexes into pll_index_info.phase_ms / phase_launches). */
 #define PLL_PHASE_PREP 0     /* input checks and relabelling to rank space */

@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(_PKG, "libpll.so")
 
 PLL_OK, PLL_EINVAL, PLL_ENOMEM, PLL_ENOSPC, PLL_EDIST, PLL_EDEVICE, PLL_ESCRATCH = 0, 1, 2, 3, 4, 5, 6
 DIST_INF = 0xFFFFFFFF
-FLAG_VALIDATE, FLAG_RECHECK, FLAG_RELAXED, FLAG_PROFILE, FLAG_PERSISTENT = 0x1, 0x2, 0x4, 0x8, 0x10
+FLAG_VALIDATE, FLAG_RECHECK, FLAG_RELAXED, FLAG_PROFILE, FLAG_PERSISTENT, FLAG_PACK4 = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 PHASES = ("prep", "init", "push", "check", "end", "final", "loop")
 DEFAULT_BATCH = 1024
 LABELS_IN, LABELS_OUT = 0, 1

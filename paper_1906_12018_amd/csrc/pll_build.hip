@@ -40,6 +40,7 @@ constexpr uint32_t kMaxBlocks = 4096;
 constexpr uint32_t kHotRows = 256;         // top-ranked table rows whose row masks stay all ones
 constexpr uint64_t kPullFrac = 2;          // a round with at least n / 2 receivers pulls the next one
 constexpr uint32_t kPullMinN = 16384;      // smaller graphs always push (the pull's set-up outweighs it)
+constexpr uint64_t kPackMin = 16384;       // receivers from which a fused round checks four per wave
 
 inline uint32_t blocks_for_waves(uint64_t waves) {
     uint64_t b = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -345,11 +346,14 @@ __global__ void __launch_bounds__(kBlock) k_check(BuildArgs A, uint32_t ib, uint
 }
 
 // Round j's check fused with round j+1's push (NextRound in pll_phases.h).
-template <int WM, bool BP>
+template <int WM, bool BP, bool PACK = false>
 __device__ inline void check_push_body(const BuildArgs& A, const pll::Exec& X, uint32_t ib, uint32_t bs, uint32_t j,
                                        const pll::NextRound& nr, uint32_t relaxed) {
     PhaseStats st;
-    pll::phase_check<WM, BP, true>(A, X, ib, bs, j, nr.rin, relaxed != 0, st, &nr);
+    if (PACK && !BP)
+        pll::phase_check4<WM>(A, X, ib, bs, j, relaxed != 0, st, nr);
+    else
+        pll::phase_check<WM, BP, true>(A, X, ib, bs, j, nr.rin, relaxed != 0, st, &nr);
     const unsigned long long v[9] = {st.cand,     st.acc, st.read,  st.table,          st.cost_pos,
                                      st.cost_neg, st.bp,  st.edges + st.pulled, st.edges};
     const int which[9] = {PLL_ST_CAND,     PLL_ST_ACC, PLL_ST_READ,  PLL_ST_TABLE,      PLL_ST_COST_POS,
@@ -358,10 +362,10 @@ __device__ inline void check_push_body(const BuildArgs& A, const pll::Exec& X, u
 }
 
 // at most 128 VGPRs, i.e. 4 waves per SIMD, like the unfused check
-template <int WM>
+template <int WM, bool PACK>
 __global__ void __launch_bounds__(kBlock, 4) k_check_push(BuildArgs A, uint32_t ib, uint32_t bs, uint32_t j,
                                                           pll::NextRound nr, uint32_t relaxed) {
-    check_push_body<WM, false>(A, grid_exec(A), ib, bs, j, nr, relaxed);
+    check_push_body<WM, false, PACK>(A, grid_exec(A), ib, bs, j, nr, relaxed);
 }
 
 // The blocks [b0, b0 + nb) of the grid run a phase on their own: queue
@@ -979,11 +983,13 @@ void dispatch_check(uint32_t blocks, hipStream_t s, const BuildArgs& A, uint32_t
 
 template <int WM>
 void launch_check_push(uint32_t blocks, hipStream_t s, const BuildArgs& A, uint32_t ib, uint32_t bs, uint32_t j,
-                       const pll::NextRound& nr, uint32_t relaxed) {
+                       const pll::NextRound& nr, uint32_t relaxed, bool pack) {
     if (A.bp_t)
         k_check_push_bp<WM><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, nr, relaxed);
+    else if (pack)
+        k_check_push<WM, true><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, nr, relaxed);
     else
-        k_check_push<WM><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, nr, relaxed);
+        k_check_push<WM, false><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, nr, relaxed);
 }
 
 void dispatch_check_push2(uint32_t nb0, uint32_t nb1, hipStream_t s, const BuildArgs& A0, const pll::NextRound& nr0,
@@ -999,13 +1005,13 @@ void dispatch_check_push2(uint32_t nb0, uint32_t nb1, hipStream_t s, const Build
 }
 
 void dispatch_check_push(uint32_t blocks, hipStream_t s, const BuildArgs& A, uint32_t ib, uint32_t bs, uint32_t j,
-                         const pll::NextRound& nr, uint32_t relaxed) {
+                         const pll::NextRound& nr, uint32_t relaxed, bool pack) {
     switch (words_class(A.W)) {
-        case 1: launch_check_push<1>(blocks, s, A, ib, bs, j, nr, relaxed); break;
-        case 2: launch_check_push<2>(blocks, s, A, ib, bs, j, nr, relaxed); break;
-        case 4: launch_check_push<4>(blocks, s, A, ib, bs, j, nr, relaxed); break;
-        case 8: launch_check_push<8>(blocks, s, A, ib, bs, j, nr, relaxed); break;
-        default: launch_check_push<16>(blocks, s, A, ib, bs, j, nr, relaxed); break;
+        case 1: launch_check_push<1>(blocks, s, A, ib, bs, j, nr, relaxed, pack); break;
+        case 2: launch_check_push<2>(blocks, s, A, ib, bs, j, nr, relaxed, pack); break;
+        case 4: launch_check_push<4>(blocks, s, A, ib, bs, j, nr, relaxed, pack); break;
+        case 8: launch_check_push<8>(blocks, s, A, ib, bs, j, nr, relaxed, pack); break;
+        default: launch_check_push<16>(blocks, s, A, ib, bs, j, nr, relaxed, pack); break;
     }
 }
 
@@ -1487,8 +1493,10 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
             Aj.recv = rbuf[j & 1u];
             if (P.on) k_delay<<<1, 1, 0, s>>>(delay_ticks);
             hipEvent_t r1 = P.mark();
-            dispatch_check_push(blocks_for_waves(std::min<uint64_t>(n, next_est + 2048)), s, Aj, ib, bs, j, nr,
-                                relaxed);
+            // rounds with many receivers check four per wave (phase_check4)
+            const bool pack = (flags & PLL_FLAG_PACK4) || next_est >= kPackMin;
+            const uint64_t waves = pack ? next_est / 4 + 512 : next_est + 2048;
+            dispatch_check_push(blocks_for_waves(std::min<uint64_t>(n, waves)), s, Aj, ib, bs, j, nr, relaxed, pack);
             P.span(PLL_PHASE_CHECK, r1, P.mark(), 1);
             TRY_HIP(hipGetLastError());
             if (pull) {
@@ -2027,7 +2035,8 @@ int build_index(uint32_t n, uint64_t nnz, const uint64_t* d_row_ptr, const uint3
     const uint32_t b = o.batch_size ? o.batch_size : PLL_BMAX;
     if (b > PLL_BMAX || n >= PLL_MAX_N) return PLL_EINVAL;
     if ((o.flags & PLL_FLAG_RELAXED) && !(o.flags & PLL_FLAG_RECHECK)) return PLL_EINVAL;
-    if (o.flags & ~(PLL_FLAG_VALIDATE | PLL_FLAG_RECHECK | PLL_FLAG_RELAXED | PLL_FLAG_PROFILE | PLL_FLAG_PERSISTENT))
+    if (o.flags & ~(PLL_FLAG_VALIDATE | PLL_FLAG_RECHECK | PLL_FLAG_RELAXED | PLL_FLAG_PROFILE | PLL_FLAG_PERSISTENT |
+                    PLL_FLAG_PACK4))
         return PLL_EINVAL;
     if ((directed || weighted) && (o.flags & (PLL_FLAG_RELAXED | PLL_FLAG_PERSISTENT))) return PLL_EINVAL;
     if (o.bp_roots > 64 || (o.bp_roots && (directed || weighted || (o.flags & PLL_FLAG_PERSISTENT))))

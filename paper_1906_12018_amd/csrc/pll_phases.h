@@ -333,6 +333,30 @@ __device__ inline void phase_batch_init(const BuildArgs& A, const Exec& X, uint3
     }
 }
 
+// The lanes whose vertex r got a delivery (`any`) take r's receiver slot
+// of the next round (one per vertex and round, via its round stamp) into
+// queue rq stored in recv; the lane that wins the slot also records r's
+// first touch in this batch.  The whole wave calls it.
+__device__ inline void enqueue_receivers(const BuildArgs& A, const Exec& X, uint32_t* recv, uint32_t rq,
+                                         uint32_t rstamp, uint32_t bstamp, uint32_t r, bool any) {
+    bool enq = false;
+    if (any && A.recv_stamp[r] != rstamp) enq = atomicExch(&A.recv_stamp[r], rstamp) != rstamp;
+    bool first = false;
+    if (enq && A.touch_stamp[r] != bstamp) {
+        A.touch_stamp[r] = bstamp;
+        first = true;
+    }
+    if (ballot64(enq)) {
+        const uint32_t rp = shard_append(&X.qs[X.my].recv[rq], enq, (uint64_t)X.my * X.seg);
+        if (enq) recv[rp] = r;
+        const uint32_t tp = shard_append(&X.qs[X.my].touched, first, (uint64_t)X.my * X.seg);
+        if (first) {
+            A.touched[tp] = r;
+            A.tstart[tp] = A.llen[r];
+        }
+    }
+}
+
 // Push delta L(a) (lane w < W holds word w in dl; nz marks the nonzero
 // words) along the CSR entries [beg, end) of the active vertex a, into the
 // message buffer msgs and receiver queue rq (counters) stored in recv.
@@ -360,24 +384,7 @@ __device__ inline void push_edges(const BuildArgs& A, const Exec& X, uint64_t* m
                 }
             }
         }
-        // one receiver slot per vertex and round; the lane that wins the
-        // slot also records the vertex's first touch in this batch
-        bool enq = false;
-        if (any && A.recv_stamp[r] != rstamp) enq = atomicExch(&A.recv_stamp[r], rstamp) != rstamp;
-        bool first = false;
-        if (enq && A.touch_stamp[r] != bstamp) {
-            A.touch_stamp[r] = bstamp;
-            first = true;
-        }
-        if (ballot64(enq)) {
-            const uint32_t rp = shard_append(&X.qs[X.my].recv[rq], enq, (uint64_t)X.my * X.seg);
-            if (enq) recv[rp] = r;
-            const uint32_t tp = shard_append(&X.qs[X.my].touched, first, (uint64_t)X.my * X.seg);
-            if (first) {
-                A.touched[tp] = r;
-                A.tstart[tp] = A.llen[r];
-            }
-        }
+        enqueue_receivers(A, X, recv, rq, rstamp, bstamp, r, any);
     }
 }
 
@@ -726,6 +733,290 @@ __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t i
         } else {
             enqueue_heavy(A, X, q, i, end - beg);
         }
+    }
+}
+
+// OR over each 16-lane row by DPP row rotations: every lane of a row gets
+// its row's OR (the whole wave must be active).
+__device__ inline uint32_t row_or32_dpp(uint32_t x) {
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x121, 0xf, 0xf, false);  // row_ror:1
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x122, 0xf, 0xf, false);  // row_ror:2
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x124, 0xf, 0xf, false);  // row_ror:4
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xf, 0xf, false);  // row_ror:8
+    return x;
+}
+
+__device__ inline uint64_t row_or64_dpp(uint64_t x) {
+    return ((uint64_t)row_or32_dpp((uint32_t)(x >> 32)) << 32) | row_or32_dpp((uint32_t)x);
+}
+
+// Lane `src`'s x in every lane (the LDS crossbar; src may differ per lane).
+__device__ inline uint64_t shfl64(uint64_t x, uint32_t src) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src * 4u), (int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src * 4u), (int)(uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// The pruning scans of four receivers at once: group g = lane / 16 scans
+// the list of its own receiver 16 entries at a time, and lane 16g + w holds
+// word w (< W <= 16) of that receiver's candidates in cw.  The test is the
+// one of prune_scan and prune_scan_nbrs, per group: the source is either
+// L(v) (entries arena[off .. off+len)) or, with `nbr`, v's neighbour row
+// (rcol[off .. off+len), hubs ranked below lim at distance 1).  Each chunk
+// makes one pass per live candidate word of each group (the groups'
+// passes run side by side), and each group OR-reduces its word's prunes
+// within its 16-lane row.  A group stops after the chunk that leaves none
+// of its candidates live, or at its list's end.  Returns, in lane 16g + w,
+// the pruned candidates of word w of receiver g.
+template <int WM>
+__device__ inline uint64_t prune_scan4(const BuildArgs& A, uint64_t off, uint32_t len, bool nbr, uint32_t lim,
+                                       uint32_t j, uint64_t cw, bool relaxed, uint32_t ib, PhaseStats& st) {
+    const uint32_t lane = lane_id();
+    const uint32_t sub = lane & 15u;
+    const uint32_t gsh = lane & 48u;  // 16 * group
+    const uint32_t* src = (nbr ? A.rcol : A.arena) + off;
+    uint64_t pw = 0;
+    uint32_t next = sub < len ? src[sub] : 0u;
+    for (uint32_t base = 0;; base += 16) {
+        const uint64_t live_lane = cw & ~pw;
+        const uint64_t lb = ballot64(live_lane != 0);
+        // this group still scans: candidates live and entries left
+        const bool gon = ((lb >> gsh) & 0xFFFFull) != 0 && base < len;
+        const uint64_t todo0 = ballot64(gon && live_lane != 0);
+        if (!todo0) break;
+        const uint32_t idx = base + sub;
+        bool ok = gon && idx < len;
+        st.read += ok;
+        const uint32_t ent = next;
+        next = gon && idx + 16 < len ? src[idx + 16] : 0u;
+        uint32_t h, tt;
+        if (nbr) {
+            h = ent;
+            ok = ok && h < lim;
+            tt = 0x01010101u;  // T[h][k] <= 2 - 1
+        } else {
+            h = ent >> 8;
+            const uint32_t d = ent & 255u;
+            ok = ok && d < j;
+            if (relaxed) ok = ok && h < ib;
+            // at most 254, the largest finite table byte (see prune_scan)
+            tt = ok ? min(j - d, PLL_INF8 - 1u) * 0x01010101u : 0u;
+        }
+        const uint64_t rm = ok ? A.rmchk[h] : 0ull;
+        const uint8_t* row = A.Tchk + (size_t)(ok ? h : 0u) * A.bstride;
+        uint64_t todo = todo0;
+        while (todo) {
+            const uint32_t gm = (uint32_t)(todo >> gsh) & 0xFFFFu;
+            const bool act = gm != 0;
+            const uint32_t w = act ? (uint32_t)__builtin_ctz(gm) : 0u;
+            const uint64_t live = shfl64(live_lane, gsh + w);
+            uint64_t m = 0;
+            if (act && ((rm >> (4 * w)) & 15u)) {
+                m = le_mask64(row + 64u * w, tt) & live;
+                st.table += 4;
+            }
+            const uint64_t red = row_or64_dpp(m);
+            const bool here = act && sub == w;
+            if (here) pw |= red;
+            todo &= ~ballot64(here);
+        }
+    }
+    return pw;
+}
+
+// Inclusive prefix sum within each 16-lane row (DPP row shifts; lanes
+// shifted in from outside the row add 0; the whole wave must be active).
+__device__ inline uint32_t row_incl_scan32(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);  // row_shr:8
+    return x;
+}
+
+// push_edges for up to four receivers of one wave at once: group g's delta
+// words are in lanes 16g + w of acc4, and its row is rcol[beg .. beg + deg)
+// (beg and deg held by the group's lanes; deg = 0 for a group that pushes
+// nothing here).  The rows are walked as one concatenated range, 64 edges
+// per step, each lane taking the delta of its edge's receiver; deliveries
+// and receiver slots are those of push_edges.
+__device__ inline void push_edges4(const BuildArgs& A, const Exec& X, const NextRound& nr, uint32_t ib, uint64_t acc4,
+                                   uint64_t beg, uint32_t deg) {
+    const uint32_t lane = lane_id();
+    // starts of groups 1..3 in the concatenation, and its length
+    const uint32_t s1 = readlane32(deg, 0);
+    const uint32_t s2 = s1 + readlane32(deg, 16);
+    const uint32_t s3 = s2 + readlane32(deg, 32);
+    const uint32_t D = s3 + readlane32(deg, 48);
+    const uint64_t b0 = readlane64(beg, 0), b1 = readlane64(beg, 16), b2 = readlane64(beg, 32),
+                   b3 = readlane64(beg, 48);
+    // candidate words with a delta in any group
+    const uint64_t nzl = ballot64(acc4 != 0);
+    const uint32_t nzw = (uint32_t)(nzl | (nzl >> 16) | (nzl >> 32) | (nzl >> 48)) & 0xFFFFu;
+    for (uint32_t t0 = 0; t0 < D; t0 += 64) {
+        const uint32_t t = t0 + lane;
+        // the last group whose start is <= t (empty groups share the next one's start)
+        const uint32_t gl = (uint32_t)(t >= s1) + (uint32_t)(t >= s2) + (uint32_t)(t >= s3);
+        const uint64_t bg = gl == 0 ? b0 : gl == 1 ? b1 : gl == 2 ? b2 : b3;
+        const uint32_t sg = gl == 0 ? 0u : gl == 1 ? s1 : gl == 2 ? s2 : s3;
+        const bool in = t < D;
+        const uint32_t r = in ? A.rcol[bg + (t - sg)] : 0u;
+        const bool fwd = in && r > ib;
+        const uint32_t rel = r - ib;
+        bool any = false;
+        uint32_t todo = nzw;
+        while (todo) {
+            const uint32_t w = (uint32_t)__builtin_ctz(todo);
+            todo &= todo - 1;
+            uint64_t m = shfl64(acc4, 16u * gl + w);
+            if (fwd) {
+                m &= rank_mask(rel, w);
+                if (m) {
+                    m &= ~A.C[(size_t)r * A.W + w];
+                    if (m) {
+                        atomicOr((unsigned long long*)&nr.msgs[(size_t)r * A.W + w], (unsigned long long)m);
+                        any = true;
+                    }
+                }
+            }
+        }
+        enqueue_receivers(A, X, nr.recv, nr.rout, nr.rstamp, nr.bstamp, r, any);
+    }
+}
+
+// The fused check (FUSE of phase_check, without bit-parallel labels) with
+// four receivers per wave: receivers i0 .. i0+3 are read and scanned side by
+// side by the four 16-lane groups (prune_scan4), so four receivers' chains
+// of dependent loads (receiver, list, label chunk, row mask, table segment)
+// are in flight in one wave.  The accepted entries are then appended one
+// receiver after another, and the next round's deliveries of all four go
+// out in one pass over their concatenated rows (push_edges4).  Active-list
+// slots, heavy rows, pulled rounds and statistics are phase_check's.
+template <int WM>
+__device__ inline void phase_check4(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t bs, uint32_t j,
+                                    bool relaxed, PhaseStats& st, const NextRound& nr) {
+    const uint32_t lane = lane_id();
+    const uint32_t W = A.W;
+    const uint32_t sub = lane & 15u, g = lane >> 4;
+    const uint32_t q = nr.hout;
+    uint32_t pre;
+    const uint32_t nrecv = shard_prefix(lane < X.nq ? X.qs[lane].recv[nr.rin] : 0u, pre);
+    // clear the counts the next launch appends to
+    if (X.zero_i < X.nq) {
+        X.qs[X.zero_i].recv[nr.rclr] = 0;
+        X.qs[X.zero_i].hq[q ^ 1u] = 0;
+    }
+    for (uint32_t i0 = 4u * X.w; i0 < nrecv; i0 += 4u * X.nw) {
+        const uint32_t ng = min(4u, nrecv - i0);
+        uint32_t slot = 0;
+        for (uint32_t gg = 0; gg < ng; ++gg) {
+            const uint32_t s = shard_of(X.nq, pre, i0 + gg);
+            const uint32_t at = s * X.seg + (i0 + gg - readlane32(pre, s));
+            if (g == gg) slot = at;
+        }
+        const bool has = g < ng;
+        const uint32_t i = i0 + g;
+        const uint32_t v = has ? A.recv[slot] : 0u;
+        uint64_t mine = 0;
+        if (has && sub < W) {
+            const size_t at = (size_t)v * W + sub;
+            mine = A.msgs[at];
+            A.msgs[at] = 0;
+            mine &= ~A.C[at];
+            A.C[at] |= mine;
+        }
+        const uint32_t len = has ? A.llen[v] : 0u;
+        const uint64_t off = has ? A.loff[v] : 0ull;
+        // round 1 never prunes (see phase_check); round 2 reads the
+        // neighbour row when it is the shorter source
+        uint64_t pw = 0;
+        if (j > 1) {
+            bool nbr = false;
+            uint64_t soff = off;
+            uint32_t slen = len, lim = 0;
+            if (j == 2 && A.nbr_hubs && has) {
+                const uint64_t rb = A.rrow[v], re = A.rrow[v + 1];
+                if (re - rb < len) {
+                    nbr = true;
+                    soff = rb;
+                    slen = (uint32_t)(re - rb);
+                    lim = min(v, relaxed ? ib : ib + bs);
+                }
+            }
+            pw = prune_scan4<WM>(A, soff, slen, nbr, lim, j, mine, relaxed, ib, st);
+        }
+        const uint64_t acc4 = mine & ~pw;
+        st.cand += __builtin_popcountll(mine);
+        st.cost_pos += (unsigned long long)len * (uint32_t)__builtin_popcountll(acc4);
+        st.cost_neg += (unsigned long long)len * (uint32_t)__builtin_popcountll(mine & ~acc4);
+        const uint64_t accl = ballot64(acc4 != 0);
+        if (!accl) continue;  // nothing accepted: no slots, no pushes
+        const bool gacc = ((accl >> (lane & 48u)) & 0xFFFFull) != 0;
+        if (gacc) {  // the active-list slot of a receiver that accepted
+            if (sub == 0) A.act_v[q][i] = v;
+            if (sub < W) A.act_delta[q][(size_t)i * W + sub] = acc4;
+        }
+        if (j >= PLL_INF8) {
+            if (lane == 0) atomicOr(&A.ctr->error, PLL_ERR_DIST);
+            continue;
+        }
+        // entries of each word before it, within each receiver's candidates
+        const uint32_t incl = row_incl_scan32((uint32_t)__builtin_popcountll(acc4));
+        uint32_t appended = 0;  // bit gg: receiver gg's entries are in its list
+        for (uint32_t gg = 0; gg < ng; ++gg) {
+            uint64_t todo = (accl >> (16u * gg)) & 0xFFFFull;
+            if (!todo) continue;
+            const uint32_t vg = readlane32(v, 16u * gg);
+            const uint32_t lg = readlane32(len, 16u * gg);
+            const uint32_t total = readlane32(incl, 16u * gg + 15u);
+            const uint64_t og = wave_reserve(A, X, vg, readlane64(off, 16u * gg), lg, total);
+            if (og == ~0ull) continue;
+            if (lane == 0) st.acc += total;
+            const bool in_batch = vg - ib < bs;
+            const uint64_t lt = lanemask_lt();
+            while (todo) {
+                const uint32_t w = (uint32_t)__builtin_ctzll(todo);
+                todo &= todo - 1;
+                const uint64_t aw = readlane64(acc4, 16u * gg + w);
+                const uint32_t pwos = readlane32(incl, 16u * gg + w) - (uint32_t)__builtin_popcountll(aw);
+                if ((aw >> lane) & 1ull) {
+                    const uint32_t k = w * 64u + lane;
+                    A.arena[og + lg + pwos + __builtin_popcountll(aw & lt)] = pll_pack(ib + k, j);
+                    if (in_batch) {
+                        A.T[(size_t)(ib + k) * A.bstride + (vg - ib)] = (uint8_t)j;
+                        if (ib + k >= A.hot)
+                            atomicOr((unsigned long long*)&A.rowmask[ib + k], 1ull << ((vg - ib) >> 4));
+                    }
+                }
+            }
+            if (lane == 0) A.llen[vg] = lg + total;
+            appended |= 1u << gg;
+        }
+        // round j+1: pulled (record where delta L(v) is) or pushed along the
+        // rows, those longer than kHeavy as heavy items of a separate launch
+        const bool out = (appended >> g) & 1u;
+        uint64_t rb = 0;
+        uint32_t deg = 0;
+        if (out) {
+            rb = A.rrow[v];
+            deg = (uint32_t)(A.rrow[v + 1] - rb);
+        }
+        if (nr.pull) {
+            if (out && sub == 0) {
+                A.act_at[v] = ((uint64_t)nr.rstamp << 32) | i;
+                st.pulled += deg;
+            }
+            continue;
+        }
+        const bool heavy = deg > kHeavy;
+        if (out && !heavy && sub == 0) st.edges += deg;
+        uint64_t hv = ballot64(out && heavy && sub == 0);
+        while (hv) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(hv);
+            hv &= hv - 1;
+            enqueue_heavy(A, X, q, i0 + l / 16u, readlane32(deg, l));
+        }
+        push_edges4(A, X, nr, ib, acc4, rb, out && !heavy ? deg : 0u);
     }
 }
 

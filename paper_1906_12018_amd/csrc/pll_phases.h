@@ -300,6 +300,17 @@ __device__ inline void phase_batch_init(const BuildArgs& A, const Exec& X, uint3
     for (uint32_t k = X.w; k < bs; k += X.nw) {
         const uint32_t u = ib + k;
         const uint32_t len = A.llen[u];
+        const uint64_t off0 = A.loff[u];
+        // the first four chunks of L(u) and u's degree are loaded ahead of
+        // the bookkeeping (a relocation by wave_reserve copies the same
+        // entries, so they stay valid)
+        uint32_t e[4];
+#pragma unroll
+        for (uint32_t c = 0; c < 4; ++c) {
+            const uint32_t i = 64u * c + lane;
+            e[c] = i < len ? A.arena[off0 + i] : 0u;
+        }
+        const uint64_t deg = A.rrow[u + 1] - A.rrow[u];
         const uint32_t tpos = shard_append(&X.qs[X.my].touched, lane == 0, (uint64_t)X.my * X.seg);
         if (lane == 0) {
             A.touch_stamp[u] = bstamp;
@@ -311,7 +322,7 @@ __device__ inline void phase_batch_init(const BuildArgs& A, const Exec& X, uint3
             if (lane < A.W) A.act_delta[0][(size_t)k * A.W + lane] = 0ull;
             continue;
         }
-        const uint64_t off = wave_reserve(A, X, u, A.loff[u], len, 1);
+        const uint64_t off = wave_reserve(A, X, u, off0, len, 1);
         if (off == ~0ull) continue;
         const unsigned long long kq = 1ull << (k >> 4);
         if (lane == 0) {
@@ -320,16 +331,28 @@ __device__ inline void phase_batch_init(const BuildArgs& A, const Exec& X, uint3
             A.T[(size_t)u * A.bstride + k] = 0;
             if (u >= A.hot) atomicOr((unsigned long long*)&A.rowmask[u], kq);
         }
-        for (uint32_t i = lane; i < len; i += 64) {
-            const uint32_t e = A.arena[off + i];
-            const uint32_t h = e >> 8;
-            A.T[(size_t)h * A.bstride + k] = (uint8_t)(e & 255u);
-            if (h >= A.hot) atomicOr((unsigned long long*)&A.rowmask[h], kq);
+        // four chunks at a time: loaded before any is written out
+        for (uint32_t i0 = 0; i0 < len; i0 += 256) {
+            if (i0) {
+#pragma unroll
+                for (uint32_t c = 0; c < 4; ++c) {
+                    const uint32_t i = i0 + 64u * c + lane;
+                    e[c] = i < len ? A.arena[off + i] : 0u;
+                }
+            }
+#pragma unroll
+            for (uint32_t c = 0; c < 4; ++c) {
+                if (i0 + 64u * c + lane < len) {
+                    const uint32_t h = e[c] >> 8;
+                    A.T[(size_t)h * A.bstride + k] = (uint8_t)(e[c] & 255u);
+                    if (h >= A.hot) atomicOr((unsigned long long*)&A.rowmask[h], kq);
+                }
+            }
         }
         if (lane == 0) A.act_v[0][k] = u;
         if (lane == 0 && A.act_rng[0]) A.act_rng[0][k] = make_uint2(len, 1u);  // the self entry
         if (lane < A.W) A.act_delta[0][(size_t)k * A.W + lane] = (lane == (k >> 6)) ? (1ull << (k & 63)) : 0ull;
-        enqueue_heavy(A, X, 0, k, A.rrow[u + 1] - A.rrow[u]);
+        enqueue_heavy(A, X, 0, k, deg);
     }
 }
 
@@ -357,6 +380,28 @@ __device__ inline void enqueue_receivers(const BuildArgs& A, const Exec& X, uint
     }
 }
 
+// Deliver to vertex r the words w[k] of a delta whose candidates ranked
+// above r are m[k] (0 for unused slots): each is filtered by C(r) and ORed
+// into msgs(r).  The four C loads are issued before any is used, so the
+// words of one edge cost one round trip.  Returns whether anything was
+// delivered.
+__device__ inline bool deliver4(const BuildArgs& A, uint64_t* msgs, uint32_t r, const uint32_t (&w)[4],
+                                const uint64_t (&m)[4]) {
+    uint64_t c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = m[k] ? A.C[(size_t)r * A.W + w[k]] : 0ull;
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t x = m[k] & ~c[k];
+        if (x) {
+            atomicOr((unsigned long long*)&msgs[(size_t)r * A.W + w[k]], (unsigned long long)x);
+            any = true;
+        }
+    }
+    return any;
+}
+
 // Push delta L(a) (lane w < W holds word w in dl; nz marks the nonzero
 // words) along the CSR entries [beg, end) of the active vertex a, into the
 // message buffer msgs and receiver queue rq (counters) stored in recv.
@@ -367,22 +412,20 @@ __device__ inline void push_edges(const BuildArgs& A, const Exec& X, uint64_t* m
     for (uint64_t e0 = beg; e0 < end; e0 += 64) {
         const uint64_t e = e0 + lane;
         const uint32_t r = e < end ? A.rcol[e] : 0u;
+        const bool fwd = e < end && r > ib;
+        const uint32_t rel = r - ib;
         bool any = false;
-        if (e < end && r > ib) {
-            const uint32_t rel = r - ib;
-            uint64_t todo = nz;
-            while (todo) {
-                const uint32_t w = (uint32_t)__builtin_ctzll(todo);
+        uint64_t todo = nz;
+        while (todo) {  // four words at a time
+            uint32_t w[4];
+            uint64_t m[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                w[k] = todo ? (uint32_t)__builtin_ctzll(todo) : 0u;
+                m[k] = todo && fwd ? readlane64(dl, w[k]) & rank_mask(rel, w[k]) : 0ull;
                 todo &= todo - 1;
-                uint64_t m = readlane64(dl, w) & rank_mask(rel, w);
-                if (m) {
-                    m &= ~A.C[(size_t)r * A.W + w];
-                    if (m) {
-                        atomicOr((unsigned long long*)&msgs[(size_t)r * A.W + w], (unsigned long long)m);
-                        any = true;
-                    }
-                }
             }
+            any |= deliver4(A, msgs, r, w, m);
         }
         enqueue_receivers(A, X, recv, rq, rstamp, bstamp, r, any);
     }
@@ -850,9 +893,8 @@ __device__ inline void push_edges4(const BuildArgs& A, const Exec& X, const Next
     const uint32_t D = s3 + readlane32(deg, 48);
     const uint64_t b0 = readlane64(beg, 0), b1 = readlane64(beg, 16), b2 = readlane64(beg, 32),
                    b3 = readlane64(beg, 48);
-    // candidate words with a delta in any group
+    // bit 16g + w: group g has a delta in word w
     const uint64_t nzl = ballot64(acc4 != 0);
-    const uint32_t nzw = (uint32_t)(nzl | (nzl >> 16) | (nzl >> 32) | (nzl >> 48)) & 0xFFFFu;
     for (uint32_t t0 = 0; t0 < D; t0 += 64) {
         const uint32_t t = t0 + lane;
         // the last group whose start is <= t (empty groups share the next one's start)
@@ -864,21 +906,19 @@ __device__ inline void push_edges4(const BuildArgs& A, const Exec& X, const Next
         const bool fwd = in && r > ib;
         const uint32_t rel = r - ib;
         bool any = false;
-        uint32_t todo = nzw;
-        while (todo) {
-            const uint32_t w = (uint32_t)__builtin_ctz(todo);
-            todo &= todo - 1;
-            uint64_t m = shfl64(acc4, 16u * gl + w);
-            if (fwd) {
-                m &= rank_mask(rel, w);
-                if (m) {
-                    m &= ~A.C[(size_t)r * A.W + w];
-                    if (m) {
-                        atomicOr((unsigned long long*)&nr.msgs[(size_t)r * A.W + w], (unsigned long long)m);
-                        any = true;
-                    }
-                }
+        // the nonzero words of this edge's receiver, four at a time
+        uint32_t todo = fwd ? (uint32_t)(nzl >> (16u * gl)) & 0xFFFFu : 0u;
+        while (ballot64(todo != 0)) {
+            uint32_t w[4];
+            uint64_t m[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                w[k] = todo ? (uint32_t)__builtin_ctz(todo) : 0u;
+                const uint64_t x = shfl64(acc4, 16u * gl + w[k]);
+                m[k] = todo ? x & rank_mask(rel, w[k]) : 0ull;
+                todo &= todo - 1;
             }
+            any |= deliver4(A, nr.msgs, r, w, m);
         }
         enqueue_receivers(A, X, nr.recv, nr.rout, nr.rstamp, nr.bstamp, r, any);
     }
@@ -1386,10 +1426,21 @@ __device__ inline void phase_clear_table(const BuildArgs& A, const Exec& X, uint
         const uint32_t u = ib + k;
         const uint32_t len = A.llen[u];
         const uint64_t off = A.loff[u];
-        for (uint32_t i = lane; i < len; i += 64) {
-            const uint32_t h = A.arena[off + i] >> 8;
-            A.T[(size_t)h * A.bstride + k] = (uint8_t)PLL_INF8;
-            if (h >= A.hot) A.rowmask[h] = 0;
+        // four chunks of the list are loaded before any is cleared
+        for (uint32_t i0 = 0; i0 < len; i0 += 256) {
+            uint32_t h[4];
+#pragma unroll
+            for (uint32_t c = 0; c < 4; ++c) {
+                const uint32_t i = i0 + 64u * c + lane;
+                h[c] = i < len ? A.arena[off + i] >> 8 : 0u;
+            }
+#pragma unroll
+            for (uint32_t c = 0; c < 4; ++c) {
+                if (i0 + 64u * c + lane < len) {
+                    A.T[(size_t)h[c] * A.bstride + k] = (uint8_t)PLL_INF8;
+                    if (h[c] >= A.hot) A.rowmask[h[c]] = 0;
+                }
+            }
         }
         if (lane == 0 && u >= A.hot) A.rowmask[u] = 0;
     }

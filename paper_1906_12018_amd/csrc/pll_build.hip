@@ -39,6 +39,7 @@ constexpr int kWavesPerBlock = kBlock / PLL_WAVE;
 constexpr uint32_t kMaxBlocks = 4096;
 constexpr uint32_t kHotRows = 256;         // top-ranked table rows whose row masks stay all ones
 constexpr uint64_t kPullFrac = 2;          // a round with at least n / 2 receivers pulls the next one
+constexpr uint64_t kPullFrac1 = 8;         // ... and a batch's first round with at least n / 8
 constexpr uint32_t kPullMinN = 16384;      // smaller graphs always push (the pull's set-up outweighs it)
 constexpr uint64_t kPackMin = 16384;       // receivers from which a fused round checks four per wave
 
@@ -1199,7 +1200,7 @@ int init_state(DevAllocs& M, BuildArgs& A, uint32_t n, uint64_t nnz, uint32_t W,
     A.rowmask = M.get<uint64_t>(n);
     A.Tchk = A.T;
     A.rmchk = A.rowmask;
-    A.hq_seg = 2 * (nnz / kHeavy) + 64;
+    A.hq_seg = 2 * (nnz / pll::kHeavyItem) + 64;
     for (int q = 0; q < 2; ++q) {
         A.act_v[q] = M.get<uint32_t>(n);
         A.act_delta[q] = M.get<uint64_t>((size_t)n * W);
@@ -1484,7 +1485,9 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
         uint64_t next_est = r1_est;
         for (uint32_t j = 1;; ++j) {
             ++rounds;
-            const uint32_t pull = pull_ok && next_est * kPullFrac >= n ? 1u : 0u;
+            // the first round's receivers push the batch's densest deltas along
+            // high-degree rows, so gathering pays off from fewer of them
+            const uint32_t pull = pull_ok && next_est * (j == 1 ? kPullFrac1 : kPullFrac) >= n ? 1u : 0u;
             const pll::NextRound nr{mbuf[(j + 1) & 1u], rbuf[(j + 1) & 1u], (j - 1) % 3, j % 3, (j + 1) % 3, j & 1u,
                                     rstamp + 1, bstamp, pull};
             ++rstamp;
@@ -2169,7 +2172,7 @@ size_t noalloc_state_bytes(uint32_t n, uint64_t nnz, uint32_t W) {
     size_t b = blk(sizeof(DevCounters));
     b += blk(4 * N) + blk(4 * (N + 1)) + blk(8 * ((N + 1) / kScanTile + 2)) + blk(8 * (N + 1)) + blk(4 * E);
     b += 2 * blk(8 * (N + 1)) + 2 * blk(4 * N) + 2 * blk(8 * N * W) + blk(64 * W * N) + blk(8 * N);
-    const size_t hq_seg = 2 * (nnz / kHeavy) + 64;
+    const size_t hq_seg = 2 * (nnz / pll::kHeavyItem) + 64;
     b += 2 * (blk(4 * N) + blk(8 * N * W) + blk(8 * PLL_SHARDS * hq_seg));
     b += 3 * blk(4 * PLL_SHARDS * N) + 2 * blk(4 * N);
     b += blk(8 * N * W) + blk(4 * PLL_SHARDS * N);

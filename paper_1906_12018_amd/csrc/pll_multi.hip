@@ -508,7 +508,7 @@ int multi_attempt(uint32_t count, const pll_graph_desc* graphs, uint32_t b, uint
     std::vector<Off> off(count);
     for (uint32_t g = 0; g < count; ++g) {
         const uint64_t n = graphs[g].n, nnz = graphs[g].nnz, gs = G[g];
-        const uint64_t hq_seg = 2 * (nnz / pll::kHeavy) + 64;
+        const uint64_t hq_seg = 2 * (nnz / pll::kHeavyItem) + 64;
         Off& o = off[g];
         o.gc = take(zb, sizeof(GangCtl));
         o.loff = take(zb, 8 * (n + 1));

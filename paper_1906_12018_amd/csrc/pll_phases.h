@@ -12,8 +12,10 @@
 
 namespace pll {
 
-// Rows longer than this are pushed as several work items of kHeavy edges.
+// Rows longer than kHeavy are not pushed by the wave that owns them but
+// queued as work items of kHeavyItem edges, spread over every wave.
 constexpr uint32_t kHeavy = 1024;
+constexpr uint32_t kHeavyItem = 256;
 
 struct Exec {
     uint32_t w, nw;   // this wave's index in the group, waves in the group
@@ -274,11 +276,11 @@ __device__ inline uint32_t shard_append(uint32_t* counter, bool take, uint64_t s
     return (uint32_t)(seg_base + base + __builtin_popcountll(bal & lanemask_lt()));
 }
 
-// Queue the row of active slot `slot` (list q) as kHeavy-edge items when
-// it is longer than kHeavy.
+// Queue the row of active slot `slot` (list q) as kHeavyItem-edge items
+// when it is longer than kHeavy.
 __device__ inline void enqueue_heavy(const BuildArgs& A, const Exec& X, uint32_t q, uint32_t slot, uint64_t deg) {
     if (deg <= kHeavy) return;
-    const uint32_t nch = (uint32_t)((deg + kHeavy - 1) / kHeavy);
+    const uint32_t nch = (uint32_t)((deg + kHeavyItem - 1) / kHeavyItem);
     uint32_t base = 0;
     if (lane_id() == 0) base = atomicAdd(&X.qs[X.my].hq[q], nch);
     base = readlane32(base, 0);
@@ -447,8 +449,8 @@ __device__ inline void phase_push_heavy(const BuildArgs& A, const Exec& X, uint3
         const uint64_t dl = lane < A.W ? act_d[(size_t)item.x * A.W + lane] : 0ull;
         const uint64_t nz = ballot64(dl != 0);
         const uint32_t a = act_v[item.x];
-        const uint64_t beg = A.rrow[a] + (uint64_t)item.y * kHeavy;
-        const uint64_t end = min(A.rrow[a + 1], beg + kHeavy);
+        const uint64_t beg = A.rrow[a] + (uint64_t)item.y * kHeavyItem;
+        const uint64_t end = min(A.rrow[a + 1], beg + kHeavyItem);
         if (lane == 0) st.edges += end - beg;
         push_edges(A, X, msgs, recv, ib, rq, rstamp, bstamp, dl, nz, beg, end);
     }
@@ -1339,8 +1341,8 @@ __device__ inline void phase_push_w(const BuildArgs& A, const Exec& X, uint32_t 
         const uint2 item = A.hq[p][s * A.hq_seg + (t - readlane32(pre, s))];
         const uint2 rg = A.act_rng[p][item.x];
         const uint32_t a = A.act_v[p][item.x];
-        const uint64_t beg = A.rrow[a] + (uint64_t)item.y * kHeavy;
-        const uint64_t end = min(A.rrow[a + 1], beg + kHeavy);
+        const uint64_t beg = A.rrow[a] + (uint64_t)item.y * kHeavyItem;
+        const uint64_t end = min(A.rrow[a + 1], beg + kHeavyItem);
         if (lane == 0) st.edges += end - beg;
         push_edges_w(A, X, ib, p, rstamp, bstamp, A.loff[a] + rg.x, rg.y, beg, end);
     }

@@ -1549,7 +1549,7 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
         }
         hipEvent_t e1 = P.mark();
         dispatch_batch_end(blocks_for_waves(sum_touched(h)), s, A, ib, bs, recheck);
-        k_clear_table<<<blocks_for_waves(bs), kBlock, 0, s>>>(A, ib, bs, ctr);
+        k_clear_table<<<blocks_for_waves(4ull * bs), kBlock, 0, s>>>(A, ib, bs, ctr);
         P.span(PLL_PHASE_END, e1, P.mark(), 2);
         TRY_HIP(hipGetLastError());
         // compact the lists into a larger arena once a bump region is half used
@@ -1719,7 +1719,7 @@ int build_attempt_weighted(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
         }
         hipEvent_t e1 = P.mark();
         dispatch_batch_end_w(blocks_for_waves(sum_touched(h)), s, A, ib, bs);
-        k_clear_table<<<blocks_for_waves(bs), kBlock, 0, s>>>(A, ib, bs, nullptr);
+        k_clear_table<<<blocks_for_waves(4ull * bs), kBlock, 0, s>>>(A, ib, bs, nullptr);
         P.span(PLL_PHASE_END, e1, P.mark(), 2);
         TRY_HIP(hipGetLastError());
         if (!arena_fixed && ib + b < n && max_top(h) * 2 > A.region_cap) {
@@ -1937,7 +1937,7 @@ int build_attempt_directed(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, co
         // are cleared only after both
         hipEvent_t e1 = P.mark();
         for (int d = 0; d < 2; ++d) dispatch_batch_end(blocks_for_waves(sum_touched(h[d])), s, A[d], ib, bs, recheck);
-        for (int d = 0; d < 2; ++d) k_clear_table<<<blocks_for_waves(bs), kBlock, 0, s>>>(A[d], ib, bs, nullptr);
+        for (int d = 0; d < 2; ++d) k_clear_table<<<blocks_for_waves(4ull * bs), kBlock, 0, s>>>(A[d], ib, bs, nullptr);
         P.span(PLL_PHASE_END, e1, P.mark(), 4);
         TRY_HIP(hipGetLastError());
         for (int d = 0; d < 2; ++d) {

@@ -1424,27 +1424,19 @@ __device__ inline void phase_check_w(const BuildArgs& A, const Exec& X, uint32_t
 // Reset the distance table rows written during the batch.
 __device__ inline void phase_clear_table(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t bs) {
     const uint32_t lane = lane_id();
-    for (uint32_t k = X.w; k < bs; k += X.nw) {
+    // four waves per root: task t clears the 64-entry chunks c, c + 4, ...
+    // of root k (t = 4k + c)
+    for (uint32_t t = X.w; t < 4u * bs; t += X.nw) {
+        const uint32_t k = t >> 2, c = t & 3u;
         const uint32_t u = ib + k;
         const uint32_t len = A.llen[u];
         const uint64_t off = A.loff[u];
-        // four chunks of the list are loaded before any is cleared
-        for (uint32_t i0 = 0; i0 < len; i0 += 256) {
-            uint32_t h[4];
-#pragma unroll
-            for (uint32_t c = 0; c < 4; ++c) {
-                const uint32_t i = i0 + 64u * c + lane;
-                h[c] = i < len ? A.arena[off + i] >> 8 : 0u;
-            }
-#pragma unroll
-            for (uint32_t c = 0; c < 4; ++c) {
-                if (i0 + 64u * c + lane < len) {
-                    A.T[(size_t)h[c] * A.bstride + k] = (uint8_t)PLL_INF8;
-                    if (h[c] >= A.hot) A.rowmask[h[c]] = 0;
-                }
-            }
+        for (uint32_t i = 64u * c + lane; i < len; i += 256u) {
+            const uint32_t h = A.arena[off + i] >> 8;
+            A.T[(size_t)h * A.bstride + k] = (uint8_t)PLL_INF8;
+            if (h >= A.hot) A.rowmask[h] = 0;
         }
-        if (lane == 0 && u >= A.hot) A.rowmask[u] = 0;
+        if (c == 0 && lane == 0 && u >= A.hot) A.rowmask[u] = 0;
     }
 }
 

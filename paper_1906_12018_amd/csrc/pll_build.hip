@@ -347,14 +347,17 @@ __global__ void __launch_bounds__(kBlock) k_check(BuildArgs A, uint32_t ib, uint
 }
 
 // Round j's check fused with round j+1's push (NextRound in pll_phases.h).
-template <int WM, bool BP, bool PACK = false>
+// SMALLT: every prune threshold of round j is at most pll::kSmallT (j <= kSmallT),
+// so the scans take the cheaper byte compare.  The packed check is only
+// instantiated with it.
+template <int WM, bool BP, bool PACK = false, bool SMALLT = false>
 __device__ inline void check_push_body(const BuildArgs& A, const pll::Exec& X, uint32_t ib, uint32_t bs, uint32_t j,
                                        const pll::NextRound& nr, uint32_t relaxed) {
     PhaseStats st;
     if (PACK && !BP)
-        pll::phase_check4<WM>(A, X, ib, bs, j, relaxed != 0, st, nr);
+        pll::phase_check4<WM, SMALLT>(A, X, ib, bs, j, relaxed != 0, st, nr);
     else
-        pll::phase_check<WM, BP, true>(A, X, ib, bs, j, nr.rin, relaxed != 0, st, &nr);
+        pll::phase_check<WM, BP, true, false, SMALLT && !BP>(A, X, ib, bs, j, nr.rin, relaxed != 0, st, &nr);
     const unsigned long long v[9] = {st.cand,     st.acc, st.read,  st.table,          st.cost_pos,
                                      st.cost_neg, st.bp,  st.edges + st.pulled, st.edges};
     const int which[9] = {PLL_ST_CAND,     PLL_ST_ACC, PLL_ST_READ,  PLL_ST_TABLE,      PLL_ST_COST_POS,
@@ -363,10 +366,10 @@ __device__ inline void check_push_body(const BuildArgs& A, const pll::Exec& X, u
 }
 
 // at most 128 VGPRs, i.e. 4 waves per SIMD, like the unfused check
-template <int WM, bool PACK>
+template <int WM, bool PACK, bool SMALLT>
 __global__ void __launch_bounds__(kBlock, 4) k_check_push(BuildArgs A, uint32_t ib, uint32_t bs, uint32_t j,
                                                           pll::NextRound nr, uint32_t relaxed) {
-    check_push_body<WM, false, PACK>(A, grid_exec(A), ib, bs, j, nr, relaxed);
+    check_push_body<WM, false, PACK, SMALLT>(A, grid_exec(A), ib, bs, j, nr, relaxed);
 }
 
 // The blocks [b0, b0 + nb) of the grid run a phase on their own: queue
@@ -386,14 +389,14 @@ __device__ inline pll::Exec side_exec(const BuildArgs& A, uint32_t b0, uint32_t 
 
 // Directed graphs: both sides' fused rounds in one launch, blocks [0, nb0)
 // on the forward side and the rest on the backward side.
-template <int WM>
+template <int WM, bool SMALLT>
 __global__ void __launch_bounds__(kBlock, 4) k_check_push2(BuildArgs A0, pll::NextRound nr0, BuildArgs A1,
                                                            pll::NextRound nr1, uint32_t ib, uint32_t bs, uint32_t j,
                                                            uint32_t nb0) {
     if (blockIdx.x < nb0)
-        check_push_body<WM, false>(A0, side_exec(A0, 0, nb0), ib, bs, j, nr0, 0);
+        check_push_body<WM, false, false, SMALLT>(A0, side_exec(A0, 0, nb0), ib, bs, j, nr0, 0);
     else
-        check_push_body<WM, false>(A1, side_exec(A1, nb0, gridDim.x - nb0), ib, bs, j, nr1, 0);
+        check_push_body<WM, false, false, SMALLT>(A1, side_exec(A1, nb0, gridDim.x - nb0), ib, bs, j, nr1, 0);
 }
 
 // with bit-parallel labels (no register cap: it would spill)
@@ -987,22 +990,33 @@ void launch_check_push(uint32_t blocks, hipStream_t s, const BuildArgs& A, uint3
                        const pll::NextRound& nr, uint32_t relaxed, bool pack) {
     if (A.bp_t)
         k_check_push_bp<WM><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, nr, relaxed);
-    else if (pack)
-        k_check_push<WM, true><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, nr, relaxed);
+    else if (pack)  // only in rounds j <= kSmallT
+        k_check_push<WM, true, true><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, nr, relaxed);
+    else if (j <= pll::kSmallT)
+        k_check_push<WM, false, true><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, nr, relaxed);
     else
-        k_check_push<WM, false><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, nr, relaxed);
+        k_check_push<WM, false, false><<<blocks, kBlock, 0, s>>>(A, ib, bs, j, nr, relaxed);
+}
+
+template <bool SMALLT>
+void launch_check_push2(uint32_t nb0, uint32_t nb1, hipStream_t s, const BuildArgs& A0, const pll::NextRound& nr0,
+                        const BuildArgs& A1, const pll::NextRound& nr1, uint32_t ib, uint32_t bs, uint32_t j) {
+    const uint32_t g = nb0 + nb1;
+    switch (words_class(A0.W)) {
+        case 1: k_check_push2<1, SMALLT><<<g, kBlock, 0, s>>>(A0, nr0, A1, nr1, ib, bs, j, nb0); break;
+        case 2: k_check_push2<2, SMALLT><<<g, kBlock, 0, s>>>(A0, nr0, A1, nr1, ib, bs, j, nb0); break;
+        case 4: k_check_push2<4, SMALLT><<<g, kBlock, 0, s>>>(A0, nr0, A1, nr1, ib, bs, j, nb0); break;
+        case 8: k_check_push2<8, SMALLT><<<g, kBlock, 0, s>>>(A0, nr0, A1, nr1, ib, bs, j, nb0); break;
+        default: k_check_push2<16, SMALLT><<<g, kBlock, 0, s>>>(A0, nr0, A1, nr1, ib, bs, j, nb0); break;
+    }
 }
 
 void dispatch_check_push2(uint32_t nb0, uint32_t nb1, hipStream_t s, const BuildArgs& A0, const pll::NextRound& nr0,
                           const BuildArgs& A1, const pll::NextRound& nr1, uint32_t ib, uint32_t bs, uint32_t j) {
-    const uint32_t g = nb0 + nb1;
-    switch (words_class(A0.W)) {
-        case 1: k_check_push2<1><<<g, kBlock, 0, s>>>(A0, nr0, A1, nr1, ib, bs, j, nb0); break;
-        case 2: k_check_push2<2><<<g, kBlock, 0, s>>>(A0, nr0, A1, nr1, ib, bs, j, nb0); break;
-        case 4: k_check_push2<4><<<g, kBlock, 0, s>>>(A0, nr0, A1, nr1, ib, bs, j, nb0); break;
-        case 8: k_check_push2<8><<<g, kBlock, 0, s>>>(A0, nr0, A1, nr1, ib, bs, j, nb0); break;
-        default: k_check_push2<16><<<g, kBlock, 0, s>>>(A0, nr0, A1, nr1, ib, bs, j, nb0); break;
-    }
+    if (j <= pll::kSmallT)
+        launch_check_push2<true>(nb0, nb1, s, A0, nr0, A1, nr1, ib, bs, j);
+    else
+        launch_check_push2<false>(nb0, nb1, s, A0, nr0, A1, nr1, ib, bs, j);
 }
 
 void dispatch_check_push(uint32_t blocks, hipStream_t s, const BuildArgs& A, uint32_t ib, uint32_t bs, uint32_t j,
@@ -1497,7 +1511,7 @@ int build_attempt(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint3
             if (P.on) k_delay<<<1, 1, 0, s>>>(delay_ticks);
             hipEvent_t r1 = P.mark();
             // rounds with many receivers check four per wave (phase_check4)
-            const bool pack = (flags & PLL_FLAG_PACK4) || next_est >= kPackMin;
+            const bool pack = ((flags & PLL_FLAG_PACK4) || next_est >= kPackMin) && j <= pll::kSmallT;
             const uint64_t waves = pack ? next_est / 4 + 512 : next_est + 2048;
             dispatch_check_push(blocks_for_waves(std::min<uint64_t>(n, waves)), s, Aj, ib, bs, j, nr, relaxed, pack);
             P.span(PLL_PHASE_CHECK, r1, P.mark(), 1);

@@ -61,6 +61,43 @@ __device__ inline uint64_t le_mask64(const uint8_t* p, uint32_t tt) {
     return m;
 }
 
+// le_mask64 for thresholds t <= kSmallT, with tt1 = (t + 1) * 0x01010101:
+// every byte of x | 0x80 is at least 128 > t + 1, so the subtraction
+// borrows within no byte, and bit 7 of the difference is clear exactly when
+// the byte's low 7 bits are <= t; a byte with bit 7 set (128..255) is above
+// t.  Four instructions per word instead of le4's seven.
+constexpr uint32_t kSmallT = 126;
+
+__device__ inline uint32_t le4s(uint32_t x, uint32_t tt1) {
+    const uint32_t H = 0x80808080u;
+    const uint32_t r = ~(((x | H) - tt1) | x) & H;
+    return ((r >> 7) * 0x01020408u) >> 24;
+}
+
+__device__ inline uint64_t le_mask64s(const uint8_t* p, uint32_t tt1) {
+    const uint4* q = reinterpret_cast<const uint4*>(p);
+    uint64_t m = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint4 v = q[i];
+        const uint32_t b = le4s(v.x, tt1) | (le4s(v.y, tt1) << 4) | (le4s(v.z, tt1) << 8) | (le4s(v.w, tt1) << 12);
+        m |= (uint64_t)b << (16 * i);
+    }
+    return m;
+}
+
+// The segment compare of the scans: SMALLT (every threshold <= kSmallT) takes
+// le_mask64s with tt = (t + 1) * 0x01010101, else le_mask64 with t * 0x01010101.
+template <bool SMALLT>
+__device__ inline uint32_t seg_tt(uint32_t t) {
+    return (SMALLT ? t + 1u : t) * 0x01010101u;
+}
+
+template <bool SMALLT>
+__device__ inline uint64_t seg_le(const uint8_t* p, uint32_t tt) {
+    return SMALLT ? le_mask64s(p, tt) : le_mask64(p, tt);
+}
+
 // le_mask64 over the 16-byte quarters selected by `need` (bit i: bytes
 // 16i .. 16i+15); the other quarters are neither loaded nor matched.
 __device__ inline uint64_t le_mask64_q(const uint8_t* p, uint32_t tt, uint32_t need) {
@@ -109,7 +146,7 @@ __device__ inline uint64_t wave_or64_u(uint64_t x) {
 // of its quarters qualifies (fewer, wider loads: measured faster on the large
 // single-graph builds, while the many-graph kernel, whose small graphs leave
 // table rows sparse, gains from the gating).
-template <int WM, bool QGATE = false>
+template <int WM, bool QGATE = false, bool SMALLT = false>
 __device__ inline uint64_t prune_scan(const BuildArgs& A, uint64_t off, uint32_t len, uint32_t j, uint64_t cw,
                                       bool relaxed, uint32_t ib, PhaseStats& st) {
     const uint32_t lane = lane_id();
@@ -128,7 +165,7 @@ __device__ inline uint64_t prune_scan(const BuildArgs& A, uint64_t off, uint32_t
         const uint64_t rm = ok ? A.rmchk[h] : 0ull;
         // threshold at most 254, the largest finite table byte: at round 255
         // (which only reports the overflow) an empty cell must not prune
-        const uint32_t tt = ok ? min(j - d, PLL_INF8 - 1u) * 0x01010101u : 0u;
+        const uint32_t tt = ok ? seg_tt<SMALLT>(min(j - d, PLL_INF8 - 1u)) : 0u;
         const uint8_t* row = A.Tchk + (size_t)h * A.bstride;
         // One pass per word that still holds live candidates (a scalar loop
         // over their mask): every lane compares its entry's table segment,
@@ -150,7 +187,7 @@ __device__ inline uint64_t prune_scan(const BuildArgs& A, uint64_t off, uint32_t
                     st.table += __builtin_popcount(need & 15u);
                 }
             } else if ((rm >> (4 * w)) & 15u) {
-                m = le_mask64(row + 64u * w, tt) & live;
+                m = seg_le<SMALLT>(row + 64u * w, tt) & live;
                 st.table += 4;
             }
             const uint64_t red = wave_or64_u(m);
@@ -173,13 +210,13 @@ __device__ inline uint64_t prune_scan(const BuildArgs& A, uint64_t off, uint32_t
 // entries).  Candidate u_k is pruned when T[h][k] <= 1; the table loads,
 // which are the same as those of the label scan, and the lane reductions
 // are those of prune_scan.
-template <int WM, bool QGATE = false>
+template <int WM, bool QGATE = false, bool SMALLT = false>
 __device__ inline uint64_t prune_scan_nbrs(const BuildArgs& A, uint32_t v, uint32_t lim, uint64_t cw,
                                            PhaseStats& st) {
     const uint32_t lane = lane_id();
     uint64_t pw = 0;
     const uint64_t beg = A.rrow[v], end = A.rrow[v + 1];
-    const uint32_t tt = 0x01010101u;  // T[h][k] <= 2 - 1
+    const uint32_t tt = seg_tt<SMALLT>(1u);  // T[h][k] <= 2 - 1
     for (uint64_t base = beg; base < end; base += 64) {
         const uint64_t idx = base + lane;
         const uint32_t h = idx < end ? A.rcol[idx] : ~0u;
@@ -202,7 +239,7 @@ __device__ inline uint64_t prune_scan_nbrs(const BuildArgs& A, uint32_t v, uint3
                     st.table += __builtin_popcount(need & 15u);
                 }
             } else if ((rm >> (4 * w)) & 15u) {
-                m = le_mask64(row + 64u * w, tt) & live;
+                m = seg_le<SMALLT>(row + 64u * w, tt) & live;
                 st.table += 4;
             }
             const uint64_t red = wave_or64_u(m);
@@ -677,7 +714,7 @@ __device__ inline uint64_t bp_prune_words(const BuildArgs& A, uint32_t v, uint32
 // and nr->rclr, cleared here); active lists and heavy items use parity
 // nr->hout.
 
-template <int WM, bool BP = false, bool FUSE = false, bool QGATE = false>
+template <int WM, bool BP = false, bool FUSE = false, bool QGATE = false, bool SMALLT = false>
 __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t bs, uint32_t j, uint32_t p,
                                    bool relaxed, PhaseStats& st, const NextRound* nr = nullptr) {
     const uint32_t lane = lane_id();
@@ -719,9 +756,9 @@ __device__ inline void phase_check(const BuildArgs& A, const Exec& X, uint32_t i
         // ranked below it, and L(u_k) holds only hubs ranked above u_k.
         uint64_t pw = 0;
         if (j == 2 && A.nbr_hubs && A.rrow[v + 1] - A.rrow[v] < len)
-            pw = prune_scan_nbrs<WM, QGATE>(A, v, min(v, relaxed ? ib : ib + bs), scan, st);
+            pw = prune_scan_nbrs<WM, QGATE, SMALLT>(A, v, min(v, relaxed ? ib : ib + bs), scan, st);
         else if (j > 1)
-            pw = prune_scan<WM, QGATE>(A, off, len, j, scan, relaxed, ib, st);
+            pw = prune_scan<WM, QGATE, SMALLT>(A, off, len, j, scan, relaxed, ib, st);
         const uint64_t acc = lane < W ? (scan & ~pw) : 0ull;
         const uint32_t cnt = (uint32_t)__builtin_popcountll(acc);
         const uint32_t pos = wave_excl_scan32(cnt);
@@ -813,7 +850,7 @@ __device__ inline uint64_t shfl64(uint64_t x, uint32_t src) {
 // within its 16-lane row.  A group stops after the chunk that leaves none
 // of its candidates live, or at its list's end.  Returns, in lane 16g + w,
 // the pruned candidates of word w of receiver g.
-template <int WM>
+template <int WM, bool SMALLT>
 __device__ inline uint64_t prune_scan4(const BuildArgs& A, uint64_t off, uint32_t len, bool nbr, uint32_t lim,
                                        uint32_t j, uint64_t cw, bool relaxed, uint32_t ib, PhaseStats& st) {
     const uint32_t lane = lane_id();
@@ -838,14 +875,14 @@ __device__ inline uint64_t prune_scan4(const BuildArgs& A, uint64_t off, uint32_
         if (nbr) {
             h = ent;
             ok = ok && h < lim;
-            tt = 0x01010101u;  // T[h][k] <= 2 - 1
+            tt = seg_tt<SMALLT>(1u);  // T[h][k] <= 2 - 1
         } else {
             h = ent >> 8;
             const uint32_t d = ent & 255u;
             ok = ok && d < j;
             if (relaxed) ok = ok && h < ib;
             // at most 254, the largest finite table byte (see prune_scan)
-            tt = ok ? min(j - d, PLL_INF8 - 1u) * 0x01010101u : 0u;
+            tt = ok ? seg_tt<SMALLT>(min(j - d, PLL_INF8 - 1u)) : 0u;
         }
         const uint64_t rm = ok ? A.rmchk[h] : 0ull;
         const uint8_t* row = A.Tchk + (size_t)(ok ? h : 0u) * A.bstride;
@@ -857,7 +894,7 @@ __device__ inline uint64_t prune_scan4(const BuildArgs& A, uint64_t off, uint32_
             const uint64_t live = shfl64(live_lane, gsh + w);
             uint64_t m = 0;
             if (act && ((rm >> (4 * w)) & 15u)) {
-                m = le_mask64(row + 64u * w, tt) & live;
+                m = seg_le<SMALLT>(row + 64u * w, tt) & live;
                 st.table += 4;
             }
             const uint64_t red = row_or64_dpp(m);
@@ -934,7 +971,7 @@ __device__ inline void push_edges4(const BuildArgs& A, const Exec& X, const Next
 // receiver after another, and the next round's deliveries of all four go
 // out in one pass over their concatenated rows (push_edges4).  Active-list
 // slots, heavy rows, pulled rounds and statistics are phase_check's.
-template <int WM>
+template <int WM, bool SMALLT>
 __device__ inline void phase_check4(const BuildArgs& A, const Exec& X, uint32_t ib, uint32_t bs, uint32_t j,
                                     bool relaxed, PhaseStats& st, const NextRound& nr) {
     const uint32_t lane = lane_id();
@@ -985,7 +1022,7 @@ __device__ inline void phase_check4(const BuildArgs& A, const Exec& X, uint32_t 
                     lim = min(v, relaxed ? ib : ib + bs);
                 }
             }
-            pw = prune_scan4<WM>(A, soff, slen, nbr, lim, j, mine, relaxed, ib, st);
+            pw = prune_scan4<WM, SMALLT>(A, soff, slen, nbr, lim, j, mine, relaxed, ib, st);
         }
         const uint64_t acc4 = mine & ~pw;
         st.cand += __builtin_popcountll(mine);

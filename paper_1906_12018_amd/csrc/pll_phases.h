@@ -38,14 +38,27 @@ struct PhaseStats {
     unsigned long long pulled = 0;
 };
 
-// Per byte of x: 1 if byte <= t, where tt = t * 0x01010101 (t <= 254).  Bytes
-// are compared without carries between them: s holds, in bit 7 of each
-// byte, [low 7 bits of t >= low 7 bits of x]; the high bits decide the rest.
-__device__ inline uint32_t le4(uint32_t x, uint32_t tt) {
+// Bit 7 of each byte of the result: that byte of x is <= t, where
+// tt = t * 0x01010101 (t <= 254).  Bytes are compared without carries
+// between them: s holds, in bit 7 of each byte, [low 7 bits of t >= low 7
+// bits of x]; the high bits decide the rest.
+__device__ inline uint32_t le4_flags(uint32_t x, uint32_t tt) {
     const uint32_t H = 0x80808080u;
     const uint32_t s = (tt | H) - (x & ~H);
-    const uint32_t r = ((tt & ~x) | (~(tt ^ x) & s)) & H;
-    return ((r >> 7) * 0x01020408u) >> 24;  // gather bits 7, 15, 23, 31 into bits 0..3
+    return ((tt & ~x) | (~(tt ^ x) & s)) & H;
+}
+
+// The flags of two words (bits 7, 15, 23, 31 of a and of b) as 8 bits, a's
+// in bits 0..3: one multiply gathers both, since with a's flags moved to
+// bits 0, 8, 16, 24 and b's to 4, 12, 20, 28, every cross term of the
+// product lands below bit 24 or above bit 31, each on a bit of its own.
+__device__ inline uint32_t gather8(uint32_t a, uint32_t b) {
+    return (((a >> 7) | (b >> 3)) * 0x01020408u) >> 24;
+}
+
+// The 16 flags of a 16-byte quarter, byte i in bit i.
+__device__ inline uint32_t gather16(uint32_t fx, uint32_t fy, uint32_t fz, uint32_t fw) {
+    return gather8(fx, fy) | (gather8(fz, fw) << 8);
 }
 
 // Bit i of the result: table byte p[i] <= t, for 64 consecutive bytes.
@@ -55,7 +68,7 @@ __device__ inline uint64_t le_mask64(const uint8_t* p, uint32_t tt) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const uint4 v = q[i];
-        const uint32_t b = le4(v.x, tt) | (le4(v.y, tt) << 4) | (le4(v.z, tt) << 8) | (le4(v.w, tt) << 12);
+        const uint32_t b = gather16(le4_flags(v.x, tt), le4_flags(v.y, tt), le4_flags(v.z, tt), le4_flags(v.w, tt));
         m |= (uint64_t)b << (16 * i);
     }
     return m;
@@ -65,25 +78,28 @@ __device__ inline uint64_t le_mask64(const uint8_t* p, uint32_t tt) {
 // every byte of x | 0x80 is at least 128 > t + 1, so the subtraction
 // borrows within no byte, and bit 7 of the difference is clear exactly when
 // the byte's low 7 bits are <= t; a byte with bit 7 set (128..255) is above
-// t.  Four instructions per word instead of le4's seven.
+// t.  Four instructions per word instead of le4_flags's seven.
 constexpr uint32_t kSmallT = 126;
 
-__device__ inline uint32_t le4s(uint32_t x, uint32_t tt1) {
+// bit 7 of each byte of the result: that byte of x is <= t
+__device__ inline uint32_t le4s_flags(uint32_t x, uint32_t tt1) {
     const uint32_t H = 0x80808080u;
-    const uint32_t r = ~(((x | H) - tt1) | x) & H;
-    return ((r >> 7) * 0x01020408u) >> 24;
+    return ~(((x | H) - tt1) | x) & H;
 }
 
 __device__ inline uint64_t le_mask64s(const uint8_t* p, uint32_t tt1) {
     const uint4* q = reinterpret_cast<const uint4*>(p);
-    uint64_t m = 0;
+    uint32_t half[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint4 v = q[i];
-        const uint32_t b = le4s(v.x, tt1) | (le4s(v.y, tt1) << 4) | (le4s(v.z, tt1) << 8) | (le4s(v.w, tt1) << 12);
-        m |= (uint64_t)b << (16 * i);
+    for (int h = 0; h < 2; ++h) {
+        const uint4 v0 = q[2 * h], v1 = q[2 * h + 1];
+        const uint32_t b0 = gather16(le4s_flags(v0.x, tt1), le4s_flags(v0.y, tt1), le4s_flags(v0.z, tt1),
+                                     le4s_flags(v0.w, tt1));
+        const uint32_t b1 = gather16(le4s_flags(v1.x, tt1), le4s_flags(v1.y, tt1), le4s_flags(v1.z, tt1),
+                                     le4s_flags(v1.w, tt1));
+        half[h] = b0 | (b1 << 16);
     }
-    return m;
+    return ((uint64_t)half[1] << 32) | half[0];
 }
 
 // The segment compare of the scans: SMALLT (every threshold <= kSmallT) takes
@@ -107,7 +123,7 @@ __device__ inline uint64_t le_mask64_q(const uint8_t* p, uint32_t tt, uint32_t n
     for (int i = 0; i < 4; ++i) {
         if ((need >> i) & 1u) {
             const uint4 v = q[i];
-            const uint32_t b = le4(v.x, tt) | (le4(v.y, tt) << 4) | (le4(v.z, tt) << 8) | (le4(v.w, tt) << 12);
+            const uint32_t b = gather16(le4_flags(v.x, tt), le4_flags(v.y, tt), le4_flags(v.z, tt), le4_flags(v.w, tt));
             m |= (uint64_t)b << (16 * i);
         }
     }
@@ -1227,7 +1243,7 @@ __device__ inline uint32_t add_sat4(uint32_t x, uint32_t dd) {
 }
 
 // Bit i: min(p[i] + d, 255) <= thr[i], for 64 consecutive table bytes p and
-// thresholds thr (le4 compares bytes against any per-byte threshold).
+// thresholds thr (le4_flags compares bytes against any per-byte threshold).
 __device__ inline uint64_t sum_le_mask64(const uint8_t* p, uint32_t dd, const uint4* thr) {
     const uint4* q = reinterpret_cast<const uint4*>(p);
     uint64_t m = 0;
@@ -1235,8 +1251,8 @@ __device__ inline uint64_t sum_le_mask64(const uint8_t* p, uint32_t dd, const ui
     for (int i = 0; i < 4; ++i) {
         const uint4 v = q[i];
         const uint4 t = thr[i];
-        const uint32_t b = le4(add_sat4(v.x, dd), t.x) | (le4(add_sat4(v.y, dd), t.y) << 4) |
-                           (le4(add_sat4(v.z, dd), t.z) << 8) | (le4(add_sat4(v.w, dd), t.w) << 12);
+        const uint32_t b = gather16(le4_flags(add_sat4(v.x, dd), t.x), le4_flags(add_sat4(v.y, dd), t.y),
+                                    le4_flags(add_sat4(v.z, dd), t.z), le4_flags(add_sat4(v.w, dd), t.w));
         m |= (uint64_t)b << (16 * i);
     }
     return m;

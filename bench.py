@@ -905,10 +905,11 @@ def build_mode(args):
                      "timing": "HIP events around every k_check_push launch on the build stream, over --steps "
                                "profiled builds run right after the timed steps",
                      "cost_model": {"bytes_per_step": model_bytes, "GBs": model_gbs, "frac": model_gbs / HBM_PEAK_GBS,
-                                    "note": "effective rate: every candidate check priced at 5 B per entry of "
-                                            "L(v) although the scans stop early and one pass over the table "
-                                            "tests all of a vertex's candidates; achieved/frac above count the "
-                                            "bytes the kernel requests"}},
+                                    "note": "effective rate, which can exceed the HBM peak: every candidate "
+                                            "check priced at 5 B per entry of L(v) although the scans stop early "
+                                            "and one pass over the table tests all of a vertex's candidates; "
+                                            "achieved/frac above count the bytes the kernel requests, traffic "
+                                            "the DRAM-side bytes"}},
         "roofline_query": {"kernel": qk, "bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": q_gbs / HBM_PEAK_GBS,
                            "achievable": achievable["best_GBs"],

@@ -14,7 +14,9 @@ import paper_1906_12018_amd as pll
 import synth
 from gpu_util import assert_labels_equal, build, check_counters, gpu_query
 from test_gpu_build import small_cases
+from test_gpu_bp import check_bp
 from test_gpu_directed import build_dir, check_directed, small_digraphs
+from test_gpu_weighted import build_w, check_weighted, small_wgraphs
 
 pytestmark = pytest.mark.gpu
 
@@ -110,4 +112,20 @@ def test_directed_builds_ignore_the_flag(gi, b):
     order = synth.degree_order_directed(g)
     idx = build_dir(g, order, batch_size=b, flags=PACK)
     check_directed(idx, g, order)
+    idx.free()
+
+
+@pytest.mark.parametrize("b", [64, 1024])
+def test_weighted_and_bit_parallel_builds_ignore_the_flag(b):
+    """Weighted and bit-parallel builds have checks of their own: with the
+    flag their labels, counters and queries are still the oracles'."""
+    for g in small_wgraphs()[-2:]:
+        order = synth.degree_order(g)
+        idx = build_w(g, order, batch_size=b, flags=PACK)
+        check_weighted(idx, g, order)
+        idx.free()
+    g = synth.ba_graph(700, 5, 12)
+    order = synth.degree_order(g)
+    idx = build(g, order, batch_size=b, bp_roots=4, flags=PACK)
+    check_bp(idx, g, order, 4)
     idx.free()

@@ -37,7 +37,7 @@ namespace {
 constexpr int kBlock = 256;              // 4 waves
 constexpr int kWavesPerBlock = kBlock / PLL_WAVE;
 constexpr uint32_t kMaxBlocks = 4096;
-constexpr uint32_t kHotRows = 256;         // top-ranked table rows whose row masks stay all ones
+constexpr uint32_t kHotRows = 4096;        // top-ranked table rows whose row masks stay all ones
 constexpr uint64_t kPullFrac = 2;          // a round with at least n / 2 receivers pulls the next one
 constexpr uint64_t kPullFrac1 = 8;         // ... and a batch's first round with at least n / 8
 constexpr uint32_t kPullMinN = 16384;      // smaller graphs always push (the pull's set-up outweighs it)

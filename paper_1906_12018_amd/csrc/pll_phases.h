@@ -1150,6 +1150,14 @@ __device__ inline void phase_batch_end(const BuildArgs& A, const Exec& X, uint32
         }
         const uint32_t tail = len - ts;
         if (tail < 2 && !(recheck && tail >= 1)) continue;
+        // A segment appended in one round is already in ascending hub rank
+        // (each acceptance appends its candidates in ascending order): without
+        // the recheck, a segment of up to 64 entries that is sorted stays.
+        if (!recheck && tail <= 64) {
+            const uint32_t e = lane < tail ? A.arena[off + ts + lane] : ~0u;
+            const uint32_t nx = (uint32_t)__shfl_down((int)e, 1, 64);
+            if (!ballot64(lane + 1 < tail && e >= nx)) continue;
+        }
         if (lane < W) s_pres[lane] = 0;
         if (WEIGHTED) {
             for (uint32_t k = lane; k < bs; k += 64) s_pos[k] = 0;

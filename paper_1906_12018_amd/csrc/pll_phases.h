@@ -907,15 +907,16 @@ __device__ inline uint64_t prune_scan4(const BuildArgs& A, uint64_t off, uint32_
             const uint32_t gm = (uint32_t)(todo >> gsh) & 0xFFFFu;
             const bool act = gm != 0;
             const uint32_t w = act ? (uint32_t)__builtin_ctz(gm) : 0u;
-            const uint64_t live = shfl64(live_lane, gsh + w);
             uint64_t m = 0;
             if (act && ((rm >> (4 * w)) & 15u)) {
-                m = seg_le<SMALLT>(row + 64u * w, tt) & live;
+                m = seg_le<SMALLT>(row + 64u * w, tt);
                 st.table += 4;
             }
+            // the lane that holds word w masks the group's OR with its live
+            // candidates (the OR of masked words is the masked OR)
             const uint64_t red = row_or64_dpp(m);
             const bool here = act && sub == w;
-            if (here) pw |= red;
+            if (here) pw |= red & live_lane;
             todo &= ~ballot64(here);
         }
     }

@@ -194,20 +194,21 @@ __device__ inline uint64_t prune_scan(const BuildArgs& A, uint64_t off, uint32_t
         while (lw) {
             const uint32_t w = (uint32_t)__builtin_ctzll(lw);
             lw &= lw - 1;
-            const uint64_t live = readlane64(live_lane, w);
             uint64_t m = 0;
             if (QGATE) {
+                const uint64_t live = readlane64(live_lane, w);
                 const uint32_t need = (uint32_t)(rm >> (4 * w)) & quarters(live);
                 if (need & 15u) {
-                    m = le_mask64_q(row + 64u * w, tt, need) & live;
+                    m = le_mask64_q(row + 64u * w, tt, need);
                     st.table += __builtin_popcount(need & 15u);
                 }
             } else if ((rm >> (4 * w)) & 15u) {
-                m = seg_le<SMALLT>(row + 64u * w, tt) & live;
+                m = seg_le<SMALLT>(row + 64u * w, tt);
                 st.table += 4;
             }
+            // lane w masks the reduced prunes with its live candidates
             const uint64_t red = wave_or64_u(m);
-            if (lane == w) pw |= red;
+            if (lane == w) pw |= red & live_lane;
         }
         if (!ballot64((cw & ~pw) != 0)) break;
     }
@@ -246,20 +247,21 @@ __device__ inline uint64_t prune_scan_nbrs(const BuildArgs& A, uint32_t v, uint3
         while (lw) {
             const uint32_t w = (uint32_t)__builtin_ctzll(lw);
             lw &= lw - 1;
-            const uint64_t live = readlane64(live_lane, w);
             uint64_t m = 0;
             if (QGATE) {
+                const uint64_t live = readlane64(live_lane, w);
                 const uint32_t need = (uint32_t)(rm >> (4 * w)) & quarters(live);
                 if (need & 15u) {
-                    m = le_mask64_q(row + 64u * w, tt, need) & live;
+                    m = le_mask64_q(row + 64u * w, tt, need);
                     st.table += __builtin_popcount(need & 15u);
                 }
             } else if ((rm >> (4 * w)) & 15u) {
-                m = seg_le<SMALLT>(row + 64u * w, tt) & live;
+                m = seg_le<SMALLT>(row + 64u * w, tt);
                 st.table += 4;
             }
+            // lane w masks the reduced prunes with its live candidates
             const uint64_t red = wave_or64_u(m);
-            if (lane == w) pw |= red;
+            if (lane == w) pw |= red & live_lane;
         }
         if (!ballot64((cw & ~pw) != 0)) break;
     }

@@ -413,7 +413,7 @@ __global__ void __launch_bounds__(kBlock) k_pull_items(BuildArgs A, uint2* items
 
 __global__ void __launch_bounds__(kBlock) k_pull(BuildArgs A, uint32_t ib, const uint2* items, const uint32_t* nitems,
                                                  uint32_t q, pll::NextRound nr) {
-    pll::phase_pull(A, grid_exec(A), ib, items, nitems, q, nr);
+    pll::phase_pull4(A, grid_exec(A), ib, items, nitems, q, nr);
 }
 
 // The heavy rows the fused round queued, pushed for the next round.

@@ -596,6 +596,73 @@ __device__ inline void phase_pull(const BuildArgs& A, const Exec& X, uint32_t ib
     }
 }
 
+// phase_pull with four items per wave: the 16-lane group g = lane / 16
+// gathers item i0 + g, 16 CSR entries at a time, and its lane 16g + w holds
+// word w of the delta it collects.  Each step, every group ORs in the delta
+// of one of its active neighbours (the groups' steps run side by side), so
+// four items' chains of dependent loads (item, row, neighbour, stamp,
+// delta) are in flight in one wave.  Deliveries are phase_pull's.
+__device__ inline void phase_pull4(const BuildArgs& A, const Exec& X, uint32_t ib, const uint2* items,
+                                   const uint32_t* nitems, uint32_t q, const NextRound& nr) {
+    const uint32_t lane = lane_id();
+    const uint32_t W = A.W;
+    const uint32_t wd = lane & 15u, gsh = lane & 48u;
+    const uint64_t* act_d = A.act_delta[q];
+    const uint32_t total = *nitems;
+    for (uint32_t t0 = 4u * X.w; t0 < total; t0 += 4u * X.nw) {
+        const uint32_t t = t0 + (lane >> 4);
+        const uint2 it = t < total ? items[t] : make_uint2(0u, 0u);
+        const uint32_t r = it.x;
+        const bool valid = t < total && r > ib;
+        uint64_t beg = 0, end = 0;
+        if (valid) {
+            beg = A.rrow[r] + (uint64_t)it.y * kPullSeg;
+            end = min(A.rrow[r + 1], beg + kPullSeg);
+        }
+        uint64_t m = 0;
+        for (uint64_t e0 = 0;; e0 += 16) {
+            if (!ballot64(valid && beg + e0 < end)) break;
+            const uint64_t e = beg + e0 + wd;
+            const bool in = valid && e < end;
+            const uint64_t at = in ? A.act_at[A.rcol[e]] : 0ull;
+            const bool act = in && (uint32_t)(at >> 32) == nr.rstamp;
+            uint64_t am = ballot64(act);
+            while (am) {
+                const uint32_t gm = (uint32_t)(am >> gsh) & 0xFFFFu;
+                const uint32_t k = gm ? (uint32_t)__builtin_ctz(gm) : 0u;
+                const uint32_t slot = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((gsh + k) * 4u), (int)(uint32_t)at);
+                if (gm && wd < W) m |= act_d[(size_t)slot * W + wd];
+                am &= ~ballot64(gm && wd == k);
+            }
+        }
+        if (valid && wd < W) {
+            m &= rank_mask(r - ib, wd);
+            if (m) m &= ~A.C[(size_t)r * W + wd];
+        } else {
+            m = 0;
+        }
+        if (m) atomicOr((unsigned long long*)&nr.msgs[(size_t)r * W + wd], (unsigned long long)m);
+        const uint64_t got = ballot64(m != 0);
+        if (!got) continue;
+        // one receiver slot per vertex and round, taken by lane 0 of the group
+        bool enq = false, first = false;
+        if (wd == 0 && ((got >> gsh) & 0xFFFFull)) {
+            if (A.recv_stamp[r] != nr.rstamp) enq = atomicExch(&A.recv_stamp[r], nr.rstamp) != nr.rstamp;
+            if (enq && A.touch_stamp[r] != nr.bstamp) {
+                A.touch_stamp[r] = nr.bstamp;
+                first = true;
+            }
+        }
+        const uint32_t rp = shard_append(&X.qs[X.my].recv[nr.rout], enq, (uint64_t)X.my * X.seg);
+        if (enq) nr.recv[rp] = r;
+        const uint32_t tp = shard_append(&X.qs[X.my].touched, first, (uint64_t)X.my * X.seg);
+        if (first) {
+            A.touched[tp] = r;
+            A.tstart[tp] = A.llen[r];
+        }
+    }
+}
+
 // The pull items of a rank-space CSR: (r, c) for every segment c of
 // kPullSeg entries of every vertex r with neighbours, appended in any order.
 __device__ inline void phase_pull_items(const BuildArgs& A, const Exec& X, uint2* items, uint32_t* nitems) {
